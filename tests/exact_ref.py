@@ -1,0 +1,69 @@
+"""Brute-force re-statement of the 16-colour sweep for tiny lattices.
+
+Written from the paper's literal rules, in exact arithmetic, to pin the C
+oracle: payoffs are summed group by group (Sec. III, Eq. (1)-(2)) with
+Python ``Fraction``s, and the Fermi probability of Eq. (3) is evaluated with
+mpmath at 60 significant digits and rounded to the 32-bit threshold exactly.
+It never forms the integer sigma, never builds a table and takes its random
+words from rocRAND's Philox (passed in), so an indexing, sign or table-layout
+mistake in the oracle shows up as a different lattice.
+
+Pure-Python loops: only for L <= 16 and a few sweeps.
+"""
+from fractions import Fraction
+
+import mpmath
+
+mpmath.mp.dps = 60
+
+_NB = ((0, 0), (0, 1), (0, -1), (1, 0), (-1, 0))  # a site and its 4 neighbours
+_DIR = ((0, 1), (0, -1), (1, 0), (-1, 0))          # d = 0 E, 1 W, 2 S, 3 N
+
+
+def payoff(s, L, r, i, j):
+    """Eq. (1)-(2) summed over the 5 groups containing (i, j); exact."""
+    r = Fraction(r)
+    coop = s[i % L][j % L]
+    total = Fraction(0)
+    for di, dj in _NB:
+        ci, cj = i + di, j + dj
+        nc = sum(s[(ci + a) % L][(cj + b) % L] for a, b in _NB)
+        total += r * nc / 5 - (1 if coop else 0)
+    return total
+
+
+def threshold(dpi, K):
+    """min(2^32 - 1, floor(W * 2^32 + 1/2)), W = 1/(1 + exp(dpi/K)), exact."""
+    z = mpmath.mpf(dpi.numerator) / mpmath.mpf(dpi.denominator) / mpmath.mpf(Fraction(K).numerator) \
+        * mpmath.mpf(Fraction(K).denominator)
+    w = 1 / (1 + mpmath.exp(z))
+    t = int(mpmath.floor(w * mpmath.mpf(2) ** 32 + mpmath.mpf(1) / 2))
+    return min(t, 2**32 - 1)
+
+
+def sweep_counters(L, t, seed):
+    """Philox rows [c0, c1, c2, c3, k0, k1] for every site of sweep t."""
+    rows = []
+    for i in range(L):
+        for j in range(L):
+            k = 4 * (i % 4) + (j % 4)
+            rows.append([i * L + j, t, k, 0, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+    return rows
+
+
+def sweep(s, L, r, K, words, t=None):
+    """One 16-colour sweep in place.  words[x] = Philox output for site x."""
+    for k in range(16):
+        a, b = divmod(k, 4)
+        for i in range(a, L, 4):
+            for j in range(b, L, 4):
+                w = words[i * L + j]
+                d = int(w[0]) >> 30
+                u = int(w[1])
+                yi, yj = (i + _DIR[d][0]) % L, (j + _DIR[d][1]) % L
+                if s[i][j] == s[yi][yj]:
+                    continue
+                dpi = payoff(s, L, r, i, j) - payoff(s, L, r, yi, yj)
+                if u < threshold(dpi, K):
+                    s[i][j] = s[yi][yj]
+    return s
