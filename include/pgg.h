@@ -1,0 +1,163 @@
+/*
+ * pgg.h -- C ABI of the MI355X (gfx950) spatial public goods game engine.
+ *
+ * The model is the spatial public goods game of M. Perc, "High-performance
+ * parallel computing in the classroom using the public goods game as an
+ * example" (2017), Sec. III: an L x L periodic square lattice of cooperators
+ * (C = 1) and defectors (D = 0), overlapping von Neumann groups of G = 5,
+ * cost c = 1, multiplication factor r (payoffs Eq. (1)-(2), summed over the
+ * five groups a player belongs to), and imitation of a random nearest
+ * neighbour with the Fermi probability of Eq. (3) at noise K.  The observable
+ * is the cooperator fraction rho_C of Eq. (4).
+ *
+ * The engine advances the lattice with a deterministic sweep: one Monte
+ * Carlo step (MCS) visits the 16 colour classes k = 4 (i mod 4) + (j mod 4),
+ * k = 0..15 in order, and gives every site of class k one elementary step of
+ * Sec. III.  Concurrently updated sites are at least 4 apart, beyond the
+ * 3-line read radius of an elementary step (Sec. IV), so a colour class
+ * updates in parallel without races.  Random numbers come from
+ * Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ * (x, t, k, 0) for the elementary step of site x = i L + j in sweep t
+ * (0-based), direction d = w0 >> 30 (0 E, 1 W, 2 S, 3 N), acceptance word
+ * u = w1; the initial state uses counter (x, 0, 0, 1) and s_x = [w0 < P0],
+ * P0 = min(2^32, floor(p0 2^32 + 1/2)).  A copy happens iff s_x != s_y and
+ * u < T[dSigma + 25][ds + 1], T = min(2^32 - 1, floor(W 2^32 + 1/2)),
+ * W = 1 / (1 + exp(((r dSigma)/5 - 5 ds)/K)) in binary64, where Sigma is the
+ * sum of the cooperator counts of the five groups containing a player, so
+ * that Pi = (r/5) Sigma - 5 s exactly.  Results are a pure function of
+ * (parameters, t, lattice): identical for both storage layouts, every kernel
+ * variant, chunking of sweeps into calls, batching and streams.
+ *
+ * Conventions for every call:
+ *   - Every call returns pgg_status; 0 is success, negative is an error.
+ *     No C++ exception crosses this boundary.  pgg_last_error() returns a
+ *     thread-local description of the last error raised on the calling thread.
+ *   - Arguments are validated before anything is allocated or launched; an
+ *     invalid argument returns PGG_E_INVAL with no side effect.
+ *   - A HIP error returns PGG_E_DEVICE and poisons the handle: every later
+ *     call on it except pgg_destroy returns PGG_E_STATE.
+ *   - A handle is not thread-safe; distinct handles may be used from distinct
+ *     threads.  Work is ordered on the handle's HIP stream.
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *     pointers are HIP device memory on the current device.
+ */
+#ifndef PGG_H
+#define PGG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PGG_OK = 0,
+    PGG_E_INVAL = -1,  /* invalid argument; nothing was changed            */
+    PGG_E_NOMEM = -2,  /* device or host allocation failed                 */
+    PGG_E_DEVICE = -3, /* a HIP call failed; the handle is now poisoned    */
+    PGG_E_STATE = -4   /* handle poisoned by an earlier device error       */
+} pgg_status;
+
+/* Storage of the strategy lattice in device memory.  Results are identical. */
+typedef enum {
+    PGG_LAYOUT_INT8 = 0, /* one byte per site (0 or 1), row-major, x = i L + j */
+    PGG_LAYOUT_BITS = 1  /* one bit per site: column j of row i is bit (j mod
+                            32) of 32-bit word j / 32 of the row; each row is
+                            padded to a multiple of 64 bits with zero bits     */
+} pgg_layout;
+
+/* Sweep kernel selection (a tuning choice; results never depend on it). */
+typedef enum {
+    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR, bits -> ROWBAND_COMPACT          */
+    PGG_KERNEL_COLOUR = 1,  /* int8 only: one launch per colour class, global
+                               memory, every site evaluated (reference path)   */
+    PGG_KERNEL_ROWBAND = 2, /* bits only: one launch per row residue i mod 4
+                               (4 colour classes), rows staged in LDS, every
+                               site evaluated                                    */
+    PGG_KERNEL_ROWBAND_COMPACT = 3 /* bits only: as ROWBAND, but sites whose 4
+                               neighbours all share their strategy are resolved
+                               without drawing random numbers (their update is
+                               a no-op), and the rest are packed densely onto
+                               the lanes                                         */
+} pgg_kernel;
+
+/* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
+typedef struct {
+    uint32_t L;      /* lattice side; 4 <= L <= 32768 and L % 4 == 0          */
+    double r;        /* multiplication factor; finite, r >= 0 (paper: r > 1)  */
+    double K;        /* Fermi noise of Eq. (3); finite, K > 0 (paper: 0.5)    */
+    double p0;       /* initial cooperator fraction in [0, 1] (paper: 0.5)    */
+    uint64_t seed;   /* Philox key                                            */
+    uint32_t layout; /* pgg_layout                                            */
+    uint32_t kernel; /* pgg_kernel; must match the layout unless AUTO         */
+} pgg_params;
+
+typedef struct pgg_sim pgg_sim; /* opaque handle */
+
+/* Bytes of device memory the lattice of these parameters occupies (the size
+ * a caller-supplied dev_buf must have).  0 if the parameters are invalid. */
+size_t pgg_device_bytes(const pgg_params* p);
+
+/* Create a simulation and draw its initial state (Sec. III: every player C
+ * with probability p0, D otherwise), t = 0.
+ *   p          host; copied, the caller keeps ownership.
+ *   dev_buf    device buffer of >= pgg_device_bytes(p) bytes that will hold
+ *              the lattice (e.g. a torch tensor's data_ptr()); it must stay
+ *              valid until pgg_destroy.  NULL: the library allocates and
+ *              owns the lattice memory.  Small per-handle buffers (the
+ *              threshold table, counters, count history) are always
+ *              allocated by the library.
+ *   dev_bytes  size of dev_buf (ignored when dev_buf is NULL).
+ *   hip_stream hipStream_t to order all work on; NULL = the null stream.
+ *   out        host; receives the handle (set to NULL on error).
+ * Synchronises the stream once (to read N_C(0)). */
+pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* hip_stream,
+                    pgg_sim** out);
+
+/* Advance n_sweeps Monte Carlo steps (one sweep = the 16 colour classes)
+ * from the current sweep index t; afterwards t += n_sweeps.  Requires
+ * t + n_sweeps <= 2^32.
+ *   coop_counts  host array of n_sweeps entries receiving N_C(t+1) ... N_C(t+n)
+ *                (the Eq. (4) sum after each sweep), or NULL.
+ * With coop_counts == NULL the call only enqueues work on the stream and
+ * returns; with it, the call synchronises the stream. n_sweeps == 0 is a
+ * no-op. */
+pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts);
+
+/* rho = N_C(t) / L^2 after the last completed sweep (Eq. (4) without the
+ * time average).  Synchronises the stream. rho: host. */
+pgg_status pgg_density(pgg_sim* s, double* rho);
+
+/* N_C(t), the number of cooperators.  Synchronises the stream. n_c: host. */
+pgg_status pgg_coop_count(pgg_sim* s, uint64_t* n_c);
+
+/* The current sweep index t (number of sweeps completed).  Host only. */
+pgg_status pgg_sweep_index(const pgg_sim* s, uint64_t* t);
+
+/* Copy the lattice to host_LxL (host, L*L bytes, row-major, values 0/1).
+ * Synchronises the stream. */
+pgg_status pgg_read_lattice(pgg_sim* s, uint8_t* host_LxL);
+
+/* Replace the lattice by host_LxL (host, L*L bytes of 0/1; any other byte
+ * value is PGG_E_INVAL) and set the sweep index to t (t <= 2^32), e.g. to
+ * resume from a checkpoint.  Synchronises the stream. */
+pgg_status pgg_write_lattice(pgg_sim* s, const uint8_t* host_LxL, uint64_t t);
+
+/* Copy the 153 Fermi thresholds T[(dSigma + 25) * 3 + ds + 1] that the
+ * device uses to host_T (host, 153 entries).  Synchronises the stream. */
+pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T);
+
+/* Release the handle and every buffer the library allocated.  Never frees a
+ * caller-supplied dev_buf.  NULL is a no-op.  Synchronises the stream. */
+void pgg_destroy(pgg_sim* s);
+
+/* Thread-local, NUL-terminated description of the last error on this thread
+ * ("" if none).  Valid until the next call on this thread. */
+const char* pgg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGG_H */

@@ -1,0 +1,211 @@
+"""ctypes binding of libpgg.so (declared in include/pgg.h).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+the library.  There is no fallback: if libpgg.so is missing or no GPU is
+visible, the calls raise.
+
+Function names follow the C ABI (``pgg_init``, ``pgg_sweep``,
+``pgg_density``, ...); ``Sim`` wraps a handle.  PyTorch is used only to
+provide device memory (an optional caller-owned lattice buffer) and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpgg.so")
+
+PGG_OK, PGG_E_INVAL, PGG_E_NOMEM, PGG_E_DEVICE, PGG_E_STATE = 0, -1, -2, -3, -4
+LAYOUT_INT8, LAYOUT_BITS = 0, 1
+KERNEL_AUTO, KERNEL_COLOUR, KERNEL_ROWBAND, KERNEL_ROWBAND_COMPACT = 0, 1, 2, 3
+LAYOUTS = {"int8": LAYOUT_INT8, "bits": LAYOUT_BITS}
+KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBAND,
+           "rowband_compact": KERNEL_ROWBAND_COMPACT}
+
+# Every symbol include/pgg.h declares (checked by the CPU test suite).
+EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
+           "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
+           "pgg_destroy", "pgg_last_error")
+
+
+class PggParams(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("r", ctypes.c_double), ("K", ctypes.c_double),
+                ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
+                ("kernel", ctypes.c_uint32)]
+
+
+class PggError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("pgg status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libpgg.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpgg.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, u8p, u32p, u64p = ctypes.c_void_p, P(ctypes.c_uint8), P(ctypes.c_uint32), P(ctypes.c_uint64)
+    sig = {
+        "pgg_device_bytes": (ctypes.c_size_t, [P(PggParams)]),
+        "pgg_init": (ctypes.c_int, [P(PggParams), vp, ctypes.c_size_t, vp, P(vp)]),
+        "pgg_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, u64p]),
+        "pgg_density": (ctypes.c_int, [vp, P(ctypes.c_double)]),
+        "pgg_coop_count": (ctypes.c_int, [vp, u64p]),
+        "pgg_sweep_index": (ctypes.c_int, [vp, u64p]),
+        "pgg_read_lattice": (ctypes.c_int, [vp, u8p]),
+        "pgg_write_lattice": (ctypes.c_int, [vp, u8p, ctypes.c_uint64]),
+        "pgg_threshold_table": (ctypes.c_int, [vp, u32p]),
+        "pgg_destroy": (None, [vp]),
+        "pgg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != PGG_OK:
+        raise PggError(status, load().pgg_last_error().decode())
+
+
+def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto") -> PggParams:
+    return PggParams(int(L), float(r), float(K), float(p0), int(seed) & (2**64 - 1),
+                     LAYOUTS[layout] if isinstance(layout, str) else int(layout),
+                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel))
+
+
+def pgg_device_bytes(params: PggParams) -> int:
+    return int(load().pgg_device_bytes(ctypes.byref(params)))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def pgg_init(params: PggParams, dev_buf=None, stream=None):
+    """Returns an opaque handle (c_void_p).  dev_buf: torch tensor or None."""
+    lib = load()
+    h = ctypes.c_void_p()
+    ptr, nbytes = None, 0
+    if dev_buf is not None:
+        ptr, nbytes = dev_buf.data_ptr(), dev_buf.numel() * dev_buf.element_size()
+    _check(lib.pgg_init(ctypes.byref(params), ptr, nbytes, _stream_handle(stream), ctypes.byref(h)))
+    return h
+
+
+def pgg_sweep(handle, n: int, want_counts: bool = True):
+    """Advance n sweeps; returns N_C after each sweep (uint64) or None."""
+    if want_counts:
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+        _check(load().pgg_sweep(handle, int(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out[:n]
+    _check(load().pgg_sweep(handle, int(n), None))
+    return None
+
+
+def pgg_density(handle) -> float:
+    v = ctypes.c_double()
+    _check(load().pgg_density(handle, ctypes.byref(v)))
+    return v.value
+
+
+def pgg_coop_count(handle) -> int:
+    v = ctypes.c_uint64()
+    _check(load().pgg_coop_count(handle, ctypes.byref(v)))
+    return v.value
+
+
+def pgg_sweep_index(handle) -> int:
+    v = ctypes.c_uint64()
+    _check(load().pgg_sweep_index(handle, ctypes.byref(v)))
+    return v.value
+
+
+def pgg_read_lattice(handle, L: int) -> np.ndarray:
+    out = np.zeros((L, L), dtype=np.uint8)
+    _check(load().pgg_read_lattice(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return out
+
+
+def pgg_write_lattice(handle, lattice: np.ndarray, t: int) -> None:
+    a = np.ascontiguousarray(lattice, dtype=np.uint8)
+    _check(load().pgg_write_lattice(handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(t)))
+
+
+def pgg_threshold_table(handle) -> np.ndarray:
+    out = np.zeros(153, dtype=np.uint32)
+    _check(load().pgg_threshold_table(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return out.reshape(51, 3)
+
+
+def pgg_destroy(handle) -> None:
+    if handle:
+        load().pgg_destroy(handle)
+
+
+class Sim:
+    """One lattice on the GPU.  Mirrors the C calls one to one."""
+
+    def __init__(self, L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto",
+                 dev_buf=None, stream=None):
+        self.params = make_params(L, r, K, p0, seed, layout, kernel)
+        self.L = int(L)
+        self._buf = dev_buf  # keep a caller tensor alive as long as the handle
+        self.handle = pgg_init(self.params, dev_buf, stream)
+
+    def sweep(self, n, want_counts=True):
+        return pgg_sweep(self.handle, n, want_counts)
+
+    def density(self):
+        return pgg_density(self.handle)
+
+    def coop_count(self):
+        return pgg_coop_count(self.handle)
+
+    @property
+    def t(self):
+        return pgg_sweep_index(self.handle)
+
+    def read_lattice(self):
+        return pgg_read_lattice(self.handle, self.L)
+
+    def write_lattice(self, lattice, t):
+        pgg_write_lattice(self.handle, lattice, t)
+
+    def threshold_table(self):
+        return pgg_threshold_table(self.handle)
+
+    def close(self):
+        if self.handle:
+            pgg_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pgg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pgg_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def pgg():
+    from paper_1704_08098_amd import pgg as mod
+    if not os.path.exists(mod.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    mod.load()
+    return mod
+
+
+def test_every_declared_symbol_is_exported(pgg):
+    lib = ctypes.CDLL(pgg.LIB_PATH)
+    names = _declared()
+    assert "pgg_init" in names and "pgg_sweep" in names and "pgg_density" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(pgg.EXPORTS) == names
+
+
+def test_params_struct_layout(pgg):
+    # uint32 L; double r, K, p0; uint64 seed; uint32 layout, kernel
+    assert ctypes.sizeof(pgg.PggParams) == 48
+    assert pgg.PggParams.seed.offset == 32
+
+
+def test_device_bytes(pgg):
+    assert pgg.pgg_device_bytes(pgg.make_params(100, 3.8, layout="int8")) == 100 * 100
+    # bits: rows padded to 64 bits -> 2 words of 64 bits for L = 100
+    assert pgg.pgg_device_bytes(pgg.make_params(100, 3.8, layout="bits")) == 100 * 16
+    assert pgg.pgg_device_bytes(pgg.make_params(4096, 3.8, layout="bits")) == 4096 * 512
+    assert pgg.pgg_device_bytes(pgg.make_params(102, 3.8)) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(L=6), dict(L=0), dict(L=32772), dict(K=0.0), dict(K=-1.0),
+                                dict(r=float("nan")), dict(r=-0.5), dict(p0=1.5),
+                                dict(p0=float("nan")), dict(layout=7),
+                                dict(layout="int8", kernel="rowband"),
+                                dict(layout="bits", kernel="colour"), dict(kernel=9)])
+def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
+    args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")
+    args.update(kw)
+    p = pgg.make_params(**args)
+    with pytest.raises(pgg.PggError) as e:
+        pgg.pgg_init(p)
+    assert e.value.status == pgg.PGG_E_INVAL
+    assert "invalid parameters" in pgg.load().pgg_last_error().decode()
+
+
+def test_null_handle_is_rejected(pgg):
+    lib = pgg.load()
+    assert lib.pgg_sweep(None, 1, None) == pgg.PGG_E_INVAL
+    assert lib.pgg_coop_count(None, None) == pgg.PGG_E_INVAL
+    lib.pgg_destroy(None)  # no-op
+
+
+def test_engine_has_no_cpu_fallback():
+    # The product modules never import the oracle.
+    pkg = os.path.join(ROOT, "paper_1704_08098_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "pgg_ref_" not in text, f

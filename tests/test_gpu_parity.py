@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Bit-exact: lattice state and integer cooperator count after every sweep.
+Every GPU step prints what it runs (variant, L, r, seed) before it runs.
+"""
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+from paper_1704_08098_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [("int8", "colour"), ("bits", "rowband"), ("bits", "rowband_compact")]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pgg(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.set_device(0)
+    from paper_1704_08098_amd import pgg as mod
+    mod.load()
+    return mod
+
+
+def _oracle_trajectory(args):
+    """Lattices after each of n sweeps (oracle, sweep by sweep) and counts."""
+    import oracle
+    L, r, K, p0, seed, n = args
+    s, nc0 = oracle.init(L, p0, seed)
+    lats, counts = [], []
+    for t in range(n):
+        s, c = oracle.sweep(s, r, K, seed, t, 1)
+        lats.append(s)
+        counts.append(int(c[0]))
+    return nc0, np.stack(lats), np.array(counts, dtype=np.uint64)
+
+
+@pytest.fixture(scope="module")
+def small_trajectories(oracle_lib):
+    cfg = wl.SMALL
+    args = [(cfg["L"], cfg["r"], cfg["K"], cfg["p0"], s, cfg["sweeps"]) for s in cfg["seeds"]]
+    with ProcessPoolExecutor(max_workers=len(args)) as ex:
+        return dict(zip(cfg["seeds"], ex.map(_oracle_trajectory, args)))
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+def test_small_config_every_sweep(pgg, small_trajectories, layout, kernel):
+    """L = 100, r = 3.8, 1000 sweeps, five seeds: every sweep, bit for bit."""
+    cfg = wl.SMALL
+    for seed in cfg["seeds"]:
+        nc0, lats, counts = small_trajectories[seed]
+        say("small config", layout, kernel, "seed", seed)
+        with pgg.Sim(cfg["L"], cfg["r"], cfg["K"], cfg["p0"], seed, layout, kernel) as sim:
+            assert sim.coop_count() == nc0
+            for t in range(cfg["sweeps"]):
+                c = sim.sweep(1)
+                assert int(c[0]) == int(counts[t]), (seed, t)
+                lat = sim.read_lattice()
+                if not np.array_equal(lat, lats[t]):
+                    bad = np.argwhere(lat != lats[t])
+                    pytest.fail("seed %d sweep %d: %d sites differ, first %s" % (seed, t, len(bad), bad[:5]))
+            assert sim.t == cfg["sweeps"]
+            assert sim.density() == pytest.approx(int(counts[-1]) / cfg["L"] ** 2, abs=0)
+
+
+def test_threshold_tables_match_oracle(pgg, oracle_lib):
+    rs = sorted({wl.SMALL["r"], *wl.SCAN["r_values"], *wl.DECAY["r_values"], 3.98, 5.0, 0.0, 12.5})
+    for r in rs:
+        for K in (0.5, 0.05, 3.0):
+            say("table r", r, "K", K)
+            with pgg.Sim(8, r, K, 0.5, 1, "int8") as sim:
+                assert np.array_equal(sim.threshold_table(), oracle_lib.table(r, K)), (r, K)
+
+
+@pytest.mark.parametrize("layout", ["int8", "bits"])
+def test_initial_states_match_oracle(pgg, oracle_lib, layout):
+    for L in (4, 8, 12, 36, 100, 132, 1024):
+        for p0 in (0.0, 0.1, 0.5, 0.9, 1.0):
+            seed = 1000 + L
+            say("init", layout, "L", L, "p0", p0)
+            ref, nc = oracle_lib.init(L, p0, seed)
+            with pgg.Sim(L, 3.8, 0.5, p0, seed, layout) as sim:
+                assert sim.coop_count() == nc
+                assert np.array_equal(sim.read_lattice(), ref)
+
+
+RAGGED = [(4, 3.8, 0.5, 11), (8, 4.4, 0.5, 12), (12, 3.72, 0.5, 13), (16, 5.0, 0.5, 14),
+          (20, 3.9, 1.5, 15), (36, 4.1, 0.5, 16), (60, 3.8, 0.1, 17), (68, 4.6, 0.5, 18),
+          (100, 3.75, 0.5, 2**40 + 19), (132, 3.98, 0.5, 20), (196, 4.0, 0.25, 21),
+          (260, 3.85, 0.5, 22), (512, 3.8, 0.5, 23)]
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+@pytest.mark.parametrize("L,r,K,seed", RAGGED, ids=lambda v: str(v))
+def test_ragged_and_tiny_lattices(pgg, oracle_lib, layout, kernel, L, r, K, seed):
+    """Sizes that are not multiples of the 32/64-bit words, and the wrap at L = 4..20."""
+    n = 24
+    say("ragged", layout, kernel, "L", L, "r", r, "K", K, "seed", seed)
+    s0, _ = oracle_lib.init(L, 0.5, seed)
+    with pgg.Sim(L, r, K, 0.5, seed, layout, kernel) as sim:
+        ref = s0
+        for t in range(n):
+            ref, c = oracle_lib.sweep(ref, r, K, seed, t, 1)
+            got = sim.sweep(1)
+            assert int(got[0]) == int(c[0]), t
+            assert np.array_equal(sim.read_lattice(), ref), t
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+def test_write_lattice_resume_and_chunking(pgg, oracle_lib, layout, kernel):
+    L, r, K, seed, t0 = 68, 3.9, 0.5, 77, 123
+    lat = wl.random_lattice(L, 0.4, 5)
+    ref, counts = oracle_lib.sweep(lat, r, K, seed, t0, 30)
+    say("resume", layout, kernel)
+    with pgg.Sim(L, r, K, 0.5, seed, layout, kernel) as sim:
+        sim.write_lattice(lat, t0)
+        assert sim.t == t0 and sim.coop_count() == int(lat.sum())
+        got = np.concatenate([sim.sweep(7), sim.sweep(0), sim.sweep(13), sim.sweep(10)])
+        assert np.array_equal(got, counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+        assert sim.t == t0 + 30
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+def test_sweep_index_near_2_pow_32(pgg, oracle_lib, layout, kernel):
+    L, r, seed = 36, 3.8, 9
+    lat, _ = oracle_lib.init(L, 0.5, seed)
+    t0 = 2**32 - 3
+    ref, counts = oracle_lib.sweep(lat, r, 0.5, seed, t0, 3)
+    say("t near 2^32", layout, kernel)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, layout, kernel) as sim:
+        sim.write_lattice(lat, t0)
+        assert np.array_equal(sim.sweep(3), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+        with pytest.raises(pgg.PggError) as e:
+            sim.sweep(1)
+        assert e.value.status == pgg.PGG_E_INVAL
+        assert sim.t == 2**32  # the rejected call changed nothing
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+@pytest.mark.parametrize("value", [0, 1])
+def test_absorbing_states_stay(pgg, layout, kernel, value):
+    say("absorbing", layout, kernel, value)
+    with pgg.Sim(128, 3.8, 0.5, float(value), 3, layout, kernel) as sim:
+        c = sim.sweep(20)
+        assert np.all(c == value * 128 * 128)
+        assert np.all(sim.read_lattice() == value)
+
+
+def test_write_lattice_rejects_bad_bytes(pgg):
+    with pgg.Sim(8, 3.8, 0.5, 0.5, 1, "bits") as sim:
+        bad = np.zeros((8, 8), dtype=np.uint8)
+        bad[3, 3] = 2
+        with pytest.raises(pgg.PggError) as e:
+            sim.write_lattice(bad, 0)
+        assert e.value.status == pgg.PGG_E_INVAL
+
+
+def test_caller_buffer_and_stream(pgg, oracle_lib):
+    import torch
+    L, r, seed, n = 100, 3.8, 4, 40
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    params = pgg.make_params(L, r, 0.5, 0.5, seed, "bits")
+    buf = torch.zeros(pgg.pgg_device_bytes(params), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    say("caller buffer + stream")
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", dev_buf=buf, stream=stream) as sim:
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+    # the buffer is the caller's and still holds the lattice (rows of 16 bytes)
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy().reshape(L, 16)
+    bits = np.unpackbits(host, axis=1, bitorder="little")[:, :L]
+    assert np.array_equal(bits, ref)
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+def test_scan_size_against_oracle(pgg, oracle_lib, layout, kernel):
+    """L = 1024 (the r-scan lattice) at r = 3.75: 12 sweeps, bit for bit."""
+    L, r, seed, n = 1024, 3.75, 110, 12
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say("L=1024", layout, kernel)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, layout, kernel) as sim:
+        assert sim.coop_count() == nc0
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+@pytest.fixture(scope="module")
+def decay_reference(oracle_lib):
+    L, r, seed, n = wl.DECAY["L"], wl.DECAY["r_values"][1], wl.DECAY["seeds"][0], 2
+    return oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+
+
+@pytest.mark.parametrize("layout,kernel", VARIANTS)
+def test_full_size_L4096_against_oracle(pgg, decay_reference, layout, kernel):
+    """L = 4096 at r_c: init and the first two sweeps, bit for bit."""
+    L, r, seed = wl.DECAY["L"], wl.DECAY["r_values"][1], wl.DECAY["seeds"][0]
+    ref, nc0, counts = decay_reference
+    say("L=4096", layout, kernel)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, layout, kernel) as sim:
+        assert sim.coop_count() == nc0
+        assert np.array_equal(sim.sweep(len(counts)), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_kernels_agree_at_benchmark_size(pgg):
+    """L = 4096, r = r_c, 400 sweeps: every kernel, identical counts and lattice;
+    the running count equals a recount of the lattice (any-size properties)."""
+    L, r, seed, n = wl.DECAY["L"], wl.DECAY["r_values"][1], 1, 400
+    results = []
+    for layout, kernel in VARIANTS:
+        say("bench size", layout, kernel)
+        with pgg.Sim(L, r, 0.5, 0.5, seed, layout, kernel) as sim:
+            c = sim.sweep(n)
+            lat = sim.read_lattice()
+            assert int(lat.sum()) == int(c[-1])
+            results.append((c, lat))
+    for c, lat in results[1:]:
+        assert np.array_equal(c, results[0][0])
+        assert np.array_equal(lat, results[0][1])
+
+
+def test_maximum_size_kernels_agree(pgg):
+    """L = 32768 (the largest accepted): dense and compact row-band kernels
+    give identical device lattices after two sweeps; counts are recounts."""
+    import torch
+    L, r, seed = 32768, 3.7443, 5
+    bufs, counts = [], []
+    for kernel in ("rowband", "rowband_compact"):
+        params = pgg.make_params(L, r, 0.5, 0.5, seed, "bits", kernel)
+        buf = torch.empty(pgg.pgg_device_bytes(params), dtype=torch.uint8, device="cuda")
+        say("L=32768", kernel)
+        with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", kernel, dev_buf=buf) as sim:
+            counts.append(sim.sweep(2))
+        torch.cuda.synchronize()
+        bufs.append(buf)
+    assert torch.equal(bufs[0], bufs[1])
+    assert np.array_equal(counts[0], counts[1])
+    pop = int(np.bitwise_count(bufs[0].cpu().numpy()).sum(dtype=np.uint64))
+    assert pop == int(counts[0][-1])
