@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the spatial public goods game sweep on one MI355X.
+
+A step is one Monte Carlo step (one sweep of the 16 colour classes) of the
+L x L lattice.  Default workload: L = 4096 (16.8 M sites), r = 3.7443 (the
+critical point of Sec. V), K = 0.5, i.i.d. 50/50 start, seed 1; W untimed
+sweeps, then K timed sweeps (t = W .. W+K-1), inputs resident in HBM.
+
+Prints one JSON line:
+  value       whole-job site updates/s (L^2 * K / wall time of the K sweeps)
+  roofline    the dominant kernel (the row-band sweep) against the VALU roof,
+              from its event-timed average launch duration
+  hbm         the same rate against the HBM roof at the algorithmic bytes of
+              the state (read + write once per sweep)
+  dense       the data-independent rate with every site drawing its random
+              numbers (no skipping of no-op updates)
+  cpu_baseline  the oracle, single-threaded, on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1704_08098_amd import workloads as wl  # noqa: E402
+
+METRIC = "site updates/s at L=4096 (% HBM roofline); batched replica updates/s vs plain"
+
+# MI355X peaks (published): HBM3E 8 TB/s; 256 CUs at 2.4 GHz, 64 VALU lanes
+# per CU per cycle (4 SIMDs x 16 lanes) for full-rate 32-bit operations.
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T full-rate lane-ops/s
+
+# Algorithmic VALU cost of one elementary step that draws its random numbers,
+# in full-rate 32-bit lane-op slots (derivation in the design doc):
+#   Philox4x32-10: 20 products 32x32->64 (the last round needs one), each a
+#   quarter-rate instruction = 4 slots -> 19 * 4 = 76; 3-input XORs and key
+#   mixing 2 per round -> 19 (first-round key words are uniform);
+#   payoff difference: 2 x (5 masked popcounts + 3 adds), row windows and
+#   the neighbour select -> 30; table index, compare, flip -> 6.
+SLOTS_PER_DRAWN_UPDATE = 76 + 19 + 30 + 6
+# Every site also pays the bit-parallel activity test (8 sites per 32-bit
+# word: 4 XOR, 3 OR, 1 AND, 2 window extractions) -> ~2 slots per site.
+SLOTS_PER_SITE_SCAN = 2
+# Algorithmic HBM bytes per site update: the state is read and written once
+# per sweep; bit-packed = 2 bits, int8 = 2 bytes.
+BYTES_PER_UPDATE = {"bits": 0.25, "int8": 2.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream):
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream)
+    sim.sweep(warmup, want_counts=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(steps, want_counts=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nc = sim.coop_count()
+    sim.close()
+    return dt, nc
+
+
+def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream):
+    """Same trajectory with every sweep-kernel launch bracketed by events."""
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream)
+    sim.sweep(warmup, want_counts=False)
+    sim.set_kernel_timing(True)
+    sim.sweep(steps, want_counts=False)
+    launches, ms, drawn = sim.kernel_timing()
+    sim.close()
+    return launches, ms, drawn
+
+
+def cpu_baseline(L, r, seed, n_sweeps):
+    import oracle
+    oracle.build(force=False)
+    s, _ = oracle.init(L, 0.5, seed)
+    t0 = time.perf_counter()
+    oracle.sweep(s, r, wl.K_PAPER, seed, 0, n_sweeps)
+    dt = time.perf_counter() - t0
+    return {"value": L * L * n_sweeps / dt, "unit": "site updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d sweep(s) of the L=%d, r=%g lattice from its i.i.d. 50/50 start "
+                      "(16-colour oracle, single thread, %.1f s)" % (n_sweeps, L, r, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed sweeps before them")
+    ap.add_argument("--L", type=int, default=wl.DECAY["L"])
+    ap.add_argument("--r", type=float, default=wl.R_CRITICAL)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--kernel", default="rowband_staged",
+                    choices=["rowband_staged", "rowband_compact", "rowband", "colour"])
+    ap.add_argument("--dense-steps", type=int, default=200)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the sweep of one lattice is not split across "
+              "GPUs in this build (see DESIGN.md for how it would shard); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1704_08098_amd import pgg
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    pgg.load()
+    layout = "int8" if args.kernel == "colour" else "bits"
+    stream = torch.cuda.Stream()
+    L, r, seed = args.L, args.r, args.seed
+
+    if args.copy_probe:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log("timed pass: L=%d r=%g kernel=%s warmup=%d steps=%d" % (L, r, args.kernel, args.warmup, args.steps))
+    dt, nc_end = time_sweeps(pgg, torch, L, r, seed, args.kernel, layout, args.warmup, args.steps, stream)
+    updates = float(L) * L * args.steps
+    value = updates / dt
+
+    dense = None
+    if args.kernel in ("rowband_compact", "rowband_staged") and args.dense_steps > 0:
+        log("dense pass: %d sweeps" % args.dense_steps)
+        ddt, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", layout, args.warmup,
+                             args.dense_steps, stream)
+        dense = {"value": float(L) * L * args.dense_steps / ddt, "unit": "site updates/s",
+                 "kernel": "rowband (every site draws)", "steps": args.dense_steps,
+                 "ms_per_step": 1e3 * ddt / args.dense_steps}
+
+    log("kernel-timing pass")
+    launches, kms, drawn = kernel_pass(pgg, torch, L, r, seed, args.kernel, layout, args.warmup,
+                                       args.steps, stream)
+    avg_ms = kms / max(launches, 1)
+    sites_per_launch = updates / max(launches, 1)
+    if args.kernel == "colour":
+        drawn = updates
+    drawn_per_launch = drawn / max(launches, 1)
+    slots = drawn_per_launch * SLOTS_PER_DRAWN_UPDATE + sites_per_launch * SLOTS_PER_SITE_SCAN
+    achieved_tops = slots / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": None,
+                "kernel": {"rowband_staged": "k_rowband_staged", "rowband_compact": "k_rowband_bits<true>",
+                           "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
+                "avg_launch_us": avg_ms * 1e3, "launches": launches,
+                "drawn_fraction": drawn / updates,
+                "slots_per_drawn_update": SLOTS_PER_DRAWN_UPDATE,
+                "slots_per_site_scan": SLOTS_PER_SITE_SCAN}
+    kernel_rate = sites_per_launch / (avg_ms * 1e-3)
+    hbm_bytes = BYTES_PER_UPDATE[layout]
+    hbm = {"bytes_per_update": hbm_bytes, "achieved_GBs": value * hbm_bytes / 1e9,
+           "peak_GBs": HBM_PEAK_GBS, "frac": value * hbm_bytes / 1e9 / HBM_PEAK_GBS,
+           "frac_int8_equivalent": value * 2.0 / 1e9 / HBM_PEAK_GBS,
+           "kernel_only_updates_per_s": kernel_rate}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle, %d sweep(s) at L=%d" % (args.cpu_sweeps, L))
+        cpu = cpu_baseline(L, r, seed, args.cpu_sweeps)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "site updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "single %dx%d periodic lattice, r=%g, K=0.5, i.i.d. 50/50 start "
+                               "(seed %d), sweeps %d..%d timed" % (L, L, r, seed, args.warmup,
+                                                                 args.warmup + args.steps - 1),
+                   "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
+                   "kernel": args.kernel, "parallelism": "single GPU"},
+        "roofline": roofline, "hbm": hbm, "dense": dense, "cpu_baseline": cpu,
+        "final_density": nc_end / float(L * L),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

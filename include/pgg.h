@@ -69,17 +69,26 @@ typedef enum {
 
 /* Sweep kernel selection (a tuning choice; results never depend on it). */
 typedef enum {
-    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR, bits -> ROWBAND_COMPACT          */
+    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR; bits -> ROWBAND_STAGED when its
+                               LDS footprint fits (L <= 4096 or so), otherwise
+                               ROWBAND_COMPACT                                 */
     PGG_KERNEL_COLOUR = 1,  /* int8 only: one launch per colour class, global
                                memory, every site evaluated (reference path)   */
     PGG_KERNEL_ROWBAND = 2, /* bits only: one launch per row residue i mod 4
                                (4 colour classes), rows staged in LDS, every
                                site evaluated                                    */
-    PGG_KERNEL_ROWBAND_COMPACT = 3 /* bits only: as ROWBAND, but sites whose 4
+    PGG_KERNEL_ROWBAND_COMPACT = 3, /* bits only: as ROWBAND, but sites whose 4
                                neighbours all share their strategy are resolved
                                without drawing random numbers (their update is
                                a no-op), and the rest are packed densely onto
                                the lanes                                         */
+    PGG_KERNEL_ROWBAND_STAGED = 4 /* bits only: as ROWBAND_COMPACT, but the random
+                               numbers of all four colour classes of a launch are
+                               drawn in one batch (for a superset of the sites
+                               that can change) before the classes are updated;
+                               needs 8 L R + O(L) bytes of LDS, so large L use
+                               ROWBAND_COMPACT under AUTO; an explicit request
+                               that does not fit is PGG_E_INVAL                 */
 } pgg_kernel;
 
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
@@ -147,6 +156,20 @@ pgg_status pgg_write_lattice(pgg_sim* s, const uint8_t* host_LxL, uint64_t t);
 /* Copy the 153 Fermi thresholds T[(dSigma + 25) * 3 + ds + 1] that the
  * device uses to host_T (host, 153 entries).  Synchronises the stream. */
 pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T);
+
+/* Diagnostics for measurement.  With enable != 0, every later launch of the
+ * sweep kernel by pgg_sweep on this handle is bracketed by a pair of HIP
+ * events on the handle's stream, and the row-band kernels count the site
+ * updates that drew random numbers.  Resets the totals.  Timing adds event
+ * records between launches, so a throughput measurement should run with it
+ * disabled.  Synchronises the stream. */
+pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable);
+
+/* Totals since the last pgg_set_kernel_timing: number of timed sweep-kernel
+ * launches, their summed event-to-event duration in ms, and the number of
+ * site updates that drew random numbers (row-band kernels; 0 otherwise).
+ * All three pointers are host and must be non-NULL.  Synchronises. */
+pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, uint64_t* drawn);
 
 /* Release the handle and every buffer the library allocated.  Never frees a
  * caller-supplied dev_buf.  NULL is a no-op.  Synchronises the stream. */

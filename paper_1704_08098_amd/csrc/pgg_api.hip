@@ -42,9 +42,27 @@ struct pgg_sim {
     unsigned long long* d_counts = nullptr;
     uint64_t t = 0;
     bool poisoned = false;
+    // Diagnostics (pgg_set_kernel_timing): a pair of HIP events around every
+    // launch of the sweep kernel, folded into the totals when read.
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // pool; 2 per launch
+    size_t events_used = 0;
+    uint64_t timed_launches = 0;
+    double timed_ms = 0.0;
+    unsigned long long* d_drawn = nullptr;
 };
 
 namespace {
+
+// Rows per workgroup for the row-band kernels: enough colour sites per
+// class to occupy the workgroup's 256 lanes.
+int choose_R(uint32_t L) {
+    const int q4 = (int)L / 4;
+    int R = (256 + q4 - 1) / q4;
+    if (R > q4) R = q4;
+    if (R < 1) R = 1;
+    return R;
+}
 
 bool params_valid(const pgg_params* p, const char** why) {
     if (!p) { *why = "params is NULL"; return false; }
@@ -60,7 +78,12 @@ bool params_valid(const pgg_params* p, const char** why) {
             break;
         case PGG_KERNEL_ROWBAND:
         case PGG_KERNEL_ROWBAND_COMPACT:
+        case PGG_KERNEL_ROWBAND_STAGED:
             if (p->layout != PGG_LAYOUT_BITS) { *why = "row-band kernels need the bits layout"; return false; }
+            if (p->kernel == PGG_KERNEL_ROWBAND_STAGED && p->L >= 4 && p->L <= 32768 && p->L % 4 == 0 &&
+                pgg::staged_lds_bytes((int)p->L, choose_R(p->L)) > pgg::kMaxDynamicLds) {
+                *why = "the staged kernel's LDS footprint does not fit at this L"; return false;
+            }
             break;
         default: *why = "unknown kernel"; return false;
     }
@@ -72,16 +95,6 @@ int bits_stride(uint32_t L) { return 2 * (int)((L + 63) / 64); }
 size_t lattice_bytes(const pgg_params* p) {
     if (p->layout == PGG_LAYOUT_INT8) return (size_t)p->L * p->L;
     return (size_t)p->L * (size_t)bits_stride(p->L) * sizeof(uint32_t);
-}
-
-// Rows per workgroup for the row-band kernels: enough colour sites per
-// class to occupy the workgroup's 256 lanes.
-int choose_R(uint32_t L) {
-    const int q4 = (int)L / 4;
-    int R = (256 + q4 - 1) / q4;
-    if (R > q4) R = q4;
-    if (R < 1) R = 1;
-    return R;
 }
 
 struct DeviceGuard {
@@ -122,7 +135,48 @@ void release(pgg_sim* s) {
     if (s->d_nc) (void)hipFree(s->d_nc);
     if (s->d_delta) (void)hipFree(s->d_delta);
     if (s->d_counts) (void)hipFree(s->d_counts);
+    if (s->d_drawn) (void)hipFree(s->d_drawn);
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     delete s;
+}
+
+// Fold the recorded event pairs into the totals (synchronises the stream).
+hipError_t fold_timing(pgg_sim* s) {
+    if (s->events_used == 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return e;
+    for (size_t q = 0; q + 1 < s->events_used; q += 2) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, s->events[q], s->events[q + 1]);
+        if (e != hipSuccess) return e;
+        s->timed_ms += ms;
+        s->timed_launches += 1;
+    }
+    s->events_used = 0;
+    return hipSuccess;
+}
+
+// Bracket one kernel launch with events when timing is enabled.
+template <class F>
+hipError_t timed_launch(pgg_sim* s, F&& launch) {
+    if (!s->timing) return launch();
+    if (s->events_used + 2 > s->events.size()) {
+        hipError_t e = fold_timing(s);
+        if (e != hipSuccess) return e;
+        while (s->events.size() < 8192) {
+            hipEvent_t ev;
+            e = hipEventCreate(&ev);
+            if (e != hipSuccess) return e;
+            s->events.push_back(ev);
+        }
+    }
+    hipError_t e = hipEventRecord(s->events[s->events_used], s->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(s->events[s->events_used + 1], s->stream);
+    s->events_used += 2;
+    return e;
 }
 
 }  // namespace
@@ -158,9 +212,14 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
         return PGG_E_DEVICE;
     }
     s->stride = bits_stride(p->L);
-    s->kernel = p->kernel != PGG_KERNEL_AUTO ? (int)p->kernel
-                : (p->layout == PGG_LAYOUT_INT8 ? PGG_KERNEL_COLOUR : PGG_KERNEL_ROWBAND_COMPACT);
     s->R = choose_R(p->L);
+    if (p->kernel != PGG_KERNEL_AUTO)
+        s->kernel = (int)p->kernel;
+    else if (p->layout == PGG_LAYOUT_INT8)
+        s->kernel = PGG_KERNEL_COLOUR;
+    else
+        s->kernel = pgg::staged_lds_bytes((int)p->L, s->R) <= pgg::kMaxDynamicLds ? PGG_KERNEL_ROWBAND_STAGED
+                                                                                 : PGG_KERNEL_ROWBAND_COMPACT;
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t e = hipMalloc(ptr, bytes);
@@ -212,13 +271,29 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         PGG_HIP(s, pgg::launch_fill_u64(s->d_delta, n, 0ull, s->stream));
         for (uint32_t q = 0; q < n; ++q) {
             const uint32_t t = (uint32_t)(s->t + done + q);
+            unsigned long long* dq = s->d_delta + q;
             if (s->kernel == PGG_KERNEL_COLOUR) {
-                PGG_HIP(s, pgg::launch_colour_sweep((uint8_t*)s->lattice, L, t, s->p.seed, s->d_table,
-                                                    s->d_delta + q, s->stream));
+                for (int k = 0; k < 16; ++k)
+                    PGG_HIP(s, timed_launch(s, [&] {
+                        return pgg::launch_colour_phase((uint8_t*)s->lattice, L, k, t, s->p.seed,
+                                                        s->d_table, dq, s->stream);
+                    }));
+            } else if (s->kernel == PGG_KERNEL_ROWBAND_STAGED) {
+                unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
+                for (int a = 0; a < 4; ++a)
+                    PGG_HIP(s, timed_launch(s, [&] {
+                        return pgg::launch_staged_residue((uint32_t*)s->lattice, L, s->stride, s->R, a, t,
+                                                          s->p.seed, s->d_table, dq, drawn, s->stream);
+                    }));
             } else {
-                PGG_HIP(s, pgg::launch_rowband_sweep((uint32_t*)s->lattice, L, s->stride, s->R,
-                                                     s->kernel == PGG_KERNEL_ROWBAND_COMPACT, t,
-                                                     s->p.seed, s->d_table, s->d_delta + q, s->stream));
+                const bool compact = s->kernel == PGG_KERNEL_ROWBAND_COMPACT;
+                unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
+                for (int a = 0; a < 4; ++a)
+                    PGG_HIP(s, timed_launch(s, [&] {
+                        return pgg::launch_rowband_residue((uint32_t*)s->lattice, L, s->stride, s->R,
+                                                           compact, a, t, s->p.seed, s->d_table, dq,
+                                                           drawn, s->stream);
+                    }));
             }
         }
         PGG_HIP(s, pgg::launch_scan_counts(s->d_delta, s->d_counts, (int)n, s->d_nc, s->stream));
@@ -313,6 +388,38 @@ pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T) {
     PGG_HIP(s, hipMemcpyAsync(host_T, s->d_table, pgg::kTableSize * sizeof(uint32_t),
                               hipMemcpyDeviceToHost, s->stream));
     PGG_HIP(s, hipStreamSynchronize(s->stream));
+    return PGG_OK;
+}
+
+pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable) {
+    PGG_LIVE(s);
+    DeviceGuard guard(s->device);
+    if (enable && !s->d_drawn) {
+        hipError_t e = hipMalloc((void**)&s->d_drawn, sizeof(unsigned long long));
+        if (e != hipSuccess) { set_err("hipMalloc failed: %s", hipGetErrorString(e)); return PGG_E_NOMEM; }
+    }
+    PGG_HIP(s, fold_timing(s));
+    if (enable) PGG_HIP(s, pgg::launch_fill_u64(s->d_drawn, 1, 0ull, s->stream));
+    PGG_HIP(s, hipStreamSynchronize(s->stream));
+    s->timing = enable != 0;
+    s->timed_launches = 0;
+    s->timed_ms = 0.0;
+    return PGG_OK;
+}
+
+pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, uint64_t* drawn) {
+    PGG_LIVE(s);
+    if (!launches || !total_ms || !drawn) { set_err("NULL argument"); return PGG_E_INVAL; }
+    DeviceGuard guard(s->device);
+    PGG_HIP(s, fold_timing(s));
+    unsigned long long d = 0;
+    if (s->d_drawn) {
+        PGG_HIP(s, hipMemcpyAsync(&d, s->d_drawn, sizeof(d), hipMemcpyDeviceToHost, s->stream));
+        PGG_HIP(s, hipStreamSynchronize(s->stream));
+    }
+    *launches = s->timed_launches;
+    *total_ms = s->timed_ms;
+    *drawn = d;
     return PGG_OK;
 }
 

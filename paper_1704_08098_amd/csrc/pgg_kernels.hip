@@ -157,7 +157,7 @@ template <bool COMPACT>
 __global__ void __launch_bounds__(kRowbandThreads)
 k_rowband_bits(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, int R, uint32_t t,
                uint32_t k0, uint32_t k1, const uint32_t* __restrict__ T,
-               unsigned long long* __restrict__ delta) {
+               unsigned long long* __restrict__ delta, unsigned long long* __restrict__ drawn) {
     extern __shared__ uint32_t smem[];
     const int ldw = nw + 1;             // one zero pad word per staged row
     const int rows = 4 * R + 3;
@@ -266,7 +266,13 @@ k_rowband_bits(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, int
     }
     if (my_delta) atomicAdd(&s_delta, my_delta);
     __syncthreads();
-    if (threadIdx.x == 0 && s_delta) atomicAdd(delta, (unsigned long long)(long long)s_delta);
+    if (threadIdx.x == 0) {
+        if (s_delta) atomicAdd(delta, (unsigned long long)(long long)s_delta);
+        if (drawn) {  // diagnostics: number of site updates that drew random numbers
+            const int n = COMPACT ? s_count[0] + s_count[1] + s_count[2] + s_count[3] : 4 * Rv * q4;
+            atomicAdd(drawn, (unsigned long long)n);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -416,15 +422,13 @@ hipError_t launch_scan_counts(const unsigned long long* delta, unsigned long lon
     return hipGetLastError();
 }
 
-hipError_t launch_colour_sweep(uint8_t* s, int L, uint32_t t, uint64_t seed, const uint32_t* T,
-                               unsigned long long* delta, hipStream_t st) {
+hipError_t launch_colour_phase(uint8_t* s, int L, int k, uint32_t t, uint64_t seed,
+                               const uint32_t* T, unsigned long long* delta, hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const int64_t per = (int64_t)(L / 4) * (L / 4);
     const int grid = (int)((per + 255) / 256);
-    for (int k = 0; k < 16; ++k) {
-        hipLaunchKernelGGL(k_colour_int8, dim3(grid), dim3(256), 0, st, s, L, k / 4, k % 4, t, k0, k1,
-                           T, delta);
-    }
+    hipLaunchKernelGGL(k_colour_int8, dim3(grid), dim3(256), 0, st, s, L, k / 4, k % 4, t, k0, k1, T,
+                       delta);
     return hipGetLastError();
 }
 
@@ -435,21 +439,20 @@ size_t rowband_lds_bytes(int L, int R, bool compact) {
     return words * sizeof(uint32_t);
 }
 
-hipError_t launch_rowband_sweep(uint32_t* lat, int L, int stride, int R, bool compact, uint32_t t,
-                                uint64_t seed, const uint32_t* T, unsigned long long* delta,
-                                hipStream_t st) {
+hipError_t launch_rowband_residue(uint32_t* lat, int L, int stride, int R, bool compact, int a,
+                                  uint32_t t, uint64_t seed, const uint32_t* T,
+                                  unsigned long long* delta, unsigned long long* drawn,
+                                  hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const int nw = (L + 31) / 32;
     const int bands = (L / 4 + R - 1) / R;
     const size_t lds = rowband_lds_bytes(L, R, compact);
-    for (int a = 0; a < 4; ++a) {
-        if (compact)
-            hipLaunchKernelGGL(k_rowband_bits<true>, dim3(bands), dim3(kRowbandThreads), lds, st, lat, L,
-                               stride, nw, a, R, t, k0, k1, T, delta);
-        else
-            hipLaunchKernelGGL(k_rowband_bits<false>, dim3(bands), dim3(kRowbandThreads), lds, st, lat,
-                               L, stride, nw, a, R, t, k0, k1, T, delta);
-    }
+    if (compact)
+        hipLaunchKernelGGL(k_rowband_bits<true>, dim3(bands), dim3(kRowbandThreads), lds, st, lat, L,
+                           stride, nw, a, R, t, k0, k1, T, delta, drawn);
+    else
+        hipLaunchKernelGGL(k_rowband_bits<false>, dim3(bands), dim3(kRowbandThreads), lds, st, lat, L,
+                           stride, nw, a, R, t, k0, k1, T, delta, drawn);
     return hipGetLastError();
 }
 

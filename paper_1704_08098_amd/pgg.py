@@ -20,15 +20,15 @@ LIB_PATH = os.path.join(_PKG, "libpgg.so")
 
 PGG_OK, PGG_E_INVAL, PGG_E_NOMEM, PGG_E_DEVICE, PGG_E_STATE = 0, -1, -2, -3, -4
 LAYOUT_INT8, LAYOUT_BITS = 0, 1
-KERNEL_AUTO, KERNEL_COLOUR, KERNEL_ROWBAND, KERNEL_ROWBAND_COMPACT = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_COLOUR, KERNEL_ROWBAND, KERNEL_ROWBAND_COMPACT, KERNEL_ROWBAND_STAGED = 0, 1, 2, 3, 4
 LAYOUTS = {"int8": LAYOUT_INT8, "bits": LAYOUT_BITS}
 KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBAND,
-           "rowband_compact": KERNEL_ROWBAND_COMPACT}
+           "rowband_compact": KERNEL_ROWBAND_COMPACT, "rowband_staged": KERNEL_ROWBAND_STAGED}
 
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
-           "pgg_destroy", "pgg_last_error")
+           "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_destroy", "pgg_last_error")
 
 
 class PggParams(ctypes.Structure):
@@ -66,6 +66,8 @@ def load():
         "pgg_read_lattice": (ctypes.c_int, [vp, u8p]),
         "pgg_write_lattice": (ctypes.c_int, [vp, u8p, ctypes.c_uint64]),
         "pgg_threshold_table": (ctypes.c_int, [vp, u32p]),
+        "pgg_set_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+        "pgg_kernel_timing": (ctypes.c_int, [vp, u64p, P(ctypes.c_double), u64p]),
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
     }
@@ -156,6 +158,17 @@ def pgg_threshold_table(handle) -> np.ndarray:
     return out.reshape(51, 3)
 
 
+def pgg_set_kernel_timing(handle, enable: bool) -> None:
+    _check(load().pgg_set_kernel_timing(handle, 1 if enable else 0))
+
+
+def pgg_kernel_timing(handle):
+    """(launches, total_ms, drawn) since timing was last enabled."""
+    n, ms, drawn = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_uint64()
+    _check(load().pgg_kernel_timing(handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(drawn)))
+    return n.value, ms.value, drawn.value
+
+
 def pgg_destroy(handle) -> None:
     if handle:
         load().pgg_destroy(handle)
@@ -192,6 +205,12 @@ class Sim:
 
     def threshold_table(self):
         return pgg_threshold_table(self.handle)
+
+    def set_kernel_timing(self, enable=True):
+        pgg_set_kernel_timing(self.handle, enable)
+
+    def kernel_timing(self):
+        return pgg_kernel_timing(self.handle)
 
     def close(self):
         if self.handle:

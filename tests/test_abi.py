@@ -51,7 +51,9 @@ def test_device_bytes(pgg):
                                 dict(r=float("nan")), dict(r=-0.5), dict(p0=1.5),
                                 dict(p0=float("nan")), dict(layout=7),
                                 dict(layout="int8", kernel="rowband"),
-                                dict(layout="bits", kernel="colour"), dict(kernel=9)])
+                                dict(layout="bits", kernel="colour"), dict(kernel=9),
+                                dict(L=32768, kernel="rowband_staged"),
+                                dict(layout="int8", kernel="rowband_staged")])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")
     args.update(kw)

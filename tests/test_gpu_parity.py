@@ -12,7 +12,8 @@ from paper_1704_08098_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [("int8", "colour"), ("bits", "rowband"), ("bits", "rowband_compact")]
+VARIANTS = [("int8", "colour"), ("bits", "rowband"), ("bits", "rowband_compact"),
+            ("bits", "rowband_staged")]
 
 
 def say(*a):
