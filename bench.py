@@ -57,8 +57,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream):
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream)
+def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0):
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile)
     sim.sweep(warmup, want_counts=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -70,9 +70,9 @@ def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream):
     return dt, nc
 
 
-def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream):
+def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0):
     """Same trajectory with every sweep-kernel launch bracketed by events."""
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream)
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile)
     sim.sweep(warmup, want_counts=False)
     sim.set_kernel_timing(True)
     sim.sweep(steps, want_counts=False)
@@ -101,8 +101,9 @@ def main():
     ap.add_argument("--L", type=int, default=wl.DECAY["L"])
     ap.add_argument("--r", type=float, default=wl.R_CRITICAL)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--kernel", default="rowband_staged",
-                    choices=["rowband_staged", "rowband_compact", "rowband", "colour"])
+    ap.add_argument("--kernel", default="segment",
+                    choices=["segment", "strip", "rowband_staged", "rowband_compact", "rowband", "colour"])
+    ap.add_argument("--tile", type=int, default=0, help="strip height / rows per band (0 = auto)")
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -136,12 +137,13 @@ def main():
         del a, b
 
     log("timed pass: L=%d r=%g kernel=%s warmup=%d steps=%d" % (L, r, args.kernel, args.warmup, args.steps))
-    dt, nc_end = time_sweeps(pgg, torch, L, r, seed, args.kernel, layout, args.warmup, args.steps, stream)
+    dt, nc_end = time_sweeps(pgg, torch, L, r, seed, args.kernel, layout, args.warmup, args.steps, stream,
+                             args.tile)
     updates = float(L) * L * args.steps
     value = updates / dt
 
     dense = None
-    if args.kernel in ("rowband_compact", "rowband_staged") and args.dense_steps > 0:
+    if args.kernel in ("segment", "strip", "rowband_compact", "rowband_staged") and args.dense_steps > 0:
         log("dense pass: %d sweeps" % args.dense_steps)
         ddt, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", layout, args.warmup,
                              args.dense_steps, stream)
@@ -151,9 +153,9 @@ def main():
 
     log("kernel-timing pass")
     launches, kms, drawn = kernel_pass(pgg, torch, L, r, seed, args.kernel, layout, args.warmup,
-                                       args.steps, stream)
+                                       args.steps, stream, args.tile)
     avg_ms = kms / max(launches, 1)
-    sites_per_launch = updates / max(launches, 1)
+    sites_per_launch = updates / max(launches, 1)  # the strip kernel: one launch per timed call
     if args.kernel == "colour":
         drawn = updates
     drawn_per_launch = drawn / max(launches, 1)
@@ -161,7 +163,8 @@ def main():
     achieved_tops = slots / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": None,
-                "kernel": {"rowband_staged": "k_rowband_staged", "rowband_compact": "k_rowband_bits<true>",
+                "kernel": {"segment": "k_segment", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
+                           "rowband_compact": "k_rowband_bits<true>",
                            "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,
                 "drawn_fraction": drawn / updates,

@@ -69,9 +69,8 @@ typedef enum {
 
 /* Sweep kernel selection (a tuning choice; results never depend on it). */
 typedef enum {
-    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR; bits -> ROWBAND_STAGED when its
-                               LDS footprint fits (L <= 4096 or so), otherwise
-                               ROWBAND_COMPACT                                 */
+    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR; bits -> SEGMENT for L >= 64,
+                               ROWBAND_COMPACT below                           */
     PGG_KERNEL_COLOUR = 1,  /* int8 only: one launch per colour class, global
                                memory, every site evaluated (reference path)   */
     PGG_KERNEL_ROWBAND = 2, /* bits only: one launch per row residue i mod 4
@@ -88,7 +87,24 @@ typedef enum {
                                that can change) before the classes are updated;
                                needs 8 L R + O(L) bytes of LDS, so large L use
                                ROWBAND_COMPACT under AUTO; an explicit request
-                               that does not fit is PGG_E_INVAL                 */
+                               that does not fit is PGG_E_INVAL                 */,
+    PGG_KERNEL_STRIP = 5    /* bits only: one persistent cooperative launch per
+                               pgg_sweep call; each workgroup keeps a strip of
+                               rows in LDS for all sweeps and exchanges 3-row
+                               halos with its two neighbours through global
+                               memory and progress flags (no grid barrier).
+                               Waits are bounded: a neighbour that stops making
+                               progress for ~4 s aborts the launch, and the call
+                               that observes it returns PGG_E_DEVICE.  Needs the
+                               same LDS footprint limit as ROWBAND_STAGED        */,
+    PGG_KERNEL_SEGMENT = 6  /* bits only, L >= 64: one launch per row residue;
+                               one wave per row segment, no workgroup barriers:
+                               the wave copies the 7 rows it reads into a
+                               private LDS window, runs the four colour classes
+                               on the segment plus a margin of 9/6/3/0 columns
+                               (recomputed by both neighbouring segments) and
+                               writes back its own columns; sites without a
+                               differing neighbour draw nothing                  */
 } pgg_kernel;
 
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
@@ -100,6 +116,11 @@ typedef struct {
     uint64_t seed;   /* Philox key                                            */
     uint32_t layout; /* pgg_layout                                            */
     uint32_t kernel; /* pgg_kernel; must match the layout unless AUTO         */
+    uint32_t tile;   /* work split; 0 = chosen by the library.  STRIP: rows
+                        per strip (>= 4); ROWBAND*: rows per band; SEGMENT:
+                        columns per segment (a multiple of 32, <= L - 32).
+                        A value the kernel cannot use is PGG_E_INVAL.  Results
+                        never depend on it.                                   */
 } pgg_params;
 
 typedef struct pgg_sim pgg_sim; /* opaque handle */
@@ -170,6 +191,14 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable);
  * site updates that drew random numbers (row-band kernels; 0 otherwise).
  * All three pointers are host and must be non-NULL.  Synchronises. */
 pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, uint64_t* drawn);
+
+/* Diagnostics for failure handling: the longest time (seconds, >= 0) a
+ * workgroup of the STRIP kernel waits for a neighbouring strip before it
+ * aborts the launch (default 4).  0 makes almost every wait abort, which
+ * lets a test exercise the abort path: the launch then ends early on every
+ * workgroup, and the next synchronising call returns PGG_E_DEVICE and
+ * poisons the handle.  Other kernels ignore it.  Host only. */
+pgg_status pgg_set_strip_wait(pgg_sim* s, double seconds);
 
 /* Release the handle and every buffer the library allocated.  Never frees a
  * caller-supplied dev_buf.  NULL is a no-op.  Synchronises the stream. */

@@ -23,7 +23,7 @@ void set_err(const char* fmt, ...) {
     va_end(ap);
 }
 
-constexpr uint32_t kChunk = 65536;  // sweeps per count-history chunk
+constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 
 }  // namespace
 
@@ -36,6 +36,7 @@ struct pgg_sim {
     int stride = 0;  // bits layout: 32-bit words per row
     int kernel = PGG_KERNEL_COLOUR;
     int R = 1;       // rows per workgroup (row-band kernels)
+    int segw = 0;    // columns per segment (segment kernel)
     uint32_t* d_table = nullptr;
     unsigned long long* d_nc = nullptr;
     unsigned long long* d_delta = nullptr;
@@ -50,6 +51,15 @@ struct pgg_sim {
     uint64_t timed_launches = 0;
     double timed_ms = 0.0;
     unsigned long long* d_drawn = nullptr;
+    // Persistent strip kernel plan.
+    pgg::StripTask* d_tasks = nullptr;
+    int n_tasks = 0;
+    int strip_G = 1;
+    size_t strip_lds = 0;
+    uint64_t* d_ring = nullptr;
+    size_t ring_words = 0;
+    uint32_t* d_abort = nullptr;
+    uint64_t wait_ticks = 0;
 };
 
 namespace {
@@ -64,6 +74,22 @@ int choose_R(uint32_t L) {
     return R;
 }
 
+// Columns per segment: about 8 waves per SIMD at large L, at least 128
+// columns (the 18-column margins stay cheap), at most L - 32.
+int choose_segw(uint32_t L) {
+    long w = ((long)L * (long)L / 32768) & ~31L;
+    if (w < 128) w = 128;
+    const long cap = ((long)L - 32) & ~31L;
+    if (w > cap) w = cap;
+    if (w > (long)L / 2 && L >= 128) w = ((long)L / 2) & ~31L;
+    if (w < 32) w = 32;
+    return (int)w;
+}
+
+bool strip_fits(uint32_t L, uint32_t H) {
+    return pgg::strip_lds_bytes((int)L, (int)H, 1) <= pgg::kMaxDynamicLds;
+}
+
 bool params_valid(const pgg_params* p, const char** why) {
     if (!p) { *why = "params is NULL"; return false; }
     if (p->L < 4 || p->L > 32768 || (p->L % 4) != 0) { *why = "L must be a multiple of 4 in [4, 32768]"; return false; }
@@ -71,19 +97,36 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (!std::isfinite(p->K) || !(p->K > 0.0)) { *why = "K must be finite and > 0"; return false; }
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_INT8 && p->layout != PGG_LAYOUT_BITS) { *why = "unknown layout"; return false; }
+    const uint32_t tr = p->tile;
     switch (p->kernel) {
-        case PGG_KERNEL_AUTO: break;
+        case PGG_KERNEL_AUTO:
+            if (tr != 0) { *why = "tile needs an explicit kernel"; return false; }
+            break;
         case PGG_KERNEL_COLOUR:
             if (p->layout != PGG_LAYOUT_INT8) { *why = "the colour kernel needs the int8 layout"; return false; }
+            if (tr != 0) { *why = "the colour kernel takes no tile"; return false; }
             break;
         case PGG_KERNEL_ROWBAND:
         case PGG_KERNEL_ROWBAND_COMPACT:
-        case PGG_KERNEL_ROWBAND_STAGED:
+        case PGG_KERNEL_ROWBAND_STAGED: {
             if (p->layout != PGG_LAYOUT_BITS) { *why = "row-band kernels need the bits layout"; return false; }
-            if (p->kernel == PGG_KERNEL_ROWBAND_STAGED && p->L >= 4 && p->L <= 32768 && p->L % 4 == 0 &&
-                pgg::staged_lds_bytes((int)p->L, choose_R(p->L)) > pgg::kMaxDynamicLds) {
-                *why = "the staged kernel's LDS footprint does not fit at this L"; return false;
-            }
+            if (tr > p->L / 4) { *why = "tile exceeds the L/4 rows of a residue"; return false; }
+            const int R = tr ? (int)tr : choose_R(p->L);
+            const size_t lds = p->kernel == PGG_KERNEL_ROWBAND_STAGED
+                                   ? pgg::staged_lds_bytes((int)p->L, R)
+                                   : pgg::rowband_lds_bytes((int)p->L, R, p->kernel == PGG_KERNEL_ROWBAND_COMPACT);
+            if (lds > pgg::kMaxDynamicLds) { *why = "the kernel's LDS footprint does not fit at this L and tile"; return false; }
+            break;
+        }
+        case PGG_KERNEL_SEGMENT:
+            if (p->layout != PGG_LAYOUT_BITS) { *why = "the segment kernel needs the bits layout"; return false; }
+            if (p->L < 64) { *why = "the segment kernel needs L >= 64"; return false; }
+            if (tr != 0 && (tr % 32 != 0 || tr + 32 > p->L)) { *why = "segment tile must be a multiple of 32 and <= L - 32"; return false; }
+            break;
+        case PGG_KERNEL_STRIP:
+            if (p->layout != PGG_LAYOUT_BITS) { *why = "the strip kernel needs the bits layout"; return false; }
+            if (tr != 0 && (tr < 4 || tr > p->L)) { *why = "strip tile must lie in [4, L]"; return false; }
+            if (!strip_fits(p->L, tr ? tr : 4)) { *why = "the strip kernel's LDS footprint does not fit at this L"; return false; }
             break;
         default: *why = "unknown kernel"; return false;
     }
@@ -136,6 +179,9 @@ void release(pgg_sim* s) {
     if (s->d_delta) (void)hipFree(s->d_delta);
     if (s->d_counts) (void)hipFree(s->d_counts);
     if (s->d_drawn) (void)hipFree(s->d_drawn);
+    if (s->d_tasks) (void)hipFree(s->d_tasks);
+    if (s->d_ring) (void)hipFree(s->d_ring);
+    if (s->d_abort) (void)hipFree(s->d_abort);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     delete s;
 }
@@ -179,6 +225,82 @@ hipError_t timed_launch(pgg_sim* s, F&& launch) {
     return e;
 }
 
+// Split the lattice into strips for the persistent kernel: as many strips as
+// workgroups can be resident at once (at least 4 rows each, or tile),
+// sizes differing by at most one row.
+pgg_status plan_strips(pgg_sim* s, uint32_t tile) {
+    const int L = (int)s->p.L, nw = (L + 31) / 32;
+    int cus = 0, bpc = 0, dev = 0;
+    int H = tile ? (int)tile : 4;
+    hipError_t e = hipSuccess;
+    for (;;) {
+        s->strip_lds = pgg::strip_lds_bytes(L, H + 1, 1);  // strips hold H or H + 1 rows
+        e = pgg::strip_capacity(s->strip_lds, &bpc, &cus);
+        if (e != hipSuccess) { set_err("occupancy query failed: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
+        const int capacity = bpc * cus;
+        if (capacity < 1) { set_err("the strip kernel cannot be resident"); return PGG_E_INVAL; }
+        const int S = (L + H - 1) / H;
+        if (S <= capacity) break;
+        if (tile) { set_err("%d strips of %d rows exceed the %d resident workgroups", S, H, capacity); return PGG_E_INVAL; }
+        H = (L + capacity - 1) / capacity;
+        if (H < 4) H = 4;
+    }
+    const int S = (L + H - 1) / H;
+    const int base = L / S, extra = L % S;
+    std::vector<pgg::StripTask> tasks(S);
+    int r0 = 0;
+    for (int k = 0; k < S; ++k) {
+        pgg::StripTask& tk = tasks[k];
+        std::memset(&tk, 0, sizeof(tk));
+        tk.lat = (uint32_t*)s->lattice;
+        tk.T = s->d_table;
+        tk.L = L;
+        tk.stride = s->stride;
+        tk.nw = nw;
+        tk.r0 = r0;
+        tk.H = base + (k < extra ? 1 : 0);
+        tk.up = (k + S - 1) % S;
+        tk.down = (k + 1) % S;
+        tk.k0 = (uint32_t)s->p.seed;
+        tk.k1 = (uint32_t)(s->p.seed >> 32);
+        r0 += tk.H;
+    }
+    s->n_tasks = S;
+    s->strip_G = 1;
+    s->ring_words = (size_t)S * 2 * 6 * nw;
+    int rate_khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    s->wait_ticks = (uint64_t)rate_khz * 1000ull * 4ull;  // 4 s without neighbour progress
+    auto alloc = [&](void** ptr, size_t bytes) -> hipError_t { return hipMalloc(ptr, bytes); };
+    if ((e = alloc((void**)&s->d_tasks, S * sizeof(pgg::StripTask))) != hipSuccess ||
+        (e = alloc((void**)&s->d_ring, (size_t)S * 2 * 6 * nw * sizeof(uint64_t))) != hipSuccess ||
+        (e = alloc((void**)&s->d_abort, sizeof(uint32_t))) != hipSuccess) {
+        set_err("hipMalloc failed: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
+    }
+    e = hipMemcpy(s->d_tasks, tasks.data(), S * sizeof(pgg::StripTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = pgg::launch_fill_u32(s->d_abort, 1, 0u, s->stream);
+    if (e != hipSuccess) { set_err("strip plan upload failed: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
+    return PGG_OK;
+}
+
+// After a stream synchronisation: a persistent launch that gave up waiting
+// leaves the abort flag set; report it and poison the handle.
+pgg_status check_abort(pgg_sim* s) {
+    if (!s->d_abort) return PGG_OK;
+    uint32_t v = 0;
+    hipError_t e = hipMemcpy(&v, s->d_abort, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(s, e, "abort flag read");
+    if (v) {
+        set_err("a persistent strip launch aborted: a workgroup waited too long for its neighbours");
+        s->poisoned = true;
+        return PGG_E_DEVICE;
+    }
+    return PGG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -212,14 +334,14 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
         return PGG_E_DEVICE;
     }
     s->stride = bits_stride(p->L);
-    s->R = choose_R(p->L);
+    s->R = p->tile ? (int)p->tile : choose_R(p->L);
     if (p->kernel != PGG_KERNEL_AUTO)
         s->kernel = (int)p->kernel;
     else if (p->layout == PGG_LAYOUT_INT8)
         s->kernel = PGG_KERNEL_COLOUR;
     else
-        s->kernel = pgg::staged_lds_bytes((int)p->L, s->R) <= pgg::kMaxDynamicLds ? PGG_KERNEL_ROWBAND_STAGED
-                                                                                 : PGG_KERNEL_ROWBAND_COMPACT;
+        s->kernel = p->L >= 64 ? PGG_KERNEL_SEGMENT : PGG_KERNEL_ROWBAND_COMPACT;
+    if (s->kernel == PGG_KERNEL_SEGMENT) s->segw = p->tile ? (int)p->tile : choose_segw(p->L);
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t e = hipMalloc(ptr, bytes);
@@ -238,8 +360,9 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     }
     if (st == PGG_OK) st = alloc((void**)&s->d_table, pgg::kTableSize * sizeof(uint32_t));
     if (st == PGG_OK) st = alloc((void**)&s->d_nc, sizeof(unsigned long long));
-    if (st == PGG_OK) st = alloc((void**)&s->d_delta, kChunk * sizeof(unsigned long long));
+    if (st == PGG_OK) st = alloc((void**)&s->d_delta, (size_t)kChunk * pgg::kSweepWords * sizeof(unsigned long long));
     if (st == PGG_OK) st = alloc((void**)&s->d_counts, kChunk * sizeof(unsigned long long));
+    if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
     if (st != PGG_OK) { release(s); return st; }
 
     hipError_t e = pgg::launch_build_table(p->r, p->K, s->d_table, s->stream);
@@ -268,15 +391,33 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     uint32_t done = 0;
     while (done < n_sweeps) {
         const uint32_t n = std::min(kChunk, n_sweeps - done);
-        PGG_HIP(s, pgg::launch_fill_u64(s->d_delta, n, 0ull, s->stream));
-        for (uint32_t q = 0; q < n; ++q) {
+        PGG_HIP(s, pgg::launch_fill_u64(s->d_delta, (int64_t)n * pgg::kSweepWords, 0ull, s->stream));
+        if (s->kernel == PGG_KERNEL_STRIP) {
+            const uint32_t t0 = (uint32_t)(s->t + done);
+            PGG_HIP(s, pgg::launch_tasks_set(s->d_tasks, s->n_tasks, t0, (int)n, s->d_delta,
+                                             s->timing ? s->d_drawn : nullptr, s->stream));
+            // ring tags start at 0 in every launch (tags are step + 1 >= 1)
+            PGG_HIP(s, pgg::launch_fill_u64((unsigned long long*)s->d_ring, (int64_t)s->ring_words, 0ull, s->stream));
+            PGG_HIP(s, timed_launch(s, [&] {
+                return pgg::launch_strip(s->d_tasks, s->n_tasks, s->d_ring, s->d_abort, s->wait_ticks,
+                                         s->strip_G, s->strip_lds, s->stream);
+            }));
+        }
+        for (uint32_t q = 0; s->kernel != PGG_KERNEL_STRIP && q < n; ++q) {
             const uint32_t t = (uint32_t)(s->t + done + q);
-            unsigned long long* dq = s->d_delta + q;
+            unsigned long long* dq = s->d_delta + (size_t)q * pgg::kSweepWords;
             if (s->kernel == PGG_KERNEL_COLOUR) {
                 for (int k = 0; k < 16; ++k)
                     PGG_HIP(s, timed_launch(s, [&] {
                         return pgg::launch_colour_phase((uint8_t*)s->lattice, L, k, t, s->p.seed,
                                                         s->d_table, dq, s->stream);
+                    }));
+            } else if (s->kernel == PGG_KERNEL_SEGMENT) {
+                unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
+                for (int a = 0; a < 4; ++a)
+                    PGG_HIP(s, timed_launch(s, [&] {
+                        return pgg::launch_segment_residue((uint32_t*)s->lattice, L, s->stride, s->segw, a, t,
+                                                           s->p.seed, s->d_table, dq, drawn, s->stream);
                     }));
             } else if (s->kernel == PGG_KERNEL_ROWBAND_STAGED) {
                 unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
@@ -301,6 +442,8 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
             PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_counts, n * sizeof(uint64_t),
                                       hipMemcpyDeviceToHost, s->stream));
             PGG_HIP(s, hipStreamSynchronize(s->stream));
+            pgg_status as = check_abort(s);
+            if (as != PGG_OK) return as;
         }
         done += n;
     }
@@ -315,6 +458,8 @@ pgg_status pgg_coop_count(pgg_sim* s, uint64_t* n_c) {
     unsigned long long v = 0;
     PGG_HIP(s, hipMemcpyAsync(&v, s->d_nc, sizeof(v), hipMemcpyDeviceToHost, s->stream));
     PGG_HIP(s, hipStreamSynchronize(s->stream));
+    pgg_status as = check_abort(s);
+    if (as != PGG_OK) return as;
     *n_c = v;
     return PGG_OK;
 }
@@ -342,7 +487,7 @@ pgg_status pgg_read_lattice(pgg_sim* s, uint8_t* host_LxL) {
     if (s->p.layout == PGG_LAYOUT_INT8) {
         PGG_HIP(s, hipMemcpyAsync(host_LxL, s->lattice, n, hipMemcpyDeviceToHost, s->stream));
         PGG_HIP(s, hipStreamSynchronize(s->stream));
-        return PGG_OK;
+        return check_abort(s);
     }
     uint8_t* tmp = nullptr;
     hipError_t e = hipMalloc((void**)&tmp, n);
@@ -352,7 +497,7 @@ pgg_status pgg_read_lattice(pgg_sim* s, uint8_t* host_LxL) {
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return device_fail(s, e, "read_lattice");
-    return PGG_OK;
+    return check_abort(s);
 }
 
 pgg_status pgg_write_lattice(pgg_sim* s, const uint8_t* host_LxL, uint64_t t) {
@@ -395,11 +540,11 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable) {
     PGG_LIVE(s);
     DeviceGuard guard(s->device);
     if (enable && !s->d_drawn) {
-        hipError_t e = hipMalloc((void**)&s->d_drawn, sizeof(unsigned long long));
+        hipError_t e = hipMalloc((void**)&s->d_drawn, pgg::kSweepWords * sizeof(unsigned long long));
         if (e != hipSuccess) { set_err("hipMalloc failed: %s", hipGetErrorString(e)); return PGG_E_NOMEM; }
     }
     PGG_HIP(s, fold_timing(s));
-    if (enable) PGG_HIP(s, pgg::launch_fill_u64(s->d_drawn, 1, 0ull, s->stream));
+    if (enable) PGG_HIP(s, pgg::launch_fill_u64(s->d_drawn, pgg::kSweepWords, 0ull, s->stream));
     PGG_HIP(s, hipStreamSynchronize(s->stream));
     s->timing = enable != 0;
     s->timed_launches = 0;
@@ -414,12 +559,27 @@ pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, u
     PGG_HIP(s, fold_timing(s));
     unsigned long long d = 0;
     if (s->d_drawn) {
-        PGG_HIP(s, hipMemcpyAsync(&d, s->d_drawn, sizeof(d), hipMemcpyDeviceToHost, s->stream));
+        std::vector<unsigned long long> h(pgg::kSweepWords);
+        PGG_HIP(s, hipMemcpyAsync(h.data(), s->d_drawn, h.size() * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s->stream));
         PGG_HIP(s, hipStreamSynchronize(s->stream));
+        for (int k = 0; k < pgg::kSlots; ++k) d += h[(size_t)k * pgg::kSlotStride];
     }
+    pgg_status as = check_abort(s);
+    if (as != PGG_OK) return as;
     *launches = s->timed_launches;
     *total_ms = s->timed_ms;
     *drawn = d;
+    return PGG_OK;
+}
+
+pgg_status pgg_set_strip_wait(pgg_sim* s, double seconds) {
+    PGG_LIVE(s);
+    if (!(seconds >= 0.0 && seconds <= 3600.0)) { set_err("seconds must lie in [0, 3600]"); return PGG_E_INVAL; }
+    int dev = s->device, rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    s->wait_ticks = (uint64_t)(seconds * (double)rate_khz * 1000.0);
     return PGG_OK;
 }
 

@@ -8,7 +8,17 @@
 namespace pgg {
 
 constexpr int kTableSize = 153;       // 51 values of dSigma x 3 values of ds
-constexpr int kRowbandThreads = 256;  // workgroup size of the row-band kernel
+constexpr int kRowbandThreads = 256;  // workgroup size of the row-band kernels
+
+// Per-sweep counters (net change of the cooperator count, draws) are spread
+// over kSlots addresses kSlotStride words apart (one 128-byte line each):
+// thousands of workgroups adding to one address from 8 XCDs serialise.
+constexpr int kSlots = 32;
+constexpr int kSlotStride = 16;
+constexpr int kSweepWords = kSlots * kSlotStride;  // 64-bit words per sweep
+__device__ __forceinline__ unsigned long long* slot_of(unsigned long long* base, int id) {
+    return base + (id & (kSlots - 1)) * kSlotStride;
+}
 
 hipError_t launch_build_table(double r, double K, uint32_t* T, hipStream_t st);
 hipError_t launch_init(int layout, void* lat, int L, int stride, double p0, uint64_t seed,
@@ -20,8 +30,11 @@ hipError_t launch_unpack(const uint32_t* lat, uint8_t* s, int L, int stride, hip
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_scan_counts(const unsigned long long* delta, unsigned long long* counts, int n,
                               unsigned long long* nc, hipStream_t st);
-// One colour class k of sweep t on the int8 layout (16 per sweep), adding
-// the net change of the cooperator count to *delta.
+// Every launcher below takes `delta`, the kSweepWords counters of one sweep
+// (the net change of the cooperator count is added to one of its slots), and
+// an optional `drawn` of kSweepWords counters for the number of updates that
+// drew random numbers.
+// One colour class k of sweep t on the int8 layout (16 per sweep).
 hipError_t launch_colour_phase(uint8_t* s, int L, int k, uint32_t t, uint64_t seed,
                                const uint32_t* T, unsigned long long* delta, hipStream_t st);
 // The four colour classes of row residue a of sweep t on the bits layout
@@ -37,5 +50,36 @@ hipError_t launch_staged_residue(uint32_t* lat, int L, int stride, int R, int a,
                                  unsigned long long* drawn, hipStream_t st);
 size_t staged_lds_bytes(int L, int R);
 constexpr size_t kMaxDynamicLds = 64 * 1024;
+
+// Persistent strip kernel (pgg_strip.hip).  One task per workgroup: rows
+// [r0, r0 + H) of one lattice, the tasks owning the strips above (up) and
+// below (down) -- the task itself when the strip is the whole lattice --,
+// and n sweeps starting at sweep index t0.  delta[q] receives the net change
+// of the cooperator count in sweep t0 + q; drawn (optional) counts the
+// updates that drew random numbers.
+constexpr int kStripThreads = 512;
+struct StripTask {
+    uint32_t* lat;
+    const uint32_t* T;
+    unsigned long long* delta;
+    unsigned long long* drawn;
+    int L, stride, nw, r0, H, up, down, n;
+    uint32_t t0, k0, k1, pad;
+};
+hipError_t launch_strip(const StripTask* d_tasks, int n_tasks, uint64_t* ring, uint32_t* abort_flag,
+                        uint64_t wait_ticks, int G, size_t lds, hipStream_t st);
+size_t strip_lds_bytes(int L, int H, int G);
+hipError_t strip_capacity(size_t lds, int* blocks_per_cu, int* cus);
+// Set t0, n and delta of every task (single-lattice runs).
+hipError_t launch_tasks_set(StripTask* tasks, int n_tasks, uint32_t t0, int n,
+                            unsigned long long* delta, unsigned long long* drawn, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+
+// Segment kernel (pgg_segment.hip): one wave per row segment of segw columns.
+constexpr int kSegmentThreads = 256;
+hipError_t launch_segment_residue(uint32_t* lat, int L, int stride, int segw, int a, uint32_t t,
+                                  uint64_t seed, const uint32_t* T, unsigned long long* delta,
+                                  unsigned long long* drawn, hipStream_t st);
+size_t segment_lds_bytes(int segw);
 
 }  // namespace pgg

@@ -136,7 +136,8 @@ k_colour_int8(uint8_t* __restrict__ s, int L, int a, int b, uint32_t t, uint32_t
     }
     const long long up = __popcll(__ballot(change > 0));
     const long long dn = __popcll(__ballot(change < 0));
-    if ((threadIdx.x & 63) == 0 && up != dn) atomicAdd(delta, (unsigned long long)(up - dn));
+    if ((threadIdx.x & 63) == 0 && up != dn)
+        atomicAdd(slot_of(delta, (int)(blockIdx.x * 4 + (threadIdx.x >> 6))), (unsigned long long)(up - dn));
 }
 
 // ---------------------------------------------------------------------------
@@ -267,10 +268,10 @@ k_rowband_bits(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, int
     if (my_delta) atomicAdd(&s_delta, my_delta);
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (s_delta) atomicAdd(delta, (unsigned long long)(long long)s_delta);
+        if (s_delta) atomicAdd(slot_of(delta, (int)blockIdx.x), (unsigned long long)(long long)s_delta);
         if (drawn) {  // diagnostics: number of site updates that drew random numbers
             const int n = COMPACT ? s_count[0] + s_count[1] + s_count[2] + s_count[3] : 4 * Rv * q4;
-            atomicAdd(drawn, (unsigned long long)n);
+            atomicAdd(slot_of(drawn, (int)blockIdx.x), (unsigned long long)n);
         }
     }
 }
@@ -325,8 +326,17 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsign
         p[q] = v;
 }
 
-// counts[q] = nc + sum_{q' <= q} delta[q'] (two's complement), then nc =
-// counts[n - 1].  One block of 1024 threads; each owns a contiguous chunk.
+// counts[q] = nc + sum_{q' <= q} (sum of the kSlots slots of sweep q') in
+// two's complement, then nc = counts[n - 1].  One block of 1024 threads;
+// each owns a contiguous chunk of sweeps.
+__device__ __forceinline__ unsigned long long sweep_delta(const unsigned long long* __restrict__ delta, int q) {
+    unsigned long long v = 0;
+    const unsigned long long* row = delta + (size_t)q * kSweepWords;
+#pragma unroll 8
+    for (int k = 0; k < kSlots; ++k) v += row[k * kSlotStride];
+    return v;
+}
+
 __global__ void __launch_bounds__(1024)
 k_scan_counts(const unsigned long long* __restrict__ delta, unsigned long long* __restrict__ counts,
               int n, unsigned long long* __restrict__ nc) {
@@ -335,7 +345,7 @@ k_scan_counts(const unsigned long long* __restrict__ delta, unsigned long long* 
     const int chunk = (n + 1023) / 1024;
     const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
     unsigned long long sum = 0;
-    for (int q = lo; q < hi; ++q) sum += delta[q];
+    for (int q = lo; q < hi; ++q) sum += sweep_delta(delta, q);
     part[tid] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -346,7 +356,7 @@ k_scan_counts(const unsigned long long* __restrict__ delta, unsigned long long* 
     }
     unsigned long long run = *nc + (tid ? part[tid - 1] : 0ull);
     for (int q = lo; q < hi; ++q) {
-        run += delta[q];
+        run += sweep_delta(delta, q);
         counts[q] = run;
     }
     __syncthreads();

@@ -117,7 +117,7 @@ k_rowband_staged(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, i
     const int n0 = s_count[0], n1 = s_count[1], n2 = s_count[2], n3 = s_count[3];
     const int total = n0 + n1 + n2 + n3;
     const uint32_t kbase = (uint32_t)(4 * a);
-    auto slot_of = [&](int f, int& b) {
+    auto list_slot = [&](int f, int& b) {
         b = (f >= n0) + (f >= n0 + n1) + (f >= n0 + n1 + n2);
         const int off = b == 0 ? 0 : b == 1 ? n0 : b == 2 ? n0 + n1 : n0 + n1 + n2;
         return b * RQ + (f - off);
@@ -126,8 +126,8 @@ k_rowband_staged(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, i
         const int f2 = f + (int)blockDim.x;
         const bool two = f2 < total;
         int b1, b2;
-        const int s1 = slot_of(f, b1);
-        const int s2 = slot_of(two ? f2 : f, b2);
+        const int s1 = list_slot(f, b1);
+        const int s2 = list_slot(two ? f2 : f, b2);
         const uint32_t e1 = ent[s1], e2 = ent[s2];
         const uint32_t x1 = (uint32_t)(i0 + 4 * (int)(e1 >> 16)) * (uint32_t)L + (e1 & 0xFFFFu);
         const uint32_t x2 = (uint32_t)(i0 + 4 * (int)(e2 >> 16)) * (uint32_t)L + (e2 & 0xFFFFu);
@@ -189,8 +189,8 @@ k_rowband_staged(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, i
     if (my_delta) atomicAdd(&s_delta, my_delta);
     __syncthreads();
     if (tid == 0) {
-        if (s_delta) atomicAdd(delta, (unsigned long long)(long long)s_delta);
-        if (drawn) atomicAdd(drawn, (unsigned long long)total);
+        if (s_delta) atomicAdd(slot_of(delta, (int)blockIdx.x), (unsigned long long)(long long)s_delta);
+        if (drawn) atomicAdd(slot_of(drawn, (int)blockIdx.x), (unsigned long long)total);
     }
 }
 

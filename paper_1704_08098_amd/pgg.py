@@ -21,20 +21,23 @@ LIB_PATH = os.path.join(_PKG, "libpgg.so")
 PGG_OK, PGG_E_INVAL, PGG_E_NOMEM, PGG_E_DEVICE, PGG_E_STATE = 0, -1, -2, -3, -4
 LAYOUT_INT8, LAYOUT_BITS = 0, 1
 KERNEL_AUTO, KERNEL_COLOUR, KERNEL_ROWBAND, KERNEL_ROWBAND_COMPACT, KERNEL_ROWBAND_STAGED = 0, 1, 2, 3, 4
+KERNEL_STRIP, KERNEL_SEGMENT = 5, 6
 LAYOUTS = {"int8": LAYOUT_INT8, "bits": LAYOUT_BITS}
 KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBAND,
-           "rowband_compact": KERNEL_ROWBAND_COMPACT, "rowband_staged": KERNEL_ROWBAND_STAGED}
+           "rowband_compact": KERNEL_ROWBAND_COMPACT, "rowband_staged": KERNEL_ROWBAND_STAGED,
+           "strip": KERNEL_STRIP, "segment": KERNEL_SEGMENT}
 
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
-           "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_destroy", "pgg_last_error")
+           "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_set_strip_wait", "pgg_destroy",
+           "pgg_last_error")
 
 
 class PggParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("r", ctypes.c_double), ("K", ctypes.c_double),
                 ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
-                ("kernel", ctypes.c_uint32)]
+                ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
 
 
 class PggError(RuntimeError):
@@ -68,6 +71,7 @@ def load():
         "pgg_threshold_table": (ctypes.c_int, [vp, u32p]),
         "pgg_set_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "pgg_kernel_timing": (ctypes.c_int, [vp, u64p, P(ctypes.c_double), u64p]),
+        "pgg_set_strip_wait": (ctypes.c_int, [vp, ctypes.c_double]),
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
     }
@@ -84,10 +88,10 @@ def _check(status):
         raise PggError(status, load().pgg_last_error().decode())
 
 
-def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto") -> PggParams:
+def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto", tile=0) -> PggParams:
     return PggParams(int(L), float(r), float(K), float(p0), int(seed) & (2**64 - 1),
                      LAYOUTS[layout] if isinstance(layout, str) else int(layout),
-                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel))
+                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(tile))
 
 
 def pgg_device_bytes(params: PggParams) -> int:
@@ -169,6 +173,10 @@ def pgg_kernel_timing(handle):
     return n.value, ms.value, drawn.value
 
 
+def pgg_set_strip_wait(handle, seconds: float) -> None:
+    _check(load().pgg_set_strip_wait(handle, float(seconds)))
+
+
 def pgg_destroy(handle) -> None:
     if handle:
         load().pgg_destroy(handle)
@@ -178,8 +186,8 @@ class Sim:
     """One lattice on the GPU.  Mirrors the C calls one to one."""
 
     def __init__(self, L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto",
-                 dev_buf=None, stream=None):
-        self.params = make_params(L, r, K, p0, seed, layout, kernel)
+                 dev_buf=None, stream=None, tile=0):
+        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile)
         self.L = int(L)
         self._buf = dev_buf  # keep a caller tensor alive as long as the handle
         self.handle = pgg_init(self.params, dev_buf, stream)
@@ -211,6 +219,9 @@ class Sim:
 
     def kernel_timing(self):
         return pgg_kernel_timing(self.handle)
+
+    def set_strip_wait(self, seconds):
+        pgg_set_strip_wait(self.handle, seconds)
 
     def close(self):
         if self.handle:

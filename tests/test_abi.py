@@ -34,8 +34,8 @@ def test_every_declared_symbol_is_exported(pgg):
 
 
 def test_params_struct_layout(pgg):
-    # uint32 L; double r, K, p0; uint64 seed; uint32 layout, kernel
-    assert ctypes.sizeof(pgg.PggParams) == 48
+    # uint32 L; double r, K, p0; uint64 seed; uint32 layout, kernel, tile
+    assert ctypes.sizeof(pgg.PggParams) == 56
     assert pgg.PggParams.seed.offset == 32
 
 
@@ -53,7 +53,14 @@ def test_device_bytes(pgg):
                                 dict(layout="int8", kernel="rowband"),
                                 dict(layout="bits", kernel="colour"), dict(kernel=9),
                                 dict(L=32768, kernel="rowband_staged"),
-                                dict(layout="int8", kernel="rowband_staged")])
+                                dict(layout="int8", kernel="rowband_staged"),
+                                dict(layout="int8", kernel="strip"),
+                                dict(L=32768, kernel="strip"),
+                                dict(kernel="strip", tile=2),
+                                dict(kernel="strip", tile=101),
+                                dict(kernel="rowband", tile=26),
+                                dict(L=60, kernel="segment"), dict(kernel="segment", tile=48),
+                                dict(kernel="segment", tile=96), dict(layout="int8", kernel="segment")])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")
     args.update(kw)

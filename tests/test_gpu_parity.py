@@ -13,11 +13,24 @@ from paper_1704_08098_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [("int8", "colour"), ("bits", "rowband"), ("bits", "rowband_compact"),
-            ("bits", "rowband_staged")]
+            ("bits", "rowband_staged"), ("bits", "strip"), ("bits", "segment")]
 
 
 def say(*a):
     print(*a, flush=True)
+
+
+MIN_L = {"segment": 64}
+
+
+def open_sim(pgg, L, r, K, p0, seed, layout, kernel, **kw):
+    """The Sim, or None after checking that an unsupported size is refused."""
+    if L < MIN_L.get(kernel, 4):
+        with pytest.raises(pgg.PggError) as e:
+            pgg.Sim(L, r, K, p0, seed, layout, kernel, **kw)
+        assert e.value.status == pgg.PGG_E_INVAL
+        return None
+    return pgg.Sim(L, r, K, p0, seed, layout, kernel, **kw)
 
 
 @pytest.fixture(scope="module")
@@ -106,7 +119,10 @@ def test_ragged_and_tiny_lattices(pgg, oracle_lib, layout, kernel, L, r, K, seed
     n = 24
     say("ragged", layout, kernel, "L", L, "r", r, "K", K, "seed", seed)
     s0, _ = oracle_lib.init(L, 0.5, seed)
-    with pgg.Sim(L, r, K, 0.5, seed, layout, kernel) as sim:
+    sim = open_sim(pgg, L, r, K, 0.5, seed, layout, kernel)
+    if sim is None:
+        return
+    with sim:
         ref = s0
         for t in range(n):
             ref, c = oracle_lib.sweep(ref, r, K, seed, t, 1)
@@ -137,7 +153,10 @@ def test_sweep_index_near_2_pow_32(pgg, oracle_lib, layout, kernel):
     t0 = 2**32 - 3
     ref, counts = oracle_lib.sweep(lat, r, 0.5, seed, t0, 3)
     say("t near 2^32", layout, kernel)
-    with pgg.Sim(L, r, 0.5, 0.5, seed, layout, kernel) as sim:
+    sim = open_sim(pgg, L, r, 0.5, 0.5, seed, layout, kernel)
+    if sim is None:
+        return
+    with sim:
         sim.write_lattice(lat, t0)
         assert np.array_equal(sim.sweep(3), counts)
         assert np.array_equal(sim.read_lattice(), ref)
@@ -249,3 +268,51 @@ def test_maximum_size_kernels_agree(pgg):
     assert np.array_equal(counts[0], counts[1])
     pop = int(np.bitwise_count(bufs[0].cpu().numpy()).sum(dtype=np.uint64))
     assert pop == int(counts[0][-1])
+
+
+@pytest.mark.parametrize("kernel,tile", [("strip", 4), ("strip", 5), ("strip", 7), ("strip", 13),
+                                         ("strip", 68), ("rowband", 1), ("rowband", 3),
+                                         ("rowband_compact", 2), ("rowband_staged", 4),
+                                         ("segment", 32)])
+def test_tile_do_not_change_results(pgg, oracle_lib, kernel, tile):
+    """Strip heights / rows per band, including a single strip (H = L)."""
+    L, r, seed, n = 68, 3.85, 31, 16
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say("tile", kernel, tile)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", kernel, tile=tile) as sim:
+        got = np.concatenate([sim.sweep(5), sim.sweep(11)])
+        assert np.array_equal(got, counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_strip_abort_path_reports_and_recovers(pgg, oracle_lib):
+    """A zero wait bound makes strip workgroups give up on their neighbours:
+    every workgroup exits, the call reports PGG_E_DEVICE and the handle is
+    poisoned; a fresh handle afterwards computes correctly."""
+    L, r, seed = 1024, 3.8, 3
+    say("strip abort path")
+    sim = pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "strip", tile=4)
+    sim.set_strip_wait(0.0)
+    with pytest.raises(pgg.PggError) as e:
+        sim.sweep(50)  # counts requested: synchronises and checks the flag
+    assert e.value.status == pgg.PGG_E_DEVICE
+    with pytest.raises(pgg.PggError) as e2:
+        sim.sweep(1)
+    assert e2.value.status == pgg.PGG_E_STATE
+    sim.close()
+    ref, nc0, counts = oracle_lib.run(100, r, 0.5, 0.5, seed, 10)
+    with pgg.Sim(100, r, 0.5, 0.5, seed, "bits", "strip") as ok:
+        assert np.array_equal(ok.sweep(10), counts)
+        assert np.array_equal(ok.read_lattice(), ref)
+
+
+@pytest.mark.parametrize("L,segw", [(64, 32), (100, 32), (100, 64), (132, 96), (196, 64), (260, 224),
+                                    (512, 128), (512, 480), (1024, 992)])
+def test_segment_widths(pgg, oracle_lib, L, segw):
+    """Segment widths from 32 columns to L - 32, including a short last segment."""
+    r, seed, n = 3.9, 40 + L, 12
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say("segment", L, segw)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=segw) as sim:
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
