@@ -204,6 +204,49 @@ pgg_status pgg_set_strip_wait(pgg_sim* s, double seconds);
  * caller-supplied dev_buf.  NULL is a no-op.  Synchronises the stream. */
 void pgg_destroy(pgg_sim* s);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent lattices (replicas) of uneven L, r
+ * and seed -- the ensembles the absorbing-phase-transition analysis of
+ * Sec. V averages over -- advanced together.  Every launch covers one row
+ * residue of one sweep of every replica (the segment kernel's work split,
+ * replica by replica), and a chunk of sweeps is captured once in a hipGraph
+ * and replayed.  Each replica's lattice and counts are exactly those of a
+ * pgg_init / pgg_sweep run with the same parameters.
+ * ------------------------------------------------------------------------ */
+typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
+
+/* Create n_reps replicas and draw their initial states (t = 0).
+ *   reps       host array of n_reps parameter sets: 64 <= L <= 32768, L % 4
+ *              == 0, layout BITS, kernel AUTO or SEGMENT; copied.
+ *   tiles      host array of n_reps segment widths (multiple of 32,
+ *              <= L - 32; 0 = automatic) or NULL for all automatic.
+ *   chunk      sweeps per graph replay, 1..1024 (device counters hold
+ *              chunk x n_reps x 4 KiB).
+ *   hip_stream stream to order the work on; NULL: the ensemble creates and
+ *              owns a stream of default priority (graphs cannot capture the
+ *              null stream).
+ * Synchronises the stream once. */
+pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles,
+                               uint32_t chunk, void* hip_stream, pgg_ensemble** out);
+
+/* Advance every replica n_sweeps sweeps.  counts: NULL, or host array of
+ * n_reps rows of n_sweeps entries receiving N_C after each sweep (row k is
+ * replica k).  Synchronises once per chunk when counts != NULL. */
+pgg_status pgg_ensemble_sweep(pgg_ensemble* e, uint32_t n_sweeps, uint64_t* counts);
+
+/* N_C(t) of every replica into host n_c[n_reps].  Synchronises. */
+pgg_status pgg_ensemble_coop_counts(pgg_ensemble* e, uint64_t* n_c);
+
+/* The common sweep index t of the replicas.  Host only. */
+pgg_status pgg_ensemble_sweep_index(const pgg_ensemble* e, uint64_t* t);
+
+/* Lattice of replica rep into host_LxL (L*L bytes, row-major 0/1).
+ * Synchronises. */
+pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* host_LxL);
+
+/* Release every buffer, graph and owned stream.  NULL is a no-op. */
+void pgg_ensemble_destroy(pgg_ensemble* e);
+
 /* Thread-local, NUL-terminated description of the last error on this thread
  * ("" if none).  Valid until the next call on this thread. */
 const char* pgg_last_error(void);

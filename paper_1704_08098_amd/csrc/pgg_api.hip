@@ -27,6 +27,15 @@ constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 
 }  // namespace
 
+namespace pgg {
+void set_errorf(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+}  // namespace pgg
+
 struct pgg_sim {
     pgg_params p;
     hipStream_t stream = nullptr;

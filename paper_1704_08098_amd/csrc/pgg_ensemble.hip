@@ -1,0 +1,412 @@
+// Batched ensemble: many independent lattices (replicas of uneven L, r and
+// seed) advanced together.  Every launch covers one row residue of one sweep
+// of every replica: the waves of the launch are dealt out replica by replica
+// (each replica's waves padded to whole workgroups, so a workgroup serves one
+// replica and shares its threshold table), and each wave runs the segment
+// update of one row segment.  A chunk of sweeps -- zeroing the per-sweep
+// counters, 4 launches per sweep, the per-replica count scan and the advance
+// of every replica's sweep index -- is captured once in a hipGraph and
+// replayed; the sweep index lives in device memory so the same graph serves
+// every chunk.  Results are those of the replicas run one by one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "pgg.h"
+#include "pgg_internal.hpp"
+#include "pgg_segment.hpp"
+
+namespace pgg {
+
+constexpr int kWavesPerGroup = kSegmentThreads / 64;
+
+// Replica whose wave range holds wave w: the last replica with wave_base <= w.
+__device__ __forceinline__ int replica_of_wave(const EnsRep* __restrict__ reps, int n, int w) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reps[mid].wave_base <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kSegmentThreads)
+k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
+    extern __shared__ uint32_t smem[];
+    __shared__ int s_part[kWavesPerGroup];
+    __shared__ int s_rep;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int first_wave = blockIdx.x * kWavesPerGroup;
+    if (threadIdx.x == 0) s_rep = replica_of_wave(reps, n_reps, first_wave);
+    __syncthreads();
+    const EnsRep rp = reps[s_rep];
+    uint32_t* sT = smem;
+    uint32_t* win = smem + 160 + wid * seg_wave_words(rp.segw);
+    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    __syncthreads();
+
+    const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica
+    int my_delta = 0, my_drawn = 0;
+    if (q < rp.n_active && lw < (rp.L >> 2) * rp.nseg) {
+        const int ri = lw / rp.nseg, sg = lw - (lw / rp.nseg) * rp.nseg;
+        segment_wave(rp.lat, rp.L, rp.stride, rp.nw, a, rp.segw, ri, sg, rp.t0 + (uint32_t)q, rp.k0, rp.k1,
+                     sT, win, my_delta, my_drawn);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
+    if (lane == 0) s_part[wid] = my_delta;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int dsum = 0;
+        for (int k = 0; k < kWavesPerGroup; ++k) dsum += s_part[k];
+        if (dsum)
+            atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
+                      (unsigned long long)(long long)dsum);
+    }
+}
+
+// Fermi tables, one block per replica (same arithmetic as k_build_table).
+__global__ void k_ens_tables(const EnsRep* __restrict__ reps, const double* __restrict__ rK) {
+#pragma clang fp contract(off)
+    const EnsRep& rp = reps[blockIdx.x];
+    const double r = rK[2 * blockIdx.x], K = rK[2 * blockIdx.x + 1];
+    const int idx = threadIdx.x;
+    if (idx >= kTableSize) return;
+    const int dsig = idx / 3 - 25;
+    const int ds = idx % 3 - 1;
+    const double dpi = (r * (double)dsig) / 5.0 - 5.0 * (double)ds;
+    const double w = 1.0 / (1.0 + exp(dpi / K));
+    const double scaled = floor(w * 4294967296.0 + 0.5);
+    ((uint32_t*)rp.T)[idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)scaled;
+}
+
+// Per replica: counts[rep][q] = nc[rep] + prefix over q of the sweep deltas
+// (q < n_active), then nc[rep] advances.  One block per replica.
+__global__ void __launch_bounds__(256)
+k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restrict__ counts,
+           unsigned long long* __restrict__ nc) {
+    __shared__ unsigned long long part[256];
+    const EnsRep& rp = reps[blockIdx.x];
+    const int n = min(rp.n_active, K);
+    const int tid = threadIdx.x;
+    const int chunk = (n + 255) / 256;
+    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+    auto sweep_delta = [&](int q) {
+        unsigned long long v = 0;
+        const unsigned long long* row = rp.delta + (size_t)q * kSweepWords;
+        for (int k = 0; k < kSlots; ++k) v += row[k * kSlotStride];
+        return v;
+    };
+    unsigned long long sum = 0;
+    for (int q = lo; q < hi; ++q) sum += sweep_delta(q);
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned long long v = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    unsigned long long run = nc[blockIdx.x] + (tid ? part[tid - 1] : 0ull);
+    for (int q = lo; q < hi; ++q) {
+        run += sweep_delta(q);
+        counts[(size_t)blockIdx.x * K + q] = run;
+    }
+    __syncthreads();
+    if (tid == 255) nc[blockIdx.x] += part[255];
+}
+
+// Sweep bookkeeping of every replica: n_active for the next chunk, or the
+// advance of t0 after it.
+__global__ void k_ens_set_active(EnsRep* __restrict__ reps, int n_reps, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_reps) reps[k].n_active = n;
+}
+
+__global__ void k_ens_advance(EnsRep* __restrict__ reps, int n_reps) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_reps) reps[k].t0 += (uint32_t)reps[k].n_active;
+}
+
+}  // namespace pgg
+
+// ---------------------------------------------------------------------------
+// Host engine behind the pgg_ensemble_* calls.
+// ---------------------------------------------------------------------------
+#define eerr pgg::set_errorf
+
+struct pgg_ensemble {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;  // graphs cannot capture the null stream
+    int device = 0;
+    int n = 0;
+    int chunk = 32;          // sweeps per graph replay
+    int total_waves = 0;
+    size_t lds = 0;
+    std::vector<pgg::EnsRep> host_reps;
+    pgg::EnsRep* d_reps = nullptr;
+    uint32_t* d_lattices = nullptr;
+    uint32_t* d_tables = nullptr;
+    unsigned long long* d_delta = nullptr;   // n * chunk * kSweepWords
+    unsigned long long* d_counts = nullptr;  // n * chunk
+    unsigned long long* d_nc = nullptr;      // n
+    std::map<int, hipGraphExec_t> graphs;    // by chunk length
+    std::vector<hipGraph_t> graph_defs;
+    uint64_t t = 0;
+    bool poisoned = false;
+};
+
+namespace {
+
+pgg_status efail(pgg_ensemble* e, hipError_t err, const char* what) {
+    eerr("%s: %s", what, hipGetErrorString(err));
+    if (e) e->poisoned = true;
+    return PGG_E_DEVICE;
+}
+
+#define ENS_HIP(e, call)                                            \
+    do {                                                            \
+        hipError_t err_ = (call);                                   \
+        if (err_ != hipSuccess) return efail((e), err_, #call);     \
+    } while (0)
+
+void ens_release(pgg_ensemble* e) {
+    if (!e) return;
+    (void)hipStreamSynchronize(e->stream);
+    for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : e->graph_defs) (void)hipGraphDestroy(g);
+    if (e->d_reps) (void)hipFree(e->d_reps);
+    if (e->d_lattices) (void)hipFree(e->d_lattices);
+    if (e->d_tables) (void)hipFree(e->d_tables);
+    if (e->d_delta) (void)hipFree(e->d_delta);
+    if (e->d_counts) (void)hipFree(e->d_counts);
+    if (e->d_nc) (void)hipFree(e->d_nc);
+    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+// Enqueue one chunk of len sweeps for every replica on the stream.
+hipError_t enqueue_chunk(pgg_ensemble* e, int len) {
+    hipError_t err;
+    const int nb = (e->n + 255) / 256;
+    hipLaunchKernelGGL(pgg::k_ens_set_active, dim3(nb), dim3(256), 0, e->stream, e->d_reps, e->n, len);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    err = pgg::launch_fill_u64(e->d_delta, (int64_t)e->n * e->chunk * pgg::kSweepWords, 0ull, e->stream);
+    if (err != hipSuccess) return err;
+    const int blocks = e->total_waves / pgg::kWavesPerGroup;
+    for (int q = 0; q < len; ++q) {
+        for (int a = 0; a < 4; ++a) {
+            hipLaunchKernelGGL(pgg::k_ens_segment, dim3(blocks), dim3(pgg::kSegmentThreads), e->lds, e->stream,
+                               e->d_reps, e->n, a, q);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+    }
+    hipLaunchKernelGGL(pgg::k_ens_scan, dim3(e->n), dim3(256), 0, e->stream, e->d_reps, e->chunk, e->d_counts,
+                       e->d_nc);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(pgg::k_ens_advance, dim3(nb), dim3(256), 0, e->stream, e->d_reps, e->n);
+    return hipGetLastError();
+}
+
+hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
+    auto it = e->graphs.find(len);
+    if (it != e->graphs.end()) { *out = it->second; return hipSuccess; }
+    hipGraph_t g = nullptr;
+    hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return err;
+    hipError_t enq = enqueue_chunk(e, len);
+    err = hipStreamEndCapture(e->stream, &g);
+    if (enq != hipSuccess) { if (g) (void)hipGraphDestroy(g); return enq; }
+    if (err != hipSuccess) return err;
+    hipGraphExec_t ex = nullptr;
+    err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) { (void)hipGraphDestroy(g); return err; }
+    e->graph_defs.push_back(g);
+    e->graphs[len] = ex;
+    *out = ex;
+    return hipSuccess;
+}
+
+int ens_segw(uint32_t L) {
+    // Columns per segment: at least 64 and at most L - 32, about L / 8.
+    int w = (int)(L / 8) & ~31;
+    if (w < 64) w = 64;
+    const int cap = ((int)L - 32) & ~31;
+    if (w > cap) w = cap;
+    if (w < 32) w = 32;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk,
+                               void* hip_stream, pgg_ensemble** out) {
+    if (!out) { eerr("out is NULL"); return PGG_E_INVAL; }
+    *out = nullptr;
+    if (!reps || n_reps == 0 || n_reps > 65536) { eerr("need 1..65536 replicas"); return PGG_E_INVAL; }
+    if (chunk == 0 || chunk > 1024) { eerr("chunk must lie in [1, 1024]"); return PGG_E_INVAL; }
+    for (uint32_t k = 0; k < n_reps; ++k) {
+        const pgg_params& p = reps[k];
+        if (p.L < 64 || p.L > 32768 || p.L % 4 != 0) { eerr("replica %u: L must be a multiple of 4 in [64, 32768]", k); return PGG_E_INVAL; }
+        if (!std::isfinite(p.r) || p.r < 0.0) { eerr("replica %u: r must be finite and >= 0", k); return PGG_E_INVAL; }
+        if (!std::isfinite(p.K) || !(p.K > 0.0)) { eerr("replica %u: K must be finite and > 0", k); return PGG_E_INVAL; }
+        if (!(p.p0 >= 0.0 && p.p0 <= 1.0)) { eerr("replica %u: p0 must lie in [0, 1]", k); return PGG_E_INVAL; }
+        if (p.layout != PGG_LAYOUT_BITS) { eerr("replica %u: ensembles use the bits layout", k); return PGG_E_INVAL; }
+        if (p.kernel != PGG_KERNEL_AUTO && p.kernel != PGG_KERNEL_SEGMENT) { eerr("replica %u: ensembles use the segment kernel", k); return PGG_E_INVAL; }
+        const uint32_t w = tiles ? tiles[k] : 0;
+        if (w != 0 && (w % 32 != 0 || w + 32 > p.L)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32", k); return PGG_E_INVAL; }
+    }
+    pgg_ensemble* e = new (std::nothrow) pgg_ensemble();
+    if (!e) { eerr("host allocation failed"); return PGG_E_NOMEM; }
+    e->stream = (hipStream_t)hip_stream;
+    if (!e->stream) {
+        if (hipStreamCreate(&e->stream) != hipSuccess) { eerr("stream creation failed"); delete e; return PGG_E_DEVICE; }
+        e->own_stream = true;
+    }
+    e->n = (int)n_reps;
+    e->chunk = (int)chunk;
+    if (hipGetDevice(&e->device) != hipSuccess) { eerr("no HIP device"); ens_release(e); return PGG_E_DEVICE; }
+
+    // Layout: lattices back to back (256-byte aligned), tables, per-replica waves.
+    std::vector<size_t> lat_off(n_reps);
+    size_t lat_words = 0;
+    int max_segw = 0;
+    e->host_reps.resize(n_reps);
+    int waves = 0;
+    for (uint32_t k = 0; k < n_reps; ++k) {
+        const pgg_params& p = reps[k];
+        pgg::EnsRep& rp = e->host_reps[k];
+        std::memset(&rp, 0, sizeof(rp));
+        rp.L = (int)p.L;
+        rp.stride = 2 * (int)((p.L + 63) / 64);
+        rp.nw = (int)((p.L + 31) / 32);
+        rp.segw = tiles && tiles[k] ? (int)tiles[k] : ens_segw(p.L);
+        rp.nseg = (rp.L + rp.segw - 1) / rp.segw;
+        rp.k0 = (uint32_t)p.seed;
+        rp.k1 = (uint32_t)(p.seed >> 32);
+        rp.t0 = 0;
+        rp.wave_base = waves;
+        const int wv = (rp.L / 4) * rp.nseg;
+        waves += (wv + pgg::kWavesPerGroup - 1) / pgg::kWavesPerGroup * pgg::kWavesPerGroup;
+        lat_off[k] = lat_words;
+        lat_words += ((size_t)rp.L * rp.stride + 63) & ~(size_t)63;
+        max_segw = std::max(max_segw, rp.segw);
+    }
+    e->total_waves = waves;
+    e->lds = (160 + (size_t)pgg::kWavesPerGroup * pgg::seg_wave_words(max_segw)) * sizeof(uint32_t);
+
+    auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
+        hipError_t err = hipMalloc(ptr, bytes);
+        if (err != hipSuccess) {
+            eerr("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(err));
+            return err == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
+        }
+        return PGG_OK;
+    };
+    pgg_status st = alloc((void**)&e->d_lattices, lat_words * sizeof(uint32_t));
+    if (st == PGG_OK) st = alloc((void**)&e->d_tables, (size_t)n_reps * 160 * sizeof(uint32_t));
+    if (st == PGG_OK) st = alloc((void**)&e->d_delta, (size_t)n_reps * chunk * pgg::kSweepWords * sizeof(unsigned long long));
+    if (st == PGG_OK) st = alloc((void**)&e->d_counts, (size_t)n_reps * chunk * sizeof(unsigned long long));
+    if (st == PGG_OK) st = alloc((void**)&e->d_nc, (size_t)n_reps * sizeof(unsigned long long));
+    if (st == PGG_OK) st = alloc((void**)&e->d_reps, (size_t)n_reps * sizeof(pgg::EnsRep));
+    if (st != PGG_OK) { ens_release(e); return st; }
+    for (uint32_t k = 0; k < n_reps; ++k) {
+        pgg::EnsRep& rp = e->host_reps[k];
+        rp.lat = e->d_lattices + lat_off[k];
+        rp.T = e->d_tables + (size_t)k * 160;
+        rp.delta = e->d_delta + (size_t)k * chunk * pgg::kSweepWords;
+    }
+    std::vector<double> rK(2 * n_reps);
+    for (uint32_t k = 0; k < n_reps; ++k) { rK[2 * k] = reps[k].r; rK[2 * k + 1] = reps[k].K; }
+    double* d_rK = nullptr;
+    hipError_t err = hipMalloc((void**)&d_rK, rK.size() * sizeof(double));
+    if (err == hipSuccess) err = hipMemcpy(e->d_reps, e->host_reps.data(), n_reps * sizeof(pgg::EnsRep), hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(d_rK, rK.data(), rK.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(pgg::k_ens_tables, dim3(n_reps), dim3(192), 0, e->stream, e->d_reps, d_rK);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = pgg::launch_fill_u64(e->d_nc, n_reps, 0ull, e->stream);
+    for (uint32_t k = 0; k < n_reps && err == hipSuccess; ++k) {
+        const pgg::EnsRep& rp = e->host_reps[k];
+        err = pgg::launch_init(PGG_LAYOUT_BITS, rp.lat, rp.L, rp.stride, reps[k].p0, reps[k].seed, e->d_nc + k, e->stream);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (d_rK) (void)hipFree(d_rK);
+    if (err != hipSuccess) {
+        eerr("ensemble initialisation failed: %s", hipGetErrorString(err));
+        ens_release(e);
+        return PGG_E_DEVICE;
+    }
+    *out = e;
+    return PGG_OK;
+}
+
+pgg_status pgg_ensemble_sweep(pgg_ensemble* e, uint32_t n_sweeps, uint64_t* counts) {
+    if (!e) { eerr("ensemble is NULL"); return PGG_E_INVAL; }
+    if (e->poisoned) { eerr("ensemble poisoned by an earlier device error"); return PGG_E_STATE; }
+    if (e->t + (uint64_t)n_sweeps > 4294967296ull) { eerr("sweep index would exceed 2^32"); return PGG_E_INVAL; }
+    if (n_sweeps == 0) return PGG_OK;
+    uint32_t done = 0;
+    while (done < n_sweeps) {
+        const int len = (int)std::min<uint32_t>((uint32_t)e->chunk, n_sweeps - done);
+        hipGraphExec_t g = nullptr;
+        ENS_HIP(e, graph_for(e, len, &g));
+        ENS_HIP(e, hipGraphLaunch(g, e->stream));
+        if (counts) {
+            // counts is n_reps rows of n_sweeps; this chunk fills columns done .. done + len.
+            ENS_HIP(e, hipMemcpy2DAsync(counts + done, (size_t)n_sweeps * sizeof(uint64_t), e->d_counts,
+                                        (size_t)e->chunk * sizeof(unsigned long long), (size_t)len * sizeof(uint64_t),
+                                        (size_t)e->n, hipMemcpyDeviceToHost, e->stream));
+            ENS_HIP(e, hipStreamSynchronize(e->stream));
+        }
+        done += (uint32_t)len;
+    }
+    e->t += n_sweeps;
+    return PGG_OK;
+}
+
+pgg_status pgg_ensemble_coop_counts(pgg_ensemble* e, uint64_t* n_c) {
+    if (!e || !n_c) { eerr("NULL argument"); return PGG_E_INVAL; }
+    if (e->poisoned) { eerr("ensemble poisoned by an earlier device error"); return PGG_E_STATE; }
+    ENS_HIP(e, hipMemcpyAsync(n_c, e->d_nc, (size_t)e->n * sizeof(uint64_t), hipMemcpyDeviceToHost, e->stream));
+    ENS_HIP(e, hipStreamSynchronize(e->stream));
+    return PGG_OK;
+}
+
+pgg_status pgg_ensemble_sweep_index(const pgg_ensemble* e, uint64_t* t) {
+    if (!e || !t) { eerr("NULL argument"); return PGG_E_INVAL; }
+    *t = e->t;
+    return PGG_OK;
+}
+
+pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* host_LxL) {
+    if (!e || !host_LxL) { eerr("NULL argument"); return PGG_E_INVAL; }
+    if (rep >= (uint32_t)e->n) { eerr("replica %u out of range", rep); return PGG_E_INVAL; }
+    if (e->poisoned) { eerr("ensemble poisoned by an earlier device error"); return PGG_E_STATE; }
+    const pgg::EnsRep& rp = e->host_reps[rep];
+    const size_t n = (size_t)rp.L * rp.L;
+    uint8_t* tmp = nullptr;
+    hipError_t err = hipMalloc((void**)&tmp, n);
+    if (err != hipSuccess) { eerr("staging allocation failed: %s", hipGetErrorString(err)); return PGG_E_NOMEM; }
+    err = pgg::launch_unpack(rp.lat, tmp, rp.L, rp.stride, e->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(host_LxL, tmp, n, hipMemcpyDeviceToHost, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    (void)hipFree(tmp);
+    if (err != hipSuccess) return efail(e, err, "ensemble read_lattice");
+    return PGG_OK;
+}
+
+void pgg_ensemble_destroy(pgg_ensemble* e) { ens_release(e); }
+
+}  // extern "C"

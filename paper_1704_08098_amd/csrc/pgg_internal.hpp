@@ -82,4 +82,19 @@ hipError_t launch_segment_residue(uint32_t* lat, int L, int stride, int segw, in
                                   unsigned long long* drawn, hipStream_t st);
 size_t segment_lds_bytes(int segw);
 
+// Ensemble replica descriptor (pgg_ensemble.hip): replica lattice, its
+// threshold table, its per-sweep counters (chunk x kSweepWords), geometry,
+// the first wave of its range in a launch, the number of sweeps of the
+// current chunk, Philox key and current sweep index.
+struct EnsRep {
+    uint32_t* lat;
+    const uint32_t* T;
+    unsigned long long* delta;
+    int L, stride, nw, segw, nseg, wave_base, n_active;
+    uint32_t k0, k1, t0;
+};
+
+// Sets the calling thread's pgg_last_error() text (printf-style).
+void set_errorf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
 }  // namespace pgg

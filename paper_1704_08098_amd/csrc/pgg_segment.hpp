@@ -1,0 +1,171 @@
+// One wave's share of the segment sweep (see pgg_segment.hip): row i of
+// residue a, columns [s, e), the four colour classes 4a..4a+3 of sweep t.
+// Shared by the single-lattice and the ensemble kernels.  gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pgg_device.hpp"
+#include "pgg_internal.hpp"
+
+namespace pgg {
+
+namespace seg {
+
+// 32 sites of a bit-packed row in global memory, columns c .. c + 31 taken
+// modulo L (c any int >= -2L), column c in bit 0.  Reads only words < nw.
+__device__ __forceinline__ uint32_t global_window(const uint32_t* __restrict__ row, int L, int nw, int c) {
+    while (c < 0) c += L;
+    while (c >= L) c -= L;
+    if (c + 32 <= L) {
+        const int w = c >> 5, sh = c & 31;
+        const uint32_t lo = row[w];
+        const uint32_t hi = sh ? row[w + 1] : 0u;  // c + 31 < L, so w + 1 < nw when sh > 0
+        return funnel(hi, lo, sh);
+    }
+    uint32_t out = 0;
+    int got = 0;
+    while (got < 32) {
+        const int take = min(32 - got, L - c);
+        const int w = c >> 5, sh = c & 31;
+        const uint32_t lo = row[w];
+        const uint32_t hi = (sh && w + 1 < nw) ? row[w + 1] : 0u;
+        uint32_t piece = funnel(hi, lo, sh);
+        if (take < 32) piece &= (1u << take) - 1u;
+        out |= piece << got;
+        got += take;
+        c = 0;
+    }
+    return out;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+}  // namespace seg
+
+// Window words per row and list capacity per class for a segment width.
+__host__ __device__ constexpr int seg_window_words(int segw) { return segw / 32 + 4; }
+__host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 8; }
+__host__ __device__ constexpr int seg_wave_words(int segw) { return 7 * seg_window_words(segw) + seg_list_cap(segw); }
+
+// win: the wave's LDS area of seg_wave_words(segw) words; sT: the threshold
+// table in LDS.  Adds the net change of the cooperator count over the owned
+// columns to my_delta (every lane) and the number of draws to my_drawn
+// (lane 0).
+__device__ __forceinline__ void segment_wave(uint32_t* __restrict__ lat, int L, int stride, int nw, int a,
+                                             int segw, int ri, int sg, uint32_t t, uint32_t k0, uint32_t k1,
+                                             const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
+                                             int& my_delta, int& my_drawn) {
+    using namespace seg;
+    const int lane = threadIdx.x & 63;
+    const int WB = seg_window_words(segw);
+    uint32_t* list = win + 7 * WB;
+    const int i = a + 4 * ri;
+    const int s = sg * segw;
+    const int e = min(L, s + segw);
+    const int c0 = s - 64;                   // column of window bit 0
+
+    // Load the 7 rows' windows (columns c0 .. c0 + 32 WB - 1, periodic).
+    for (int q = lane; q < 7 * WB; q += 64) {
+        const int o = q / WB, w = q - (q / WB) * WB;
+        int gi = i - 3 + o;
+        gi += (gi < 0) ? L : 0;
+        gi -= (gi >= L) ? L : 0;
+        win[q] = global_window(lat + (size_t)gi * stride, L, nw, c0 + 32 * w);
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    uint32_t* r0 = win + 3 * WB;  // the row being updated
+    const uint32_t k_first = (uint32_t)(4 * a);
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+        // Class-b sites on window positions [lo, hi).
+        const int m = 9 - 3 * b;
+        const int lo = 64 - m, hi = 64 + (e - s) + m;
+        const int wlo = lo >> 5, whi = (hi + 31) >> 5;
+        // 1. candidates per word, 2. compacted list.
+        int total = 0;
+        for (int wbase = wlo; wbase < whi; wbase += 64) {
+            const int w = wbase + lane;
+            uint32_t act = 0;
+            if (w < whi) {
+                const uint32_t X = r0[w];
+                const uint32_t E = funnel(r0[w + 1], X, 1);
+                const uint32_t Wn = funnel(X, r0[w - 1], 31);
+                act = ((X ^ E) | (X ^ Wn) | (X ^ r0[w - WB]) | (X ^ r0[w + WB])) & (0x11111111u << b);
+                // keep positions in [lo, hi)
+                const int p0 = 32 * w;
+                if (p0 < lo) act &= 0xFFFFFFFFu << (lo - p0);
+                if (p0 + 32 > hi) act &= (hi - p0) >= 32 ? 0xFFFFFFFFu : ((1u << (hi - p0)) - 1u);
+            }
+            const int cnt = __popc(act);
+            const int incl = wave_inclusive_scan(cnt);
+            int pos = total + incl - cnt;
+            while (act) {
+                const int bit = __ffs(act) - 1;
+                act &= act - 1u;
+                list[pos++] = (uint32_t)(32 * w + bit);
+            }
+            total += __shfl(incl, 63, 64);
+        }
+        __builtin_amdgcn_wave_barrier();
+        my_drawn += lane == 0 ? total : 0;
+        // 3. the elementary steps of the listed sites.
+        const uint32_t k = k_first + (uint32_t)b;
+        for (int q = lane; q < total; q += 64) {
+            const int p = (int)list[q];
+            int c = c0 + p;
+            c += (c < 0) ? L : 0;
+            c -= (c >= L) ? L : 0;
+            const uint4 rnd = philox4x32_10(make_uint4((uint32_t)(i * L + c), t, k, 0u), k0, k1);
+            const int d = (int)(rnd.x >> 30);
+            const uint32_t u = rnd.y;
+            const int w = (p - 16) >> 5, sh = (p - 16) & 31;
+            const uint32_t wm3 = funnel(r0[w + 1 - 3 * WB], r0[w - 3 * WB], sh);
+            const uint32_t wm2 = funnel(r0[w + 1 - 2 * WB], r0[w - 2 * WB], sh);
+            const uint32_t wm1 = funnel(r0[w + 1 - WB], r0[w - WB], sh);
+            const uint32_t w00 = funnel(r0[w + 1], r0[w], sh);
+            const uint32_t wp1 = funnel(r0[w + 1 + WB], r0[w + WB], sh);
+            const uint32_t wp2 = funnel(r0[w + 1 + 2 * WB], r0[w + 2 * WB], sh);
+            const uint32_t wp3 = funnel(r0[w + 1 + 3 * WB], r0[w + 3 * WB], sh);
+            const int o = dir_di(d);
+            const int py = 16 + dir_dj(d);
+            const uint32_t y2 = o < 0 ? wm3 : (o > 0 ? wm1 : wm2);
+            const uint32_t y1 = o < 0 ? wm2 : (o > 0 ? w00 : wm1);
+            const uint32_t y0 = o < 0 ? wm1 : (o > 0 ? wp1 : w00);
+            const uint32_t z1 = o < 0 ? w00 : (o > 0 ? wp2 : wp1);
+            const uint32_t z2 = o < 0 ? wp1 : (o > 0 ? wp3 : wp2);
+            const int sx = (int)((w00 >> 16) & 1u);
+            const int sy = (int)((y0 >> py) & 1u);
+            if (sx != sy) {
+                const int dsig = sigma_bits(wm2, wm1, w00, wp1, wp2, 16) - sigma_bits(y2, y1, y0, z1, z2, py);
+                if (u < sT[(dsig + 25) * 3 + (sx - sy + 1)]) {
+                    atomicXor(&r0[p >> 5], 1u << (p & 31));
+                    if (p >= 64 && p < 64 + (e - s)) my_delta += sy ? 1 : -1;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // Write back the owned columns [s, e): window words 2 .. 2 + ceil((e-s)/32).
+    const int nown = (e - s + 31) >> 5;
+    for (int q = lane; q < nown; q += 64) {
+        uint32_t v = r0[2 + q];
+        const int valid = e - (s + 32 * q);
+        if (valid < 32) v &= (1u << valid) - 1u;
+        lat[(size_t)i * stride + (s >> 5) + q] = v;
+    }
+}
+
+}  // namespace pgg

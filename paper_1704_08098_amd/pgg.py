@@ -31,7 +31,8 @@ KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBA
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_set_strip_wait", "pgg_destroy",
-           "pgg_last_error")
+           "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
+           "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy")
 
 
 class PggParams(ctypes.Structure):
@@ -74,6 +75,13 @@ def load():
         "pgg_set_strip_wait": (ctypes.c_int, [vp, ctypes.c_double]),
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
+        "pgg_ensemble_create": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, u32p, ctypes.c_uint32, vp,
+                                               P(vp)]),
+        "pgg_ensemble_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, u64p]),
+        "pgg_ensemble_coop_counts": (ctypes.c_int, [vp, u64p]),
+        "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
+        "pgg_ensemble_read_lattice": (ctypes.c_int, [vp, ctypes.c_uint32, u8p]),
+        "pgg_ensemble_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +234,79 @@ class Sim:
     def close(self):
         if self.handle:
             pgg_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Many replicas advanced together (pgg_ensemble_* calls).
+
+    replicas: sequence of dicts with L, r and optionally K, p0, seed.
+    tiles: optional per-replica segment widths (0 = automatic).
+    """
+
+    def __init__(self, replicas, tiles=None, chunk=32, stream=None):
+        lib = load()
+        n = len(replicas)
+        arr = (PggParams * n)()
+        for k, rp in enumerate(replicas):
+            arr[k] = make_params(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5),
+                                 rp.get("seed", 1), "bits", "auto")
+        self.L = [int(rp["L"]) for rp in replicas]
+        self.n = n
+        tl = None
+        if tiles is not None:
+            tl = np.ascontiguousarray(np.asarray(tiles, dtype=np.uint32))
+            assert tl.shape == (n,)
+        self._tiles = tl
+        h = ctypes.c_void_p()
+        _check(lib.pgg_ensemble_create(arr, n,
+                                       tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None
+                                       else None, int(chunk), _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def sweep(self, n_sweeps, want_counts=True):
+        """Advance every replica; returns counts (n_reps, n_sweeps) or None."""
+        if want_counts:
+            out = np.zeros((self.n, max(n_sweeps, 1)), dtype=np.uint64)
+            _check(load().pgg_ensemble_sweep(self.handle, int(n_sweeps),
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+            return out[:, :n_sweeps]
+        _check(load().pgg_ensemble_sweep(self.handle, int(n_sweeps), None))
+        return None
+
+    def coop_counts(self):
+        out = np.zeros(self.n, dtype=np.uint64)
+        _check(load().pgg_ensemble_coop_counts(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out
+
+    @property
+    def t(self):
+        v = ctypes.c_uint64()
+        _check(load().pgg_ensemble_sweep_index(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def read_lattice(self, k):
+        L = self.L[k]
+        out = np.zeros((L, L), dtype=np.uint8)
+        _check(load().pgg_ensemble_read_lattice(self.handle, int(k),
+                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out
+
+    def close(self):
+        if self.handle:
+            load().pgg_ensemble_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

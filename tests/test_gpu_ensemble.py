@@ -1,0 +1,96 @@
+"""GPU: the batched ensemble equals the replicas run one by one, bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1704_08098_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pgg(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.set_device(0)
+    from paper_1704_08098_amd import pgg as mod
+    mod.load()
+    return mod
+
+
+def _solo(pgg, rp, n):
+    with pgg.Sim(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5), rp["seed"], "bits", "segment") as sim:
+        c = sim.sweep(n)
+        return c, sim.read_lattice()
+
+
+def test_uneven_replicas_equal_solo_runs(pgg, oracle_lib):
+    reps = [dict(L=64, r=3.9, seed=1), dict(L=100, r=4.3, seed=2, p0=0.3), dict(L=128, r=3.75, seed=3),
+            dict(L=196, r=5.1, seed=4, K=0.8), dict(L=256, r=3.62, seed=2**40 + 5), dict(L=68, r=4.0, seed=6)]
+    n, chunk = 45, 8  # 5 full graph replays and a shorter tail chunk
+    say("ensemble of", len(reps), "replicas")
+    with pgg.Ensemble(reps, chunk=chunk) as ens:
+        got = np.concatenate([ens.sweep(20), ens.sweep(0), ens.sweep(25)], axis=1)
+        assert ens.t == n
+        nc = ens.coop_counts()
+        lats = [ens.read_lattice(k) for k in range(len(reps))]
+    for k, rp in enumerate(reps):
+        c, lat = _solo(pgg, rp, n)
+        assert np.array_equal(got[k], c), k
+        assert np.array_equal(lats[k], lat), k
+        assert int(nc[k]) == int(c[-1])
+    # two replicas against the oracle directly
+    for k in (1, 3):
+        rp = reps[k]
+        ref, _, counts = oracle_lib.run(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5), rp["seed"], n)
+        assert np.array_equal(got[k], counts)
+        assert np.array_equal(lats[k], ref)
+
+
+def test_graph_replays_match_eager_runs(pgg):
+    """Every replay of the captured chunk equals the eager single-lattice path."""
+    reps = [dict(L=128, r=3.8, seed=11), dict(L=256, r=3.7, seed=12)]
+    solo = [_solo(pgg, rp, 60)[0] for rp in reps]
+    with pgg.Ensemble(reps, chunk=10) as ens:
+        for rep in range(6):
+            c = ens.sweep(10)
+            for k in range(len(reps)):
+                assert np.array_equal(c[k], solo[k][10 * rep:10 * rep + 10]), (rep, k)
+
+
+@pytest.mark.parametrize("tile", [32, 64, 96, 224])
+def test_tiles_do_not_change_results(pgg, tile):
+    reps = [dict(L=256, r=3.85, seed=21), dict(L=260, r=4.1, seed=22)]
+    ref = [_solo(pgg, rp, 12) for rp in reps]
+    with pgg.Ensemble(reps, tiles=[tile, tile], chunk=5) as ens:
+        c = ens.sweep(12)
+        for k in range(len(reps)):
+            assert np.array_equal(c[k], ref[k][0])
+            assert np.array_equal(ens.read_lattice(k), ref[k][1])
+
+
+def test_full_ensemble_sample(pgg):
+    """The 256-replica ensemble (L = 128..1024), 40 sweeps: sampled replicas
+    equal their solo runs; every count equals a recount of the lattice."""
+    reps = wl.ensemble_replicas()
+    with pgg.Ensemble(reps, chunk=20) as ens:
+        c = ens.sweep(40)
+        for k in (0, 70, 130, 200, 255):
+            sc, sl = _solo(pgg, reps[k], 40)
+            assert np.array_equal(c[k], sc), k
+            lat = ens.read_lattice(k)
+            assert np.array_equal(lat, sl), k
+            assert int(lat.sum()) == int(c[k][-1])
+
+
+def test_invalid_replicas_are_rejected(pgg):
+    for bad in ([dict(L=60, r=3.8, seed=1)], [dict(L=100, r=-1.0, seed=1)], []):
+        with pytest.raises(pgg.PggError) as e:
+            pgg.Ensemble(bad)
+        assert e.value.status == pgg.PGG_E_INVAL
+    with pytest.raises(pgg.PggError):
+        pgg.Ensemble([dict(L=128, r=3.8, seed=1)], tiles=[48])
