@@ -81,6 +81,49 @@ def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, t
     return launches, ms, drawn
 
 
+def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream):
+    """Batched ensemble (all replicas, one graph replay per chunk) vs the same
+    replicas run one lattice at a time (a sample of each size, scaled)."""
+    reps = wl.ensemble_replicas(sweeps=sweeps)
+    total = float(sum(rp["L"] ** 2 for rp in reps)) * sweeps
+    ens = pgg.Ensemble(reps, chunk=chunk, stream=stream)
+    ens.sweep(min(chunk, sweeps), want_counts=False)  # first replay builds the graph
+    torch.cuda.synchronize()
+    ens.close()
+    ens = pgg.Ensemble(reps, chunk=chunk, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.sweep(sweeps, want_counts=False)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    nc = ens.coop_counts()
+    ens.close()
+    by_size = {}
+    for k, rp in enumerate(reps):
+        by_size.setdefault(rp["L"], []).append(k)
+    t_plain = 0.0
+    for L, ks in sorted(by_size.items()):
+        sample = ks[:plain_per_size]
+        ts = []
+        for k in sample:
+            rp = reps[k]
+            sim = pgg.Sim(rp["L"], rp["r"], rp["K"], rp["p0"], rp["seed"], "bits", "auto", stream=stream)
+            sim.sweep(2, want_counts=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.sweep(sweeps - 2, want_counts=False)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * sweeps / (sweeps - 2))
+            sim.close()
+        t_plain += sum(ts) / len(ts) * len(ks)
+    return {"metric": "replica-site updates/s", "value": total / t_batched, "plain_value": total / t_plain,
+            "ratio_vs_plain": t_plain / t_batched, "replicas": len(reps), "sweeps": sweeps,
+            "sizes": sorted(by_size), "chunk": chunk, "batched_s": t_batched, "plain_s_estimated": t_plain,
+            "plain": "each replica alone (pgg_init/pgg_sweep, automatic kernel), %d per size timed, "
+                     "scaled to the %d replicas of each size" % (plain_per_size, len(reps) // len(by_size)),
+            "mean_final_density": float(sum(int(v) / reps[k]["L"] ** 2 for k, v in enumerate(nc)) / len(reps))}
+
+
 def cpu_baseline(L, r, seed, n_sweeps):
     import oracle
     oracle.build(force=False)
@@ -107,6 +150,9 @@ def main():
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ensemble-sweeps", type=int, default=5000, help="0 skips the ensemble pass")
+    ap.add_argument("--ensemble-chunk", type=int, default=50)
+    ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -177,6 +223,11 @@ def main():
            "frac_int8_equivalent": value * 2.0 / 1e9 / HBM_PEAK_GBS,
            "kernel_only_updates_per_s": kernel_rate}
 
+    batched = None
+    if args.ensemble_sweeps > 0:
+        log("ensemble pass: %d sweeps" % args.ensemble_sweeps)
+        batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, %d sweep(s) at L=%d" % (args.cpu_sweeps, L))
@@ -192,7 +243,7 @@ def main():
                                                                  args.warmup + args.steps - 1),
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "parallelism": "single GPU"},
-        "roofline": roofline, "hbm": hbm, "dense": dense, "cpu_baseline": cpu,
+        "roofline": roofline, "hbm": hbm, "dense": dense, "batched": batched, "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }
     print(json.dumps(line), flush=True)

@@ -247,6 +247,73 @@ pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* hos
 /* Release every buffer, graph and owned stream.  NULL is a no-op. */
 void pgg_ensemble_destroy(pgg_ensemble* e);
 
+/* ------------------------------------------------------------------------
+ * Job server: continuous batching of simulation jobs on one GPU.  Jobs are
+ * submitted at any time and queue on the host.  Each pgg_server_step
+ * (1) admits queued jobs in arrival order while their device footprint
+ * (pgg_server_job_bytes) fits the HBM budget, then any later job that still
+ * fits (backfill), drawing their initial states on the device; (2) advances
+ * every resident job by min(chunk, remaining) sweeps in the same launches,
+ * each at its own sweep index; (3) copies the chunk's counts out and retires
+ * finished jobs (final lattice copied out, device space freed).  Lattices
+ * stay resident for a job's whole life.  A job's counts and final lattice
+ * are exactly those of pgg_init + pgg_sweep with the same parameters.
+ * Not thread-safe; one server per thread.
+ * ------------------------------------------------------------------------ */
+typedef struct pgg_server pgg_server;
+
+typedef struct {
+    uint32_t queued;       /* jobs waiting for admission                    */
+    uint32_t resident;     /* jobs on the device                            */
+    uint64_t completed;    /* jobs finished since creation                  */
+    uint64_t bytes_in_use; /* device bytes held by resident jobs            */
+    uint64_t peak_bytes;   /* largest bytes_in_use so far (<= budget)       */
+    uint64_t budget;       /* the HBM budget (rounded down to 256 B)        */
+    uint64_t site_updates; /* L^2 x sweeps completed, over all jobs         */
+} pgg_server_info;
+
+/* Device bytes a job of side L occupies under a server with this chunk:
+ * lattice (bit-packed), threshold table, per-sweep counters, N_C. */
+size_t pgg_server_job_bytes(uint32_t L, uint32_t chunk);
+
+/* Create a server.
+ *   hbm_budget    device bytes for resident jobs (one arena, allocated now);
+ *                 must hold at least the footprint of an L = 64 job.
+ *   max_L         largest L accepted (multiple of 4 in [64, 32768]); sizes a
+ *                 max_L^2-byte read-out buffer allocated outside the budget.
+ *   max_resident  most jobs on the device at once (1..65536).
+ *   chunk         sweeps per step (1..1024).
+ *   hip_stream    stream to order work on; NULL: the server owns one.
+ * Fails with PGG_E_NOMEM if the device cannot hold the arena. */
+pgg_status pgg_server_create(size_t hbm_budget, uint32_t max_L, uint32_t max_resident, uint32_t chunk,
+                             void* hip_stream, pgg_server** out);
+
+/* Queue a job: p (host, copied; 64 <= L <= max_L, layout BITS, kernel AUTO
+ * or SEGMENT) and n_sweeps >= 1.  A job whose footprint exceeds the whole
+ * budget is PGG_E_INVAL.  job_id (host) receives its id.  Host only. */
+pgg_status pgg_server_submit(pgg_server* s, const pgg_params* p, uint32_t n_sweeps, uint64_t* job_id);
+
+/* One step (admit, run one chunk, retire).  n_resident (host, or NULL)
+ * receives the number of jobs that ran in this step.  Synchronises. */
+pgg_status pgg_server_step(pgg_server* s, uint32_t* n_resident);
+
+/* Ids of jobs that finished since the last call (at most cap, oldest
+ * first) into host ids; n receives how many.  Host only. */
+pgg_status pgg_server_completed(pgg_server* s, uint64_t* ids, uint32_t cap, uint32_t* n);
+
+/* State of a job: 0 queued, 1 on the device, 2 finished; sweeps done. */
+pgg_status pgg_server_job_state(pgg_server* s, uint64_t id, int* state, uint32_t* sweeps_done);
+
+/* Results of a finished job: counts (host, n_sweeps entries: N_C after each
+ * sweep) and lattice (host, L*L bytes 0/1), each may be NULL.  Releases the
+ * job's record: a second call is PGG_E_INVAL. */
+pgg_status pgg_server_job_result(pgg_server* s, uint64_t id, uint64_t* counts, uint8_t* lattice);
+
+pgg_status pgg_server_stats(const pgg_server* s, pgg_server_info* st);
+
+/* Release the arena, the buffers and an owned stream.  NULL is a no-op. */
+void pgg_server_destroy(pgg_server* s);
+
 /* Thread-local, NUL-terminated description of the last error on this thread
  * ("" if none).  Valid until the next call on this thread. */
 const char* pgg_last_error(void);

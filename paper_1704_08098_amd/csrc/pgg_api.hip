@@ -42,6 +42,7 @@ struct pgg_sim {
     int device = 0;
     void* lattice = nullptr;
     bool owns_lattice = false;
+    uint32_t* lattice2 = nullptr;  // segment kernel: odd sweeps of a call land here
     int stride = 0;  // bits layout: 32-bit words per row
     int kernel = PGG_KERNEL_COLOUR;
     int R = 1;       // rows per workgroup (row-band kernels)
@@ -183,6 +184,7 @@ void release(pgg_sim* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     if (s->owns_lattice && s->lattice) (void)hipFree(s->lattice);
+    if (s->lattice2) (void)hipFree(s->lattice2);
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->d_nc) (void)hipFree(s->d_nc);
     if (s->d_delta) (void)hipFree(s->d_delta);
@@ -372,6 +374,7 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK) st = alloc((void**)&s->d_delta, (size_t)kChunk * pgg::kSweepWords * sizeof(unsigned long long));
     if (st == PGG_OK) st = alloc((void**)&s->d_counts, kChunk * sizeof(unsigned long long));
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
+    if (st == PGG_OK && s->kernel == PGG_KERNEL_SEGMENT) st = alloc((void**)&s->lattice2, lattice_bytes(p));
     if (st != PGG_OK) { release(s); return st; }
 
     hipError_t e = pgg::launch_build_table(p->r, p->K, s->d_table, s->stream);
@@ -423,10 +426,13 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
                     }));
             } else if (s->kernel == PGG_KERNEL_SEGMENT) {
                 unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
+                // out of place: even sweeps of the call go lattice -> lattice2, odd ones back
+                const uint32_t* cur = (q & 1) ? s->lattice2 : (const uint32_t*)s->lattice;
+                uint32_t* next = (q & 1) ? (uint32_t*)s->lattice : s->lattice2;
                 for (int a = 0; a < 4; ++a)
                     PGG_HIP(s, timed_launch(s, [&] {
-                        return pgg::launch_segment_residue((uint32_t*)s->lattice, L, s->stride, s->segw, a, t,
-                                                           s->p.seed, s->d_table, dq, drawn, s->stream);
+                        return pgg::launch_segment_residue(cur, next, L, s->stride, s->segw, a, t, s->p.seed,
+                                                           s->d_table, dq, drawn, s->stream);
                     }));
             } else if (s->kernel == PGG_KERNEL_ROWBAND_STAGED) {
                 unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
@@ -446,6 +452,9 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
                     }));
             }
         }
+        if (s->kernel == PGG_KERNEL_SEGMENT && (n & 1))  // the state of an odd chunk is in lattice2
+            PGG_HIP(s, hipMemcpyAsync(s->lattice, s->lattice2, lattice_bytes(&s->p), hipMemcpyDeviceToDevice,
+                                      s->stream));
         PGG_HIP(s, pgg::launch_scan_counts(s->d_delta, s->d_counts, (int)n, s->d_nc, s->stream));
         if (coop_counts) {
             PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_counts, n * sizeof(uint64_t),

@@ -25,8 +25,6 @@
 
 namespace pgg {
 
-constexpr int kWavesPerGroup = kSegmentThreads / 64;
-
 // Replica whose wave range holds wave w: the last replica with wave_base <= w.
 __device__ __forceinline__ int replica_of_wave(const EnsRep* __restrict__ reps, int n, int w) {
     int lo = 0, hi = n - 1;
@@ -57,7 +55,11 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
     int my_delta = 0, my_drawn = 0;
     if (q < rp.n_active && lw < (rp.L >> 2) * rp.nseg) {
         const int ri = lw / rp.nseg, sg = lw - (lw / rp.nseg) * rp.nseg;
-        segment_wave(rp.lat, rp.L, rp.stride, rp.nw, a, rp.segw, ri, sg, rp.t0 + (uint32_t)q, rp.k0, rp.k1,
+        // sweep q of the chunk reads the state after sweep q - 1: lat for even
+        // q, lat2 for odd q, and writes the other buffer.
+        const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
+        uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
+        segment_wave(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, ri, sg, rp.t0 + (uint32_t)q, rp.k0, rp.k1,
                      sT, win, my_delta, my_drawn);
     }
 #pragma unroll
@@ -91,8 +93,7 @@ __global__ void k_ens_tables(const EnsRep* __restrict__ reps, const double* __re
 // Per replica: counts[rep][q] = nc[rep] + prefix over q of the sweep deltas
 // (q < n_active), then nc[rep] advances.  One block per replica.
 __global__ void __launch_bounds__(256)
-k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restrict__ counts,
-           unsigned long long* __restrict__ nc) {
+k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restrict__ counts) {
     __shared__ unsigned long long part[256];
     const EnsRep& rp = reps[blockIdx.x];
     const int n = min(rp.n_active, K);
@@ -115,13 +116,29 @@ k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restric
         part[tid] += v;
         __syncthreads();
     }
-    unsigned long long run = nc[blockIdx.x] + (tid ? part[tid - 1] : 0ull);
+    unsigned long long run = *rp.nc + (tid ? part[tid - 1] : 0ull);
     for (int q = lo; q < hi; ++q) {
         run += sweep_delta(q);
         counts[(size_t)blockIdx.x * K + q] = run;
     }
     __syncthreads();
-    if (tid == 255) nc[blockIdx.x] += part[255];
+    if (tid == 255) *rp.nc += part[255];
+}
+
+// After a chunk whose replica ran an odd number of sweeps, its state is in
+// lat2: copy it back (one block per replica).
+__global__ void k_ens_copyback(const EnsRep* __restrict__ reps) {
+    const EnsRep& rp = reps[blockIdx.x];
+    if ((rp.n_active & 1) == 0) return;
+    const int n = rp.L * rp.stride;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) rp.lat[k] = rp.lat2[k];
+}
+
+// Zero the per-sweep counters of every replica (one block per replica).
+__global__ void k_ens_zero(const EnsRep* __restrict__ reps, int chunk) {
+    unsigned long long* d = reps[blockIdx.x].delta;
+    const int n = chunk * kSweepWords;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) d[k] = 0ull;
 }
 
 // Sweep bookkeeping of every replica: n_active for the next chunk, or the
@@ -134,6 +151,56 @@ __global__ void k_ens_set_active(EnsRep* __restrict__ reps, int n_reps, int n) {
 __global__ void k_ens_advance(EnsRep* __restrict__ reps, int n_reps) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n_reps) reps[k].t0 += (uint32_t)reps[k].n_active;
+}
+
+void ens_geometry(EnsRep& rp, int L, int segw) {
+    if (segw == 0) {
+        // Columns per segment: about L / 8, at least 64, at most L - 32.
+        segw = (L / 8) & ~31;
+        if (segw < 64) segw = 64;
+        const int cap = (L - 32) & ~31;
+        if (segw > cap) segw = cap;
+        if (segw < 32) segw = 32;
+    }
+    rp.L = L;
+    rp.stride = 2 * ((L + 63) / 64);
+    rp.nw = (L + 31) / 32;
+    rp.segw = segw;
+    rp.nseg = (L + segw - 1) / segw;
+}
+
+int ens_waves(const EnsRep& rp) {
+    const int wv = (rp.L / 4) * rp.nseg;
+    return (wv + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
+}
+
+size_t ens_lds_bytes(int max_segw) {
+    return (160 + (size_t)kWavesPerGroup * seg_wave_words(max_segw)) * sizeof(uint32_t);
+}
+
+hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
+                            bool set_active, unsigned long long* counts, hipStream_t st) {
+    hipError_t err;
+    const int nb = (n + 255) / 256;
+    if (set_active) {
+        hipLaunchKernelGGL(k_ens_set_active, dim3(nb), dim3(256), 0, st, d_reps, n, len);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(k_ens_zero, dim3(n), dim3(256), 0, st, d_reps, chunk);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int blocks = total_waves / kWavesPerGroup;
+    for (int q = 0; q < len; ++q) {
+        for (int a = 0; a < 4; ++a) {
+            hipLaunchKernelGGL(k_ens_segment, dim3(blocks), dim3(kSegmentThreads), lds, st, d_reps, n, a, q);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+    }
+    hipLaunchKernelGGL(k_ens_scan, dim3(n), dim3(256), 0, st, d_reps, chunk, counts);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_ens_copyback, dim3(n), dim3(256), 0, st, d_reps);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_ens_advance, dim3(nb), dim3(256), 0, st, d_reps, n);
+    return hipGetLastError();
 }
 
 }  // namespace pgg
@@ -193,27 +260,9 @@ void ens_release(pgg_ensemble* e) {
     delete e;
 }
 
-// Enqueue one chunk of len sweeps for every replica on the stream.
 hipError_t enqueue_chunk(pgg_ensemble* e, int len) {
-    hipError_t err;
-    const int nb = (e->n + 255) / 256;
-    hipLaunchKernelGGL(pgg::k_ens_set_active, dim3(nb), dim3(256), 0, e->stream, e->d_reps, e->n, len);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    err = pgg::launch_fill_u64(e->d_delta, (int64_t)e->n * e->chunk * pgg::kSweepWords, 0ull, e->stream);
-    if (err != hipSuccess) return err;
-    const int blocks = e->total_waves / pgg::kWavesPerGroup;
-    for (int q = 0; q < len; ++q) {
-        for (int a = 0; a < 4; ++a) {
-            hipLaunchKernelGGL(pgg::k_ens_segment, dim3(blocks), dim3(pgg::kSegmentThreads), e->lds, e->stream,
-                               e->d_reps, e->n, a, q);
-            if ((err = hipGetLastError()) != hipSuccess) return err;
-        }
-    }
-    hipLaunchKernelGGL(pgg::k_ens_scan, dim3(e->n), dim3(256), 0, e->stream, e->d_reps, e->chunk, e->d_counts,
-                       e->d_nc);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(pgg::k_ens_advance, dim3(nb), dim3(256), 0, e->stream, e->d_reps, e->n);
-    return hipGetLastError();
+    return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts,
+                                 e->stream);
 }
 
 hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
@@ -233,16 +282,6 @@ hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
     e->graphs[len] = ex;
     *out = ex;
     return hipSuccess;
-}
-
-int ens_segw(uint32_t L) {
-    // Columns per segment: at least 64 and at most L - 32, about L / 8.
-    int w = (int)(L / 8) & ~31;
-    if (w < 64) w = 64;
-    const int cap = ((int)L - 32) & ~31;
-    if (w > cap) w = cap;
-    if (w < 32) w = 32;
-    return w;
 }
 
 }  // namespace
@@ -287,23 +326,18 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         const pgg_params& p = reps[k];
         pgg::EnsRep& rp = e->host_reps[k];
         std::memset(&rp, 0, sizeof(rp));
-        rp.L = (int)p.L;
-        rp.stride = 2 * (int)((p.L + 63) / 64);
-        rp.nw = (int)((p.L + 31) / 32);
-        rp.segw = tiles && tiles[k] ? (int)tiles[k] : ens_segw(p.L);
-        rp.nseg = (rp.L + rp.segw - 1) / rp.segw;
+        pgg::ens_geometry(rp, (int)p.L, tiles ? (int)tiles[k] : 0);
         rp.k0 = (uint32_t)p.seed;
         rp.k1 = (uint32_t)(p.seed >> 32);
         rp.t0 = 0;
         rp.wave_base = waves;
-        const int wv = (rp.L / 4) * rp.nseg;
-        waves += (wv + pgg::kWavesPerGroup - 1) / pgg::kWavesPerGroup * pgg::kWavesPerGroup;
+        waves += pgg::ens_waves(rp);
         lat_off[k] = lat_words;
-        lat_words += ((size_t)rp.L * rp.stride + 63) & ~(size_t)63;
+        lat_words += 2 * (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);  // lat and lat2
         max_segw = std::max(max_segw, rp.segw);
     }
     e->total_waves = waves;
-    e->lds = (160 + (size_t)pgg::kWavesPerGroup * pgg::seg_wave_words(max_segw)) * sizeof(uint32_t);
+    e->lds = pgg::ens_lds_bytes(max_segw);
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t err = hipMalloc(ptr, bytes);
@@ -323,8 +357,10 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     for (uint32_t k = 0; k < n_reps; ++k) {
         pgg::EnsRep& rp = e->host_reps[k];
         rp.lat = e->d_lattices + lat_off[k];
+        rp.lat2 = rp.lat + (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);
         rp.T = e->d_tables + (size_t)k * 160;
         rp.delta = e->d_delta + (size_t)k * chunk * pgg::kSweepWords;
+        rp.nc = e->d_nc + k;
     }
     std::vector<double> rK(2 * n_reps);
     for (uint32_t k = 0; k < n_reps; ++k) { rK[2 * k] = reps[k].r; rK[2 * k + 1] = reps[k].K; }

@@ -76,8 +76,11 @@ hipError_t launch_tasks_set(StripTask* tasks, int n_tasks, uint32_t t0, int n,
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
 // Segment kernel (pgg_segment.hip): one wave per row segment of segw columns.
+// Out of place within a sweep: launch a reads residues < a from next, the
+// rest from cur, and writes residue a to next; after the 4 launches next
+// holds the whole lattice.
 constexpr int kSegmentThreads = 256;
-hipError_t launch_segment_residue(uint32_t* lat, int L, int stride, int segw, int a, uint32_t t,
+hipError_t launch_segment_residue(const uint32_t* cur, uint32_t* next, int L, int stride, int segw, int a, uint32_t t,
                                   uint64_t seed, const uint32_t* T, unsigned long long* delta,
                                   unsigned long long* drawn, hipStream_t st);
 size_t segment_lds_bytes(int segw);
@@ -87,12 +90,28 @@ size_t segment_lds_bytes(int segw);
 // the first wave of its range in a launch, the number of sweeps of the
 // current chunk, Philox key and current sweep index.
 struct EnsRep {
-    uint32_t* lat;
+    uint32_t* lat;              // the lattice at chunk boundaries
+    uint32_t* lat2;             // second buffer: odd sweeps of a chunk land here
     const uint32_t* T;
-    unsigned long long* delta;
+    unsigned long long* delta;  // chunk x kSweepWords
+    unsigned long long* nc;     // N_C after the last completed sweep
     int L, stride, nw, segw, nseg, wave_base, n_active;
     uint32_t k0, k1, t0;
 };
+
+constexpr int kWavesPerGroup = kSegmentThreads / 64;
+// Fill in segw, nseg, stride, nw of a replica of side L (segw 0 = automatic).
+void ens_geometry(EnsRep& rp, int L, int segw);
+// Waves of one launch for this replica, padded to whole workgroups.
+int ens_waves(const EnsRep& rp);
+size_t ens_lds_bytes(int max_segw);
+// Enqueue one chunk of `len` sweeps (len <= chunk) for the n replicas of
+// d_reps on st: (if set_active) n_active = len for every replica, zero their
+// counters, 4 segment launches per sweep (replicas run q < n_active), the
+// per-replica scan into counts[n][chunk] (and rp.nc), the copy of the final
+// state back to rp.lat when it lies in rp.lat2, the advance of t0.
+hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
+                            bool set_active, unsigned long long* counts, hipStream_t st);
 
 // Sets the calling thread's pgg_last_error() text (printf-style).
 void set_errorf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));

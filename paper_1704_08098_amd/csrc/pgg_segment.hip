@@ -28,7 +28,8 @@
 namespace pgg {
 
 __global__ void __launch_bounds__(kSegmentThreads)
-k_segment(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, int segw, int nseg, uint32_t t,
+k_segment(const uint32_t* __restrict__ cur, uint32_t* __restrict__ next, int L, int stride, int nw, int a,
+          int segw, int nseg, uint32_t t,
           uint32_t k0, uint32_t k1, const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta,
           unsigned long long* __restrict__ drawn) {
     extern __shared__ uint32_t smem[];
@@ -45,7 +46,7 @@ k_segment(uint32_t* __restrict__ lat, int L, int stride, int nw, int a, int segw
     int my_delta = 0, my_drawn = 0;
     if (gw < (L >> 2) * nseg) {  // waves past the last segment only join the reduction
         const int ri = gw / nseg, sg = gw - (gw / nseg) * nseg;
-        segment_wave(lat, L, stride, nw, a, segw, ri, sg, t, k0, k1, sT, win, my_delta, my_drawn);
+        segment_wave(cur, next, L, stride, nw, a, segw, ri, sg, t, k0, k1, sT, win, my_delta, my_drawn);
     }
     // Reduce over the workgroup; one atomic per workgroup on a spread slot.
 #pragma unroll
@@ -70,7 +71,7 @@ size_t segment_lds_bytes(int segw) {
     return (160 + (size_t)(kSegmentThreads / 64) * seg_wave_words(segw)) * sizeof(uint32_t);
 }
 
-hipError_t launch_segment_residue(uint32_t* lat, int L, int stride, int segw, int a, uint32_t t,
+hipError_t launch_segment_residue(const uint32_t* cur, uint32_t* next, int L, int stride, int segw, int a, uint32_t t,
                                   uint64_t seed, const uint32_t* T, unsigned long long* delta,
                                   unsigned long long* drawn, hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -79,8 +80,8 @@ hipError_t launch_segment_residue(uint32_t* lat, int L, int stride, int segw, in
     const int waves = (L / 4) * nseg;
     const int wpb = kSegmentThreads / 64;
     const int blocks = (waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL(k_segment, dim3(blocks), dim3(kSegmentThreads), segment_lds_bytes(segw), st, lat, L,
-                       stride, nw, a, segw, nseg, t, k0, k1, T, delta, drawn);
+    hipLaunchKernelGGL(k_segment, dim3(blocks), dim3(kSegmentThreads), segment_lds_bytes(segw), st, cur, next,
+                       L, stride, nw, a, segw, nseg, t, k0, k1, T, delta, drawn);
     return hipGetLastError();
 }
 

@@ -59,13 +59,16 @@ __host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 8; 
 __host__ __device__ constexpr int seg_wave_words(int segw) { return 7 * seg_window_words(segw) + seg_list_cap(segw); }
 
 // win: the wave's LDS area of seg_wave_words(segw) words; sT: the threshold
-// table in LDS.  Adds the net change of the cooperator count over the owned
-// columns to my_delta (every lane) and the number of draws to my_drawn
-// (lane 0).
-__device__ __forceinline__ void segment_wave(uint32_t* __restrict__ lat, int L, int stride, int nw, int a,
-                                             int segw, int ri, int sg, uint32_t t, uint32_t k0, uint32_t k1,
-                                             const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
-                                             int& my_delta, int& my_drawn) {
+// table in LDS.  The update is out of place: rows whose residue is below a
+// are read from `next` (already updated in this sweep by an earlier launch),
+// the others from `cur`; row i is written to `next`.  So no wave reads a row
+// that another wave of the same launch writes.  Adds the net change of the
+// cooperator count over the owned columns to my_delta (every lane) and the
+// number of draws to my_drawn (lane 0).
+__device__ __forceinline__ void segment_wave(const uint32_t* __restrict__ cur, uint32_t* __restrict__ next, int L,
+                                             int stride, int nw, int a, int segw, int ri, int sg, uint32_t t,
+                                             uint32_t k0, uint32_t k1, const uint32_t* __restrict__ sT,
+                                             uint32_t* __restrict__ win, int& my_delta, int& my_drawn) {
     using namespace seg;
     const int lane = threadIdx.x & 63;
     const int WB = seg_window_words(segw);
@@ -81,7 +84,8 @@ __device__ __forceinline__ void segment_wave(uint32_t* __restrict__ lat, int L, 
         int gi = i - 3 + o;
         gi += (gi < 0) ? L : 0;
         gi -= (gi >= L) ? L : 0;
-        win[q] = global_window(lat + (size_t)gi * stride, L, nw, c0 + 32 * w);
+        const uint32_t* src = ((gi & 3) < a) ? next : cur;
+        win[q] = global_window(src + (size_t)gi * stride, L, nw, c0 + 32 * w);
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -164,7 +168,7 @@ __device__ __forceinline__ void segment_wave(uint32_t* __restrict__ lat, int L, 
         uint32_t v = r0[2 + q];
         const int valid = e - (s + 32 * q);
         if (valid < 32) v &= (1u << valid) - 1u;
-        lat[(size_t)i * stride + (s >> 5) + q] = v;
+        next[(size_t)i * stride + (s >> 5) + q] = v;
     }
 }
 

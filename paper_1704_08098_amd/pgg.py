@@ -32,13 +32,22 @@ EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_set_strip_wait", "pgg_destroy",
            "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
-           "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy")
+           "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy",
+           "pgg_server_job_bytes", "pgg_server_create", "pgg_server_submit", "pgg_server_step",
+           "pgg_server_completed", "pgg_server_job_state", "pgg_server_job_result", "pgg_server_stats",
+           "pgg_server_destroy")
 
 
 class PggParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("r", ctypes.c_double), ("K", ctypes.c_double),
                 ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
                 ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
+
+
+class PggServerInfo(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_uint32), ("resident", ctypes.c_uint32), ("completed", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64), ("budget", ctypes.c_uint64),
+                ("site_updates", ctypes.c_uint64)]
 
 
 class PggError(RuntimeError):
@@ -82,6 +91,16 @@ def load():
         "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_read_lattice": (ctypes.c_int, [vp, ctypes.c_uint32, u8p]),
         "pgg_ensemble_destroy": (None, [vp]),
+        "pgg_server_job_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
+        "pgg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                             vp, P(vp)]),
+        "pgg_server_submit": (ctypes.c_int, [vp, P(PggParams), ctypes.c_uint32, u64p]),
+        "pgg_server_step": (ctypes.c_int, [vp, u32p]),
+        "pgg_server_completed": (ctypes.c_int, [vp, u64p, ctypes.c_uint32, u32p]),
+        "pgg_server_job_state": (ctypes.c_int, [vp, ctypes.c_uint64, P(ctypes.c_int), u32p]),
+        "pgg_server_job_result": (ctypes.c_int, [vp, ctypes.c_uint64, u64p, u8p]),
+        "pgg_server_stats": (ctypes.c_int, [vp, P(PggServerInfo)]),
+        "pgg_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -307,6 +326,78 @@ class Ensemble:
     def close(self):
         if self.handle:
             load().pgg_ensemble_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServerEngine:
+    """The C job server (pgg_server_* calls): submit, step, completed, result."""
+
+    def __init__(self, hbm_budget, max_L=2048, max_resident=4096, chunk=16, stream=None):
+        h = ctypes.c_void_p()
+        _check(load().pgg_server_create(int(hbm_budget), int(max_L), int(max_resident), int(chunk),
+                                        _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+        self.chunk = int(chunk)
+        self._n = {}
+
+    @staticmethod
+    def job_bytes(L, chunk):
+        return int(load().pgg_server_job_bytes(int(L), int(chunk)))
+
+    def submit(self, L, r, n_sweeps, K=0.5, p0=0.5, seed=1, tile=0):
+        jid = ctypes.c_uint64()
+        p = make_params(L, r, K, p0, seed, "bits", "auto", tile)
+        _check(load().pgg_server_submit(self.handle, ctypes.byref(p), int(n_sweeps), ctypes.byref(jid)))
+        self._n[jid.value] = (int(L), int(n_sweeps))
+        return jid.value
+
+    def step(self):
+        n = ctypes.c_uint32()
+        _check(load().pgg_server_step(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def completed(self, cap=4096):
+        ids = np.zeros(cap, dtype=np.uint64)
+        n = ctypes.c_uint32()
+        _check(load().pgg_server_completed(self.handle, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                           cap, ctypes.byref(n)))
+        return [int(v) for v in ids[:n.value]]
+
+    def state(self, jid):
+        st, done = ctypes.c_int(), ctypes.c_uint32()
+        _check(load().pgg_server_job_state(self.handle, int(jid), ctypes.byref(st), ctypes.byref(done)))
+        return st.value, done.value
+
+    def result(self, jid, want_lattice=True):
+        L, n = self._n.pop(jid)
+        counts = np.zeros(n, dtype=np.uint64)
+        lat = np.zeros((L, L), dtype=np.uint8) if want_lattice else None
+        _check(load().pgg_server_job_result(self.handle, int(jid),
+                                            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                            lat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+                                            if lat is not None else None))
+        return counts, lat
+
+    def stats(self):
+        info = PggServerInfo()
+        _check(load().pgg_server_stats(self.handle, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in PggServerInfo._fields_}
+
+    def close(self):
+        if self.handle:
+            load().pgg_server_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -316,3 +316,18 @@ def test_segment_widths(pgg, oracle_lib, L, segw):
     with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=segw) as sim:
         assert np.array_equal(sim.sweep(n), counts)
         assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_segment_many_waves_out_of_place(pgg):
+    """65 536 waves per launch (L = 4096, 64-column segments): waves start long
+    after their neighbours have finished.  The segment update reads rows only
+    from buffers that no wave of the same launch writes, so it must equal the
+    row-band kernel (whole rows per workgroup) sweep for sweep."""
+    L, r, seed, n = 4096, 3.7443, 17, 6
+    say("segment 64-column segments at L=4096")
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=64) as a, \
+            pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "rowband_compact") as b:
+        for q in range(n):
+            assert np.array_equal(a.sweep(1), b.sweep(1)), q
+        assert np.array_equal(a.sweep(3), b.sweep(3))
+        assert np.array_equal(a.read_lattice(), b.read_lattice())

@@ -1,0 +1,108 @@
+"""Host-side tests of the serving loop with a stand-in engine built on the oracle.
+
+The stand-in admits jobs in arrival order (plus backfill) under a byte
+budget, advances every resident job one chunk per step and retires finished
+ones, so the loop's bookkeeping -- ids, results, latencies, percentiles,
+admission under the budget -- is checked without a GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_08098_amd import server, workloads as wl
+
+
+class OracleEngine:
+    def __init__(self, budget, chunk, job_bytes=lambda L: L * L // 8 + 4096):
+        self.budget, self.chunk, self.job_bytes = budget, chunk, job_bytes
+        self.queue, self.resident, self.done_ids = [], [], []
+        self.jobs, self.next_id, self.in_use, self.peak = {}, 1, 0, 0
+
+    def submit(self, L, r, n_sweeps, K=0.5, p0=0.5, seed=1):
+        jid = self.next_id
+        self.next_id += 1
+        s, _ = oracle.init(L, p0, seed)
+        self.jobs[jid] = dict(L=L, r=r, K=K, seed=seed, n=n_sweeps, done=0, lat=s, counts=[])
+        self.queue.append(jid)
+        return jid
+
+    def step(self):
+        for jid in list(self.queue):
+            b = self.job_bytes(self.jobs[jid]["L"])
+            if self.in_use + b <= self.budget:
+                self.queue.remove(jid)
+                self.resident.append(jid)
+                self.in_use += b
+                self.peak = max(self.peak, self.in_use)
+        n = len(self.resident)
+        for jid in list(self.resident):
+            j = self.jobs[jid]
+            m = min(self.chunk, j["n"] - j["done"])
+            j["lat"], c = oracle.sweep(j["lat"], j["r"], j["K"], j["seed"], j["done"], m)
+            j["counts"].extend(int(v) for v in c)
+            j["done"] += m
+            if j["done"] == j["n"]:
+                self.resident.remove(jid)
+                self.in_use -= self.job_bytes(j["L"])
+                self.done_ids.append(jid)
+        return n
+
+    def completed(self):
+        out, self.done_ids = self.done_ids, []
+        return out
+
+    def result(self, jid, want_lattice=True):
+        j = self.jobs.pop(jid)
+        return np.array(j["counts"], dtype=np.uint64), (j["lat"] if want_lattice else None)
+
+    def stats(self):
+        return {"peak_bytes": self.peak, "budget": self.budget}
+
+
+def _trace(n, rate, seed):
+    jobs = wl.serving_trace(n, rate, master_seed=seed, L_range=(16, 48), mcs_range=(5, 30))
+    return jobs
+
+
+def test_every_job_gets_its_own_result_and_latency():
+    jobs = _trace(14, rate=400.0, seed=3)
+    eng = OracleEngine(budget=3 * (48 * 48 // 8 + 4096), chunk=7)
+    rep = server.serve(eng, jobs, keep_results=True)
+    assert rep["jobs"] == len(jobs)
+    assert eng.stats()["peak_bytes"] <= eng.budget
+    for k, j in enumerate(jobs):
+        counts, lat = rep["results"][k]
+        ref, nc0, ref_counts = oracle.run(j["L"], j["r"], j["K"], j["p0"], j["seed"], j["sweeps"])
+        assert np.array_equal(counts, ref_counts), k
+        assert np.array_equal(lat, ref), k
+        assert rep["latencies"][k] >= 0.0
+    assert rep["latency_p50_s"] <= rep["latency_p99_s"]
+    assert rep["max_resident"] <= 3
+
+
+def test_budget_binds_admission():
+    jobs = _trace(10, rate=1e6, seed=4)  # all arrive at once
+    eng = OracleEngine(budget=2 * (48 * 48 // 8 + 4096), chunk=5)
+    rep = server.serve(eng, jobs)
+    assert rep["max_resident"] <= 2
+    assert rep["steps"] >= 1
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert server.percentile(v, 50) == 50.0
+    assert server.percentile(v, 99) == 99.0
+    assert server.percentile([3.0], 99) == 3.0
+    with pytest.raises(ValueError):
+        server.percentile([], 50)
+
+
+def test_serving_trace_shape():
+    jobs = wl.serving_trace(500, rate_per_s=10.0, master_seed=7)
+    Ls = np.array([j["L"] for j in jobs])
+    assert np.all(Ls % 4 == 0) and Ls.min() >= 64 and Ls.max() <= 2048
+    arr = np.array([j["arrival"] for j in jobs])
+    assert np.all(np.diff(arr) >= 0)
+    gaps = np.diff(np.concatenate([[0.0], arr]))
+    assert abs(gaps.mean() - 0.1) < 0.02  # Poisson rate 10/s
+    assert all(1000 <= j["sweeps"] <= 10000 and 0.1 <= j["p0"] <= 0.9 and 3.5 <= j["r"] <= 5.6 for j in jobs)
