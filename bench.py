@@ -8,7 +8,7 @@ sweeps, then K timed sweeps (t = W .. W+K-1), inputs resident in HBM.
 
 Prints one JSON line:
   value       whole-job site updates/s (L^2 * K / wall time of the K sweeps)
-  roofline    the dominant kernel (the row-band sweep) against the VALU roof,
+  roofline    the dominant kernel (the segment sweep) against the VALU roof,
               from its event-timed average launch duration
   hbm         the same rate against the HBM roof at the algorithmic bytes of
               the state (read + write once per sweep)
@@ -39,12 +39,15 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T full-rate lane-ops/s
 
 # Algorithmic VALU cost of one elementary step that draws its random numbers,
 # in full-rate 32-bit lane-op slots (derivation in the design doc):
-#   Philox4x32-10: 20 products 32x32->64 (the last round needs one), each a
-#   quarter-rate instruction = 4 slots -> 19 * 4 = 76; 3-input XORs and key
-#   mixing 2 per round -> 19 (first-round key words are uniform);
-#   payoff difference: 2 x (5 masked popcounts + 3 adds), row windows and
-#   the neighbour select -> 30; table index, compare, flip -> 6.
-SLOTS_PER_DRAWN_UPDATE = 76 + 19 + 30 + 6
+#   Philox4x32-10: 19 products 32x32->64 (two per round, the last round
+#   needs one); a v_mad_u64_u32 issues at about 1.3 slots on gfx950
+#   (throughput micro-kernel) -> 25; the two 3-input XORs per round -> 19
+#   (first-round key words are uniform); payoff difference: 2 x (5 masked
+#   popcounts + 3 adds), row windows and the neighbour select -> 30; table
+#   index, compare, flip -> 6.
+PHILOX_PRODUCTS = 19
+SLOTS_PER_PRODUCT = 1.3
+SLOTS_PER_DRAWN_UPDATE = round(PHILOX_PRODUCTS * SLOTS_PER_PRODUCT) + 19 + 30 + 6
 # Every site also pays the bit-parallel activity test (8 sites per 32-bit
 # word: 4 XOR, 3 OR, 1 AND, 2 window extractions) -> ~2 slots per site.
 SLOTS_PER_SITE_SCAN = 2
@@ -209,7 +212,7 @@ def main():
     achieved_tops = slots / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": None,
-                "kernel": {"segment": "k_segment", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
+                "kernel": {"segment": "k_ens_segment", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
                            "rowband_compact": "k_rowband_bits<true>",
                            "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -24,6 +25,7 @@ void set_err(const char* fmt, ...) {
 }
 
 constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
+constexpr int kGraphChunk = 64;    // sweeps per graph replay (segment kernel)
 
 }  // namespace
 
@@ -43,6 +45,19 @@ struct pgg_sim {
     void* lattice = nullptr;
     bool owns_lattice = false;
     uint32_t* lattice2 = nullptr;  // segment kernel: odd sweeps of a call land here
+    // Segment kernel: run as a one-replica ensemble.  d_rep[0] serves the
+    // captured chunks (one graph per chunk length), d_rep[1] the eager
+    // launches of timing mode (it also counts draws); sweep indices live in
+    // device memory.
+    pgg::EnsRep seg_rep;
+    pgg::EnsRep* d_rep = nullptr;
+    unsigned long long* d_gdelta = nullptr;   // kGraphChunk x kSweepWords
+    unsigned long long* d_gcounts = nullptr;  // kGraphChunk
+    hipStream_t capture_stream = nullptr;
+    std::map<int, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+    int seg_waves = 0;
+    size_t seg_lds = 0;
     int stride = 0;  // bits layout: 32-bit words per row
     int kernel = PGG_KERNEL_COLOUR;
     int R = 1;       // rows per workgroup (row-band kernels)
@@ -185,6 +200,12 @@ void release(pgg_sim* s) {
     (void)hipStreamSynchronize(s->stream);
     if (s->owns_lattice && s->lattice) (void)hipFree(s->lattice);
     if (s->lattice2) (void)hipFree(s->lattice2);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : s->graph_defs) (void)hipGraphDestroy(g);
+    if (s->d_rep) (void)hipFree(s->d_rep);
+    if (s->d_gdelta) (void)hipFree(s->d_gdelta);
+    if (s->d_gcounts) (void)hipFree(s->d_gcounts);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->d_nc) (void)hipFree(s->d_nc);
     if (s->d_delta) (void)hipFree(s->d_delta);
@@ -297,6 +318,101 @@ pgg_status plan_strips(pgg_sim* s, uint32_t tile) {
     return PGG_OK;
 }
 
+// The one-replica descriptors and buffers of the segment kernel.
+pgg_status plan_segment_graph(pgg_sim* s) {
+    pgg::EnsRep& rp = s->seg_rep;
+    std::memset(&rp, 0, sizeof(rp));
+    pgg::ens_geometry(rp, (int)s->p.L, s->segw);
+    rp.k0 = (uint32_t)s->p.seed;
+    rp.k1 = (uint32_t)(s->p.seed >> 32);
+    hipError_t e = hipMalloc((void**)&s->d_rep, 2 * sizeof(pgg::EnsRep));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_gdelta, (size_t)kGraphChunk * pgg::kSweepWords * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_gcounts, (size_t)kGraphChunk * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipStreamCreate(&s->capture_stream);
+    if (e != hipSuccess) {
+        set_err("segment graph buffers: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
+    }
+    rp.lat = (uint32_t*)s->lattice;
+    rp.lat2 = s->lattice2;
+    rp.T = s->d_table;
+    rp.delta = s->d_gdelta;
+    rp.nc = s->d_nc;
+    rp.drawn = nullptr;
+    s->seg_waves = pgg::ens_waves(rp);
+    s->seg_lds = pgg::ens_lds_bytes(rp.segw);
+    const pgg::EnsRep both[2] = {rp, rp};
+    e = hipMemcpy(s->d_rep, both, sizeof(both), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { set_err("segment graph descriptor: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
+    return PGG_OK;
+}
+
+// The captured chunk of `len` sweeps (captured on the handle's own capture
+// stream -- the null stream cannot be captured -- and launched on its stream).
+hipError_t segment_graph(pgg_sim* s, int len, hipGraphExec_t* out) {
+    auto it = s->graphs.find(len);
+    if (it != s->graphs.end()) { *out = it->second; return hipSuccess; }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t enq = pgg::launch_ens_chunk(s->d_rep, 1, s->seg_waves, s->seg_lds, len, kGraphChunk, true,
+                                           s->d_gcounts, s->capture_stream);
+    e = hipStreamEndCapture(s->capture_stream, &g);
+    if (enq != hipSuccess) { if (g) (void)hipGraphDestroy(g); return enq; }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return e; }
+    s->graph_defs.push_back(g);
+    s->graphs[len] = ex;
+    *out = ex;
+    return hipSuccess;
+}
+
+// pgg_sweep for the segment kernel outside timing mode: graph replays.
+pgg_status sweep_segment_graph(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
+    PGG_HIP(s, pgg::launch_ens_set_t0(s->d_rep, 1, (uint32_t)s->t, s->stream));
+    uint32_t done = 0;
+    while (done < n_sweeps) {
+        const int len = (int)std::min<uint32_t>((uint32_t)kGraphChunk, n_sweeps - done);
+        hipGraphExec_t g = nullptr;
+        PGG_HIP(s, segment_graph(s, len, &g));
+        PGG_HIP(s, hipGraphLaunch(g, s->stream));
+        if (coop_counts)
+            PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_gcounts, (size_t)len * sizeof(uint64_t),
+                                      hipMemcpyDeviceToHost, s->stream));
+        done += (uint32_t)len;
+    }
+    if (coop_counts) PGG_HIP(s, hipStreamSynchronize(s->stream));
+    s->t += n_sweeps;
+    return PGG_OK;
+}
+
+// pgg_sweep for the segment kernel in timing mode: the same launches as a
+// replayed chunk, issued one by one between events.
+pgg_status sweep_segment_timed(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
+    pgg::EnsRep* rep = s->d_rep + 1;
+    PGG_HIP(s, pgg::launch_ens_set_t0(rep, 1, (uint32_t)s->t, s->stream));
+    uint32_t done = 0;
+    while (done < n_sweeps) {
+        const int len = (int)std::min<uint32_t>((uint32_t)kGraphChunk, n_sweeps - done);
+        PGG_HIP(s, pgg::launch_ens_begin(rep, 1, len, kGraphChunk, true, s->stream));
+        for (int q = 0; q < len; ++q)
+            for (int a = 0; a < 4; ++a)
+                PGG_HIP(s, timed_launch(s, [&] {
+                    return pgg::launch_ens_residue(rep, 1, s->seg_waves, s->seg_lds, a, q, s->stream);
+                }));
+        PGG_HIP(s, pgg::launch_ens_end(rep, 1, kGraphChunk, s->d_gcounts, s->stream));
+        if (coop_counts)
+            PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_gcounts, (size_t)len * sizeof(uint64_t),
+                                      hipMemcpyDeviceToHost, s->stream));
+        done += (uint32_t)len;
+    }
+    if (coop_counts) PGG_HIP(s, hipStreamSynchronize(s->stream));
+    s->t += n_sweeps;
+    return PGG_OK;
+}
+
 // After a stream synchronisation: a persistent launch that gave up waiting
 // leaves the abort flag set; report it and poison the handle.
 pgg_status check_abort(pgg_sim* s) {
@@ -375,6 +491,7 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK) st = alloc((void**)&s->d_counts, kChunk * sizeof(unsigned long long));
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
     if (st == PGG_OK && s->kernel == PGG_KERNEL_SEGMENT) st = alloc((void**)&s->lattice2, lattice_bytes(p));
+    if (st == PGG_OK && s->kernel == PGG_KERNEL_SEGMENT) st = plan_segment_graph(s);
     if (st != PGG_OK) { release(s); return st; }
 
     hipError_t e = pgg::launch_build_table(p->r, p->K, s->d_table, s->stream);
@@ -399,6 +516,8 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     }
     if (n_sweeps == 0) return PGG_OK;
     DeviceGuard guard(s->device);
+    if (s->kernel == PGG_KERNEL_SEGMENT)
+        return s->timing ? sweep_segment_timed(s, n_sweeps, coop_counts) : sweep_segment_graph(s, n_sweeps, coop_counts);
     const int L = (int)s->p.L;
     uint32_t done = 0;
     while (done < n_sweeps) {
@@ -424,16 +543,6 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
                         return pgg::launch_colour_phase((uint8_t*)s->lattice, L, k, t, s->p.seed,
                                                         s->d_table, dq, s->stream);
                     }));
-            } else if (s->kernel == PGG_KERNEL_SEGMENT) {
-                unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
-                // out of place: even sweeps of the call go lattice -> lattice2, odd ones back
-                const uint32_t* cur = (q & 1) ? s->lattice2 : (const uint32_t*)s->lattice;
-                uint32_t* next = (q & 1) ? (uint32_t*)s->lattice : s->lattice2;
-                for (int a = 0; a < 4; ++a)
-                    PGG_HIP(s, timed_launch(s, [&] {
-                        return pgg::launch_segment_residue(cur, next, L, s->stride, s->segw, a, t, s->p.seed,
-                                                           s->d_table, dq, drawn, s->stream);
-                    }));
             } else if (s->kernel == PGG_KERNEL_ROWBAND_STAGED) {
                 unsigned long long* drawn = s->timing ? s->d_drawn : nullptr;
                 for (int a = 0; a < 4; ++a)
@@ -452,9 +561,6 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
                     }));
             }
         }
-        if (s->kernel == PGG_KERNEL_SEGMENT && (n & 1))  // the state of an odd chunk is in lattice2
-            PGG_HIP(s, hipMemcpyAsync(s->lattice, s->lattice2, lattice_bytes(&s->p), hipMemcpyDeviceToDevice,
-                                      s->stream));
         PGG_HIP(s, pgg::launch_scan_counts(s->d_delta, s->d_counts, (int)n, s->d_nc, s->stream));
         if (coop_counts) {
             PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_counts, n * sizeof(uint64_t),
@@ -563,6 +669,11 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable) {
     }
     PGG_HIP(s, fold_timing(s));
     if (enable) PGG_HIP(s, pgg::launch_fill_u64(s->d_drawn, pgg::kSweepWords, 0ull, s->stream));
+    if (enable && s->d_rep) {  // the timing descriptor of the segment kernel counts draws
+        pgg::EnsRep rp = s->seg_rep;
+        rp.drawn = s->d_drawn;
+        PGG_HIP(s, hipMemcpyAsync(s->d_rep + 1, &rp, sizeof(rp), hipMemcpyHostToDevice, s->stream));
+    }
     PGG_HIP(s, hipStreamSynchronize(s->stream));
     s->timing = enable != 0;
     s->timed_launches = 0;

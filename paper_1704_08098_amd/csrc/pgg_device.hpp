@@ -30,6 +30,35 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
+// a ^ b ^ c in one VALU instruction: gfx950's three-input bitwise op with
+// truth table 0x96 (c: a wave-uniform value in an SGPR).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+// Words 0 and 1 of the Philox4x32-10 block of counter (c0, c1, c2, c3): the
+// same rounds as philox4x32_10, with the three-input XORs as v_xor3_b32.
+__device__ __forceinline__ uint2 philox4x32_10_w01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                   uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 9; ++round) {
+        const uint64_t pa = (uint64_t)kPhiloxA * c0;
+        const uint64_t pb = (uint64_t)kPhiloxB * c2;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    const uint64_t pb = (uint64_t)kPhiloxB * c2;  // round 10: only words 0 and 1
+    return make_uint2(xor3((uint32_t)(pb >> 32), c1, k0), (uint32_t)pb);
+}
+
 // (i + di) mod L for |di| <= 3 < L + 1, i in [0, L).
 __device__ __forceinline__ int wrap_add(int i, int di, int L) {
     int v = i + di;

@@ -38,7 +38,7 @@ __device__ __forceinline__ int replica_of_wave(const EnsRep* __restrict__ reps, 
 __global__ void __launch_bounds__(kSegmentThreads)
 k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
     extern __shared__ uint32_t smem[];
-    __shared__ int s_part[kWavesPerGroup];
+    __shared__ int s_part[2 * kWavesPerGroup];
     __shared__ int s_rep;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -48,30 +48,38 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
     const EnsRep rp = reps[s_rep];
     uint32_t* sT = smem;
     uint32_t* win = smem + 160 + wid * seg_wave_words(rp.segw);
+    const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica
+    const bool active = q < rp.n_active && lw < (rp.L >> 2) * rp.nseg;
+    // sweep q of the chunk reads the state after sweep q - 1: lat for even q,
+    // lat2 for odd q, and writes the other buffer.
+    const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
+    uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
+    const SegPos g = seg_pos(rp.L, a, rp.segw, active ? lw / rp.nseg : 0, active ? lw % rp.nseg : 0);
     for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    if (active) segment_fill(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, g, win);
     __syncthreads();
 
-    const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica
     int my_delta = 0, my_drawn = 0;
-    if (q < rp.n_active && lw < (rp.L >> 2) * rp.nseg) {
-        const int ri = lw / rp.nseg, sg = lw - (lw / rp.nseg) * rp.nseg;
-        // sweep q of the chunk reads the state after sweep q - 1: lat for even
-        // q, lat2 for odd q, and writes the other buffer.
-        const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
-        uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
-        segment_wave(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, ri, sg, rp.t0 + (uint32_t)q, rp.k0, rp.k1,
-                     sT, win, my_delta, my_drawn);
-    }
+    if (active)
+        segment_run(next, rp.L, rp.stride, a, rp.segw, g, rp.t0 + (uint32_t)q, rp.k0, rp.k1, sT, win, my_delta,
+                    my_drawn);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
-    if (lane == 0) s_part[wid] = my_delta;
+    if (lane == 0) {
+        s_part[wid] = my_delta;
+        s_part[kWavesPerGroup + wid] = my_drawn;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int dsum = 0;
-        for (int k = 0; k < kWavesPerGroup; ++k) dsum += s_part[k];
+        int dsum = 0, nsum = 0;
+        for (int k = 0; k < kWavesPerGroup; ++k) {
+            dsum += s_part[k];
+            nsum += s_part[kWavesPerGroup + k];
+        }
         if (dsum)
             atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
                       (unsigned long long)(long long)dsum);
+        if (rp.drawn && nsum) atomicAdd(slot_of(rp.drawn, (int)blockIdx.x), (unsigned long long)nsum);
     }
 }
 
@@ -153,6 +161,16 @@ __global__ void k_ens_advance(EnsRep* __restrict__ reps, int n_reps) {
     if (k < n_reps) reps[k].t0 += (uint32_t)reps[k].n_active;
 }
 
+__global__ void k_ens_set_t0(EnsRep* __restrict__ reps, int n_reps, uint32_t t0) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_reps) reps[k].t0 = t0;
+}
+
+hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st) {
+    hipLaunchKernelGGL(k_ens_set_t0, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n, t0);
+    return hipGetLastError();
+}
+
 void ens_geometry(EnsRep& rp, int L, int segw) {
     if (segw == 0) {
         // Columns per segment: about L / 8, at least 64, at most L - 32.
@@ -178,29 +196,40 @@ size_t ens_lds_bytes(int max_segw) {
     return (160 + (size_t)kWavesPerGroup * seg_wave_words(max_segw)) * sizeof(uint32_t);
 }
 
-hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
-                            bool set_active, unsigned long long* counts, hipStream_t st) {
-    hipError_t err;
-    const int nb = (n + 255) / 256;
+hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_active, hipStream_t st) {
     if (set_active) {
-        hipLaunchKernelGGL(k_ens_set_active, dim3(nb), dim3(256), 0, st, d_reps, n, len);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        hipLaunchKernelGGL(k_ens_set_active, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n, len);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_ens_zero, dim3(n), dim3(256), 0, st, d_reps, chunk);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    const int blocks = total_waves / kWavesPerGroup;
-    for (int q = 0; q < len; ++q) {
-        for (int a = 0; a < 4; ++a) {
-            hipLaunchKernelGGL(k_ens_segment, dim3(blocks), dim3(kSegmentThreads), lds, st, d_reps, n, a, q);
-            if ((err = hipGetLastError()) != hipSuccess) return err;
-        }
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_ens_segment, dim3(total_waves / kWavesPerGroup), dim3(kSegmentThreads), lds, st, d_reps,
+                       n, a, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st) {
+    hipError_t err;
     hipLaunchKernelGGL(k_ens_scan, dim3(n), dim3(256), 0, st, d_reps, chunk, counts);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_ens_copyback, dim3(n), dim3(256), 0, st, d_reps);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_ens_advance, dim3(nb), dim3(256), 0, st, d_reps, n);
+    hipLaunchKernelGGL(k_ens_advance, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n);
     return hipGetLastError();
+}
+
+hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
+                            bool set_active, unsigned long long* counts, hipStream_t st) {
+    hipError_t err = launch_ens_begin(d_reps, n, len, chunk, set_active, st);
+    for (int q = 0; err == hipSuccess && q < len; ++q)
+        for (int a = 0; err == hipSuccess && a < 4; ++a) err = launch_ens_residue(d_reps, n, total_waves, lds, a, q, st);
+    if (err != hipSuccess) return err;
+    return launch_ens_end(d_reps, n, chunk, counts, st);
 }
 
 }  // namespace pgg

@@ -75,15 +75,11 @@ hipError_t launch_tasks_set(StripTask* tasks, int n_tasks, uint32_t t0, int n,
                             unsigned long long* delta, unsigned long long* drawn, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
-// Segment kernel (pgg_segment.hip): one wave per row segment of segw columns.
-// Out of place within a sweep: launch a reads residues < a from next, the
-// rest from cur, and writes residue a to next; after the 4 launches next
-// holds the whole lattice.
+// Segment kernel (pgg_segment.hpp, launched by pgg_ensemble.hip): one wave
+// per row segment.  Out of place within a sweep: launch a reads residues < a
+// from the buffer it writes and the rest from the other one; after the 4
+// launches of a sweep the written buffer holds the whole lattice.
 constexpr int kSegmentThreads = 256;
-hipError_t launch_segment_residue(const uint32_t* cur, uint32_t* next, int L, int stride, int segw, int a, uint32_t t,
-                                  uint64_t seed, const uint32_t* T, unsigned long long* delta,
-                                  unsigned long long* drawn, hipStream_t st);
-size_t segment_lds_bytes(int segw);
 
 // Ensemble replica descriptor (pgg_ensemble.hip): replica lattice, its
 // threshold table, its per-sweep counters (chunk x kSweepWords), geometry,
@@ -95,6 +91,7 @@ struct EnsRep {
     const uint32_t* T;
     unsigned long long* delta;  // chunk x kSweepWords
     unsigned long long* nc;     // N_C after the last completed sweep
+    unsigned long long* drawn;  // kSweepWords spread counters of draws, or null
     int L, stride, nw, segw, nseg, wave_base, n_active;
     uint32_t k0, k1, t0;
 };
@@ -112,6 +109,14 @@ size_t ens_lds_bytes(int max_segw);
 // state back to rp.lat when it lies in rp.lat2, the advance of t0.
 hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
                             bool set_active, unsigned long long* counts, hipStream_t st);
+// The same chunk in three parts, for callers that bracket each segment
+// launch (residue a of sweep q of the chunk) with events of their own.
+hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_active, hipStream_t st);
+hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
+                              hipStream_t st);
+hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st);
+// Set the sweep index t0 of every replica (graph-safe, no host memory).
+hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st);
 
 // Sets the calling thread's pgg_last_error() text (printf-style).
 void set_errorf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));

@@ -1,6 +1,26 @@
-// One wave's share of the segment sweep (see pgg_segment.hip): row i of
-// residue a, columns [s, e), the four colour classes 4a..4a+3 of sweep t.
-// Shared by the single-lattice and the ensemble kernels.  gfx950.
+// Segment sweep on the bit-packed layout (gfx950): one wave per row segment,
+// no workgroup barriers.  The kernel that launches it is k_ens_segment
+// (pgg_ensemble.hip); a single lattice runs as a one-replica ensemble.
+//
+// One launch per row residue a = i mod 4 runs the colour classes
+// k = 4a + 0..3.  Within such a launch only the rows with i mod 4 = a change,
+// each only through its own sites, and a site reads rows i-3..i+3 and
+// columns j-3..j+3.  So a row can be cut into segments [s, e) that are
+// processed independently: the wave owning a segment copies the 7 rows it
+// reads into a private LDS window (columns s-64 .. e+63, periodic), and
+// updates class b on the columns [s - m_b, e + m_b) with m = (9, 6, 3, 0):
+// class 3 on [s, e) reads classes 0-2 only within 3 columns, class 2 on
+// [s-3, e+3) reads classes 0-1 within 3 more, and so on, so every site the
+// wave writes back -- the columns [s, e) -- is exact.  Sites in the margins
+// are recomputed (identically) by the neighbouring segment's wave and
+// discarded here.  A segment is at most L - 32 columns, so a margin site and
+// its periodic image never both lie in the columns a class updates.
+//
+// Per class the wave computes, bit-parallel over 32-bit words, the sites
+// with a differing neighbour (the others cannot change and draw nothing),
+// compacts them into a wave-private list, and processes the list: Philox
+// block, payoff stencil, Fermi threshold, flip in LDS.  LDS operations of a
+// wave complete in order, so the next class sees every flip of this one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,35 +78,80 @@ __host__ __device__ constexpr int seg_window_words(int segw) { return segw / 32 
 __host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 8; }
 __host__ __device__ constexpr int seg_wave_words(int segw) { return 7 * seg_window_words(segw) + seg_list_cap(segw); }
 
-// win: the wave's LDS area of seg_wave_words(segw) words; sT: the threshold
-// table in LDS.  The update is out of place: rows whose residue is below a
-// are read from `next` (already updated in this sweep by an earlier launch),
-// the others from `cur`; row i is written to `next`.  So no wave reads a row
-// that another wave of the same launch writes.  Adds the net change of the
-// cooperator count over the owned columns to my_delta (every lane) and the
-// number of draws to my_drawn (lane 0).
-__device__ __forceinline__ void segment_wave(const uint32_t* __restrict__ cur, uint32_t* __restrict__ next, int L,
-                                             int stride, int nw, int a, int segw, int ri, int sg, uint32_t t,
-                                             uint32_t k0, uint32_t k1, const uint32_t* __restrict__ sT,
-                                             uint32_t* __restrict__ win, int& my_delta, int& my_drawn) {
+// Segment geometry of one wave: row i of residue a, owned columns [s, e),
+// window bit 0 at column c0 = s - 64.
+struct SegPos {
+    int i, s, e, c0;
+};
+
+__device__ __forceinline__ SegPos seg_pos(int L, int a, int segw, int ri, int sg) {
+    SegPos g;
+    g.i = a + 4 * ri;
+    g.s = sg * segw;
+    g.e = min(L, g.s + segw);
+    g.c0 = g.s - 64;
+    return g;
+}
+
+// Fill the wave's LDS window with the 7 rows it reads (columns c0 .. c0 +
+// 32 WB - 1, periodic).  The update is out of place: rows whose residue is
+// below a are read from `next` (already updated in this sweep by an earlier
+// launch), the others from `cur`; row i is later written to `next`.  So no
+// wave reads a row that another wave of the same launch writes.  When L is
+// a multiple of 32 every window word is one word of the row (segments start
+// on word boundaries), and each lane issues its 7 loads back to back.
+__device__ __forceinline__ void segment_fill(const uint32_t* __restrict__ cur, const uint32_t* __restrict__ next,
+                                             int L, int stride, int nw, int a, int segw, const SegPos& g,
+                                             uint32_t* __restrict__ win) {
+    using namespace seg;
+    const int lane = threadIdx.x & 63;
+    const int WB = seg_window_words(segw);
+    if ((L & 31) == 0) {
+        const int w0 = (g.c0 >> 5);  // may be -2 or -1 for the first segment
+        for (int wb = 0; wb < WB; wb += 64) {
+            const int w = wb + lane;
+            if (w < WB) {
+                uint32_t v[7];
+                int widx = w0 + w;                  // in [-2, nw + 2): one wrap suffices (nw >= 2)
+                widx += (widx < 0) ? nw : 0;
+                widx -= (widx >= nw) ? nw : 0;
+#pragma unroll
+                for (int o = 0; o < 7; ++o) {
+                    int gi = g.i - 3 + o;
+                    gi += (gi < 0) ? L : 0;
+                    gi -= (gi >= L) ? L : 0;
+                    const uint32_t* src = ((gi & 3) < a) ? next : cur;
+                    v[o] = src[(size_t)gi * stride + widx];
+                }
+#pragma unroll
+                for (int o = 0; o < 7; ++o) win[o * WB + w] = v[o];
+            }
+        }
+        return;
+    }
+    for (int q = lane; q < 7 * WB; q += 64) {
+        const int o = q / WB, w = q - (q / WB) * WB;
+        int gi = g.i - 3 + o;
+        gi += (gi < 0) ? L : 0;
+        gi -= (gi >= L) ? L : 0;
+        const uint32_t* src = ((gi & 3) < a) ? next : cur;
+        win[q] = global_window(src + (size_t)gi * stride, L, nw, g.c0 + 32 * w);
+    }
+}
+
+// The four colour classes on the filled window, then the owned columns
+// written to next.  sT: the threshold table in LDS.  Adds the net change of
+// the cooperator count over the owned columns to my_delta (every lane) and
+// the number of draws to my_drawn (lane 0).
+__device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, int stride, int a, int segw,
+                                            const SegPos& g, uint32_t t, uint32_t k0, uint32_t k1,
+                                            const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
+                                            int& my_delta, int& my_drawn) {
     using namespace seg;
     const int lane = threadIdx.x & 63;
     const int WB = seg_window_words(segw);
     uint32_t* list = win + 7 * WB;
-    const int i = a + 4 * ri;
-    const int s = sg * segw;
-    const int e = min(L, s + segw);
-    const int c0 = s - 64;                   // column of window bit 0
-
-    // Load the 7 rows' windows (columns c0 .. c0 + 32 WB - 1, periodic).
-    for (int q = lane; q < 7 * WB; q += 64) {
-        const int o = q / WB, w = q - (q / WB) * WB;
-        int gi = i - 3 + o;
-        gi += (gi < 0) ? L : 0;
-        gi -= (gi >= L) ? L : 0;
-        const uint32_t* src = ((gi & 3) < a) ? next : cur;
-        win[q] = global_window(src + (size_t)gi * stride, L, nw, c0 + 32 * w);
-    }
+    const int i = g.i, s = g.s, e = g.e, c0 = g.c0;
     __builtin_amdgcn_wave_barrier();
 
     uint32_t* r0 = win + 3 * WB;  // the row being updated
@@ -131,7 +196,7 @@ __device__ __forceinline__ void segment_wave(const uint32_t* __restrict__ cur, u
             int c = c0 + p;
             c += (c < 0) ? L : 0;
             c -= (c >= L) ? L : 0;
-            const uint4 rnd = philox4x32_10(make_uint4((uint32_t)(i * L + c), t, k, 0u), k0, k1);
+            const uint2 rnd = philox4x32_10_w01((uint32_t)(i * L + c), t, k, 0u, k0, k1);
             const int d = (int)(rnd.x >> 30);
             const uint32_t u = rnd.y;
             const int w = (p - 16) >> 5, sh = (p - 16) & 31;

@@ -331,3 +331,25 @@ def test_segment_many_waves_out_of_place(pgg):
             assert np.array_equal(a.sweep(1), b.sweep(1)), q
         assert np.array_equal(a.sweep(3), b.sweep(3))
         assert np.array_equal(a.read_lattice(), b.read_lattice())
+
+
+def test_segment_graph_and_eager_paths_agree(pgg, oracle_lib):
+    """Outside timing mode the segment kernel replays captured chunks of
+    sweeps (sweep index in device memory); in timing mode it launches each
+    residue eagerly.  Calls of ragged lengths (odd, one, several chunks, a
+    chunk and a tail) switch between the two on one lattice and must follow
+    the oracle sweep for sweep."""
+    L, r, K, p0, seed = 200, 3.8, 0.5, 0.5, 23
+    lengths = [1, 63, 64, 65, 130, 3, 2]
+    n = sum(lengths)
+    ref, nc0, counts = oracle_lib.run(L, r, K, p0, seed, n)
+    say("segment graph/eager switching", L, lengths)
+    with pgg.Sim(L, r, K, p0, seed, "bits", "segment") as sim:
+        got, timing = [], False
+        for m in lengths:
+            sim.set_kernel_timing(timing)
+            got.append(sim.sweep(m))
+            timing = not timing
+        assert np.array_equal(np.concatenate(got), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+        assert sim.t == n
