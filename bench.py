@@ -84,16 +84,24 @@ def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, t
     return launches, ms, drawn
 
 
-def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream):
+def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     """Batched ensemble (all replicas, one graph replay per chunk) vs the same
-    replicas run one lattice at a time (a sample of each size, scaled)."""
+    replicas run one lattice at a time (a sample of each size, scaled).  With
+    autotune, the segment width per size and the chunk come from
+    pgg_ensemble_autotune (untimed, before the timed run)."""
     reps = wl.ensemble_replicas(sweeps=sweeps)
     total = float(sum(rp["L"] ** 2 for rp in reps)) * sweeps
-    ens = pgg.Ensemble(reps, chunk=chunk, stream=stream)
+    tiles, tuned = None, None
+    if autotune:
+        t0 = time.perf_counter()
+        tiles, chunk, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
+        tuned = {"tiles_by_L": {int(rp["L"]): int(w) for rp, w in zip(reps, tiles)}, "chunk": chunk,
+                 "probe_ms_per_sweep": ms, "tuning_s": time.perf_counter() - t0}
+    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream)
     ens.sweep(min(chunk, sweeps), want_counts=False)  # first replay builds the graph
     torch.cuda.synchronize()
     ens.close()
-    ens = pgg.Ensemble(reps, chunk=chunk, stream=stream)
+    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ens.sweep(sweeps, want_counts=False)
@@ -121,7 +129,7 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream):
         t_plain += sum(ts) / len(ts) * len(ks)
     return {"metric": "replica-site updates/s", "value": total / t_batched, "plain_value": total / t_plain,
             "ratio_vs_plain": t_plain / t_batched, "replicas": len(reps), "sweeps": sweeps,
-            "sizes": sorted(by_size), "chunk": chunk, "batched_s": t_batched, "plain_s_estimated": t_plain,
+            "sizes": sorted(by_size), "chunk": chunk, "autotuned": tuned, "batched_s": t_batched, "plain_s_estimated": t_plain,
             "plain": "each replica alone (pgg_init/pgg_sweep, automatic kernel), %d per size timed, "
                      "scaled to the %d replicas of each size" % (plain_per_size, len(reps) // len(by_size)),
             "mean_final_density": float(sum(int(v) / reps[k]["L"] ** 2 for k, v in enumerate(nc)) / len(reps))}
@@ -156,6 +164,8 @@ def main():
     ap.add_argument("--ensemble-sweeps", type=int, default=5000, help="0 skips the ensemble pass")
     ap.add_argument("--ensemble-chunk", type=int, default=50)
     ap.add_argument("--plain-per-size", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true", help="ensemble pass with automatic widths and "
+                    "--ensemble-chunk instead of pgg_ensemble_autotune")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -229,7 +239,8 @@ def main():
     batched = None
     if args.ensemble_sweeps > 0:
         log("ensemble pass: %d sweeps" % args.ensemble_sweeps)
-        batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream)
+        batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream,
+                                not args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:

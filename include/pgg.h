@@ -247,6 +247,27 @@ pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* hos
 /* Release every buffer, graph and owned stream.  NULL is a no-op. */
 void pgg_ensemble_destroy(pgg_ensemble* e);
 
+/* Autotune the batched launch for a set of replicas: the segment width of
+ * each distinct L and the chunk length of a graph replay.  Results never
+ * depend on either; only the speed does.
+ *   reps, n_reps  as for pgg_ensemble_create.
+ *   probe_sweeps  sweeps timed per trial, 1..4096 (after 2 untimed ones).
+ *   hip_stream    as for pgg_ensemble_create.
+ *   tiles_out     host array of n_reps: the chosen width of each replica
+ *                 (equal for equal L).
+ *   chunk_out     the chosen chunk length.
+ *   ms_out        NULL, or the best time per sweep of the whole ensemble.
+ * Trials run on trial ensembles created from reps (fresh initial states
+ * each): first the width of each distinct L in turn over the doublings
+ * 64, 128, ... below L - 32 plus L - 32 rounded down to a multiple of 32,
+ * the other sizes held at their best so far, then the chunk over
+ * 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
+ * trial's final cooperator counts must equal the first trial's, else
+ * PGG_E_DEVICE with a message (a tuning-dependent result would be a bug).
+ * Needs the device memory of one trial ensemble at chunk 128. */
+pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps,
+                                 void* hip_stream, uint32_t* tiles_out, uint32_t* chunk_out, double* ms_out);
+
 /* ------------------------------------------------------------------------
  * Job server: continuous batching of simulation jobs on one GPU.  Jobs are
  * submitted at any time and queue on the host.  Each pgg_server_step

@@ -313,14 +313,8 @@ hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
     return hipSuccess;
 }
 
-}  // namespace
-
-extern "C" {
-
-pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk,
-                               void* hip_stream, pgg_ensemble** out) {
-    if (!out) { eerr("out is NULL"); return PGG_E_INVAL; }
-    *out = nullptr;
+// Parameter checks of pgg_ensemble_create (no device call).
+pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk) {
     if (!reps || n_reps == 0 || n_reps > 65536) { eerr("need 1..65536 replicas"); return PGG_E_INVAL; }
     if (chunk == 0 || chunk > 1024) { eerr("chunk must lie in [1, 1024]"); return PGG_E_INVAL; }
     for (uint32_t k = 0; k < n_reps; ++k) {
@@ -334,6 +328,19 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         const uint32_t w = tiles ? tiles[k] : 0;
         if (w != 0 && (w % 32 != 0 || w + 32 > p.L)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32", k); return PGG_E_INVAL; }
     }
+    return PGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk,
+                               void* hip_stream, pgg_ensemble** out) {
+    if (!out) { eerr("out is NULL"); return PGG_E_INVAL; }
+    *out = nullptr;
+    const pgg_status vs = validate_reps(reps, n_reps, tiles, chunk);
+    if (vs != PGG_OK) return vs;
     pgg_ensemble* e = new (std::nothrow) pgg_ensemble();
     if (!e) { eerr("host allocation failed"); return PGG_E_NOMEM; }
     e->stream = (hipStream_t)hip_stream;
@@ -473,5 +480,104 @@ pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* hos
 }
 
 void pgg_ensemble_destroy(pgg_ensemble* e) { ens_release(e); }
+
+pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps, void* hip_stream,
+                                 uint32_t* tiles_out, uint32_t* chunk_out, double* ms_out) {
+    if (!reps || !tiles_out || !chunk_out) { eerr("NULL argument"); return PGG_E_INVAL; }
+    if (probe_sweeps == 0 || probe_sweeps > 4096) { eerr("probe_sweeps must lie in [1, 4096]"); return PGG_E_INVAL; }
+    const pgg_status vs = validate_reps(reps, n_reps, nullptr, 1);
+    if (vs != PGG_OK) return vs;
+    std::vector<uint32_t> sizes;
+    for (uint32_t k = 0; k < n_reps; ++k)
+        if (std::find(sizes.begin(), sizes.end(), reps[k].L) == sizes.end()) sizes.push_back(reps[k].L);
+    std::map<uint32_t, uint32_t> width;  // current choice per L (0 = automatic)
+    for (uint32_t L : sizes) width[L] = 0;
+    uint32_t chunk = 32;
+    std::vector<uint64_t> fingerprint, nc(n_reps);
+    std::vector<uint32_t> tiles(n_reps);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
+        if (ev0) (void)hipEventDestroy(ev0);
+        eerr("event creation failed");
+        return PGG_E_DEVICE;
+    }
+    // One trial: a fresh ensemble with the current choices; best of two timed runs.
+    auto trial = [&](double* ms) -> pgg_status {
+        for (uint32_t k = 0; k < n_reps; ++k) tiles[k] = width[reps[k].L];
+        pgg_ensemble* e = nullptr;
+        pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.data(), chunk, hip_stream, &e);
+        if (st != PGG_OK) return st;
+        st = pgg_ensemble_sweep(e, 2, nullptr);
+        double best = 1e300;
+        for (int rep = 0; rep < 2 && st == PGG_OK; ++rep) {
+            hipError_t err = hipEventRecord(ev0, e->stream);
+            if (err == hipSuccess) st = pgg_ensemble_sweep(e, probe_sweeps, nullptr);
+            if (err == hipSuccess && st == PGG_OK) err = hipEventRecord(ev1, e->stream);
+            if (err == hipSuccess && st == PGG_OK) err = hipEventSynchronize(ev1);
+            float f = 0.f;
+            if (err == hipSuccess && st == PGG_OK) err = hipEventElapsedTime(&f, ev0, ev1);
+            if (err != hipSuccess) { eerr("autotune timing: %s", hipGetErrorString(err)); st = PGG_E_DEVICE; }
+            best = std::min(best, (double)f / probe_sweeps);
+        }
+        if (st == PGG_OK) st = pgg_ensemble_coop_counts(e, nc.data());
+        pgg_ensemble_destroy(e);
+        if (st != PGG_OK) return st;
+        if (fingerprint.empty()) {
+            fingerprint = nc;
+        } else if (fingerprint != nc) {
+            eerr("autotune: cooperator counts differ between tuning choices");
+            return PGG_E_DEVICE;
+        }
+        *ms = best;
+        return PGG_OK;
+    };
+    double best_ms = 0.0;
+    pgg_status st = trial(&best_ms);
+    for (size_t q = 0; q < sizes.size() && st == PGG_OK; ++q) {
+        const uint32_t L = sizes[q];
+        const uint32_t cap = (L - 32) & ~31u;
+        std::vector<uint32_t> cand;
+        for (uint32_t w = 64; w < cap; w *= 2) cand.push_back(w);
+        if (cap >= 32) cand.push_back(cap);
+        pgg::EnsRep geo;
+        std::memset(&geo, 0, sizeof(geo));
+        pgg::ens_geometry(geo, (int)L, 0);
+        uint32_t best_w = width[L];
+        for (uint32_t w : cand) {
+            if (w == (uint32_t)geo.segw) continue;  // the automatic width, already timed
+            width[L] = w;
+            double ms = 0.0;
+            st = trial(&ms);
+            if (st != PGG_OK) break;
+            if (ms < best_ms) { best_ms = ms; best_w = w; }
+        }
+        width[L] = best_w;
+    }
+    const uint32_t chunks[] = {8, 16, 32, 64, 128};
+    uint32_t best_chunk = chunk;
+    for (uint32_t c : chunks) {
+        if (st != PGG_OK || c == best_chunk) continue;
+        chunk = c;
+        double ms = 0.0;
+        st = trial(&ms);
+        if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_chunk = c; }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (st != PGG_OK) return st;
+    for (uint32_t k = 0; k < n_reps; ++k) {
+        uint32_t w = width[reps[k].L];
+        if (w == 0) {  // the automatic width, made explicit
+            pgg::EnsRep rp;
+            std::memset(&rp, 0, sizeof(rp));
+            pgg::ens_geometry(rp, (int)reps[k].L, 0);
+            w = (uint32_t)rp.segw;
+        }
+        tiles_out[k] = w;
+    }
+    *chunk_out = best_chunk;
+    if (ms_out) *ms_out = best_ms;
+    return PGG_OK;
+}
 
 }  // extern "C"

@@ -33,6 +33,7 @@ EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_set_strip_wait", "pgg_destroy",
            "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
            "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy",
+           "pgg_ensemble_autotune",
            "pgg_server_job_bytes", "pgg_server_create", "pgg_server_submit", "pgg_server_step",
            "pgg_server_completed", "pgg_server_job_state", "pgg_server_job_result", "pgg_server_stats",
            "pgg_server_destroy")
@@ -91,6 +92,8 @@ def load():
         "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_read_lattice": (ctypes.c_int, [vp, ctypes.c_uint32, u8p]),
         "pgg_ensemble_destroy": (None, [vp]),
+        "pgg_ensemble_autotune": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, vp, u32p, u32p,
+                                                 P(ctypes.c_double)]),
         "pgg_server_job_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
         "pgg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                              vp, P(vp)]),
@@ -268,6 +271,27 @@ class Sim:
             pass
 
 
+def _replica_params(replicas):
+    arr = (PggParams * len(replicas))()
+    for k, rp in enumerate(replicas):
+        arr[k] = make_params(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5),
+                             rp.get("seed", 1), "bits", "auto")
+    return arr
+
+
+def ensemble_autotune(replicas, probe_sweeps=8, stream=None):
+    """pgg_ensemble_autotune: (tiles per replica, chunk, ms per sweep)."""
+    n = len(replicas)
+    arr = _replica_params(replicas)
+    tiles = np.zeros(n, dtype=np.uint32)
+    chunk = ctypes.c_uint32()
+    ms = ctypes.c_double()
+    _check(load().pgg_ensemble_autotune(arr, n, int(probe_sweeps), _stream_handle(stream),
+                                        tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                        ctypes.byref(chunk), ctypes.byref(ms)))
+    return tiles, int(chunk.value), float(ms.value)
+
+
 class Ensemble:
     """Many replicas advanced together (pgg_ensemble_* calls).
 
@@ -278,10 +302,7 @@ class Ensemble:
     def __init__(self, replicas, tiles=None, chunk=32, stream=None):
         lib = load()
         n = len(replicas)
-        arr = (PggParams * n)()
-        for k, rp in enumerate(replicas):
-            arr[k] = make_params(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5),
-                                 rp.get("seed", 1), "bits", "auto")
+        arr = _replica_params(replicas)
         self.L = [int(rp["L"]) for rp in replicas]
         self.n = n
         tl = None

@@ -87,3 +87,26 @@ def test_engine_has_no_cpu_fallback():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "pgg_ref_" not in text, f
+
+
+@pytest.mark.parametrize("bad", [dict(L=60), dict(L=130), dict(r=-1.0), dict(K=0.0), dict(p0=2.0)])
+def test_ensemble_calls_reject_invalid_replicas_before_touching_the_device(pgg, bad):
+    reps = [dict(L=128, r=3.8, seed=1), dict(L=256, r=3.7, seed=2)]
+    reps[1].update(bad)
+    with pytest.raises(pgg.PggError) as e:
+        pgg.Ensemble(reps)
+    assert e.value.status == pgg.PGG_E_INVAL
+    with pytest.raises(pgg.PggError) as e:
+        pgg.ensemble_autotune(reps)
+    assert e.value.status == pgg.PGG_E_INVAL
+    assert "replica 1" in pgg.load().pgg_last_error().decode()
+
+
+def test_ensemble_autotune_rejects_bad_arguments(pgg):
+    reps = [dict(L=128, r=3.8, seed=1)]
+    for probe in (0, 4097):
+        with pytest.raises(pgg.PggError) as e:
+            pgg.ensemble_autotune(reps, probe_sweeps=probe)
+        assert e.value.status == pgg.PGG_E_INVAL
+    lib = pgg.load()
+    assert lib.pgg_ensemble_autotune(None, 1, 4, None, None, None, None) == pgg.PGG_E_INVAL

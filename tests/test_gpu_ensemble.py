@@ -94,3 +94,26 @@ def test_invalid_replicas_are_rejected(pgg):
         assert e.value.status == pgg.PGG_E_INVAL
     with pytest.raises(pgg.PggError):
         pgg.Ensemble([dict(L=128, r=3.8, seed=1)], tiles=[48])
+
+
+def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
+    """The autotuner times width and chunk choices on trial ensembles (it fails
+    itself if any two choices give different counts); the chosen settings are
+    valid and reproduce the default ensemble and the oracle."""
+    reps = [dict(L=128, r=3.8, seed=11), dict(L=256, r=3.7, seed=12), dict(L=128, r=3.9, seed=13),
+            dict(L=256, r=3.65, seed=14), dict(L=96, r=4.0, seed=15)]
+    say("autotune over", [rp["L"] for rp in reps])
+    tiles, chunk, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
+    assert chunk in (8, 16, 32, 64, 128) and ms > 0.0
+    by_L = {}
+    for rp, w in zip(reps, tiles):
+        assert w % 32 == 0 and 32 <= w <= rp["L"] - 32
+        by_L.setdefault(rp["L"], set()).add(int(w))
+    assert all(len(ws) == 1 for ws in by_L.values())
+    n = 21
+    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk) as a, pgg.Ensemble(reps) as b:
+        ca, cb = a.sweep(n), b.sweep(n)
+        assert np.array_equal(ca, cb)
+        ref, _, counts = oracle_lib.run(256, 3.7, 0.5, 0.5, 12, n)
+        assert np.array_equal(ca[1], counts)
+        assert np.array_equal(a.read_lattice(1), ref)
