@@ -91,17 +91,17 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     pgg_ensemble_autotune (untimed, before the timed run)."""
     reps = wl.ensemble_replicas(sweeps=sweeps)
     total = float(sum(rp["L"] ** 2 for rp in reps)) * sweeps
-    tiles, tuned = None, None
+    tiles, tuned, wpg = None, None, 0
     if autotune:
         t0 = time.perf_counter()
-        tiles, chunk, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
+        tiles, chunk, wpg, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
         tuned = {"tiles_by_L": {int(rp["L"]): int(w) for rp, w in zip(reps, tiles)}, "chunk": chunk,
-                 "probe_ms_per_sweep": ms, "tuning_s": time.perf_counter() - t0}
-    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream)
+                 "waves_per_group": wpg, "probe_ms_per_sweep": ms, "tuning_s": time.perf_counter() - t0}
+    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg)
     ens.sweep(min(chunk, sweeps), want_counts=False)  # first replay builds the graph
     torch.cuda.synchronize()
     ens.close()
-    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream)
+    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ens.sweep(sweeps, want_counts=False)

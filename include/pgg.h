@@ -222,12 +222,16 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
  *              <= L - 32; 0 = automatic) or NULL for all automatic.
  *   chunk      sweeps per graph replay, 1..1024 (device counters hold
  *              chunk x n_reps x 4 KiB).
+ *   waves_per_group  segment waves per workgroup: 2, 4 or 8 (0 = 4).  A
+ *              workgroup serves one replica and shares one copy of its
+ *              threshold table; each replica's waves are padded to whole
+ *              workgroups.
  *   hip_stream stream to order the work on; NULL: the ensemble creates and
  *              owns a stream of default priority (graphs cannot capture the
  *              null stream).
  * Synchronises the stream once. */
 pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles,
-                               uint32_t chunk, void* hip_stream, pgg_ensemble** out);
+                               uint32_t chunk, uint32_t waves_per_group, void* hip_stream, pgg_ensemble** out);
 
 /* Advance every replica n_sweeps sweeps.  counts: NULL, or host array of
  * n_reps rows of n_sweeps entries receiving N_C after each sweep (row k is
@@ -248,25 +252,27 @@ pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* hos
 void pgg_ensemble_destroy(pgg_ensemble* e);
 
 /* Autotune the batched launch for a set of replicas: the segment width of
- * each distinct L and the chunk length of a graph replay.  Results never
- * depend on either; only the speed does.
+ * each distinct L, the waves per workgroup and the chunk length of a graph
+ * replay.  Results never depend on them; only the speed does.
  *   reps, n_reps  as for pgg_ensemble_create.
  *   probe_sweeps  sweeps timed per trial, 1..4096 (after 2 untimed ones).
  *   hip_stream    as for pgg_ensemble_create.
  *   tiles_out     host array of n_reps: the chosen width of each replica
  *                 (equal for equal L).
  *   chunk_out     the chosen chunk length.
+ *   wpg_out       the chosen waves per workgroup.
  *   ms_out        NULL, or the best time per sweep of the whole ensemble.
  * Trials run on trial ensembles created from reps (fresh initial states
  * each): first the width of each distinct L in turn over the doublings
  * 64, 128, ... below L - 32 plus L - 32 rounded down to a multiple of 32,
- * the other sizes held at their best so far, then the chunk over
- * 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
+ * the other sizes held at their best so far, then the waves per workgroup
+ * over 2, 4, 8, then the chunk over 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
  * trial's final cooperator counts must equal the first trial's, else
  * PGG_E_DEVICE with a message (a tuning-dependent result would be a bug).
  * Needs the device memory of one trial ensemble at chunk 128. */
 pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps,
-                                 void* hip_stream, uint32_t* tiles_out, uint32_t* chunk_out, double* ms_out);
+                                 void* hip_stream, uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out,
+                                 double* ms_out);
 
 /* ------------------------------------------------------------------------
  * Job server: continuous batching of simulation jobs on one GPU.  Jobs are

@@ -35,14 +35,15 @@ __device__ __forceinline__ int replica_of_wave(const EnsRep* __restrict__ reps, 
     return lo;
 }
 
-__global__ void __launch_bounds__(kSegmentThreads)
+template <int WPG>
+__global__ void __launch_bounds__(64 * WPG)
 k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
     extern __shared__ uint32_t smem[];
-    __shared__ int s_part[2 * kWavesPerGroup];
+    __shared__ int s_part[2 * WPG];
     __shared__ int s_rep;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
-    const int first_wave = blockIdx.x * kWavesPerGroup;
+    const int first_wave = blockIdx.x * WPG;
     if (threadIdx.x == 0) s_rep = replica_of_wave(reps, n_reps, first_wave);
     __syncthreads();
     const EnsRep rp = reps[s_rep];
@@ -67,14 +68,14 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
     for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
     if (lane == 0) {
         s_part[wid] = my_delta;
-        s_part[kWavesPerGroup + wid] = my_drawn;
+        s_part[WPG + wid] = my_drawn;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int dsum = 0, nsum = 0;
-        for (int k = 0; k < kWavesPerGroup; ++k) {
+        for (int k = 0; k < WPG; ++k) {
             dsum += s_part[k];
-            nsum += s_part[kWavesPerGroup + k];
+            nsum += s_part[WPG + k];
         }
         if (dsum)
             atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
@@ -187,14 +188,16 @@ void ens_geometry(EnsRep& rp, int L, int segw) {
     rp.nseg = (L + segw - 1) / segw;
 }
 
-int ens_waves(const EnsRep& rp) {
+int ens_waves(const EnsRep& rp, int wpg) {
     const int wv = (rp.L / 4) * rp.nseg;
-    return (wv + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
+    return (wv + wpg - 1) / wpg * wpg;
 }
 
-size_t ens_lds_bytes(int max_segw) {
-    return (160 + (size_t)kWavesPerGroup * seg_wave_words(max_segw)) * sizeof(uint32_t);
+size_t ens_lds_bytes(int max_segw, int wpg) {
+    return (160 + (size_t)wpg * seg_wave_words(max_segw)) * sizeof(uint32_t);
 }
+
+bool ens_wpg_valid(int wpg) { return wpg == 2 || wpg == 4 || wpg == 8; }
 
 hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_active, hipStream_t st) {
     if (set_active) {
@@ -207,9 +210,14 @@ hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_
 }
 
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_ens_segment, dim3(total_waves / kWavesPerGroup), dim3(kSegmentThreads), lds, st, d_reps,
-                       n, a, q);
+                              hipStream_t st, int wpg) {
+    const dim3 grid(total_waves / wpg), block(64 * wpg);
+    switch (wpg) {
+        case 2: hipLaunchKernelGGL(k_ens_segment<2>, grid, block, lds, st, d_reps, n, a, q); break;
+        case 4: hipLaunchKernelGGL(k_ens_segment<4>, grid, block, lds, st, d_reps, n, a, q); break;
+        case 8: hipLaunchKernelGGL(k_ens_segment<8>, grid, block, lds, st, d_reps, n, a, q); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -224,10 +232,11 @@ hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* 
 }
 
 hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
-                            bool set_active, unsigned long long* counts, hipStream_t st) {
+                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg) {
     hipError_t err = launch_ens_begin(d_reps, n, len, chunk, set_active, st);
     for (int q = 0; err == hipSuccess && q < len; ++q)
-        for (int a = 0; err == hipSuccess && a < 4; ++a) err = launch_ens_residue(d_reps, n, total_waves, lds, a, q, st);
+        for (int a = 0; err == hipSuccess && a < 4; ++a)
+            err = launch_ens_residue(d_reps, n, total_waves, lds, a, q, st, wpg);
     if (err != hipSuccess) return err;
     return launch_ens_end(d_reps, n, chunk, counts, st);
 }
@@ -245,6 +254,7 @@ struct pgg_ensemble {
     int device = 0;
     int n = 0;
     int chunk = 32;          // sweeps per graph replay
+    int wpg = pgg::kWavesPerGroup;  // waves (segments of one replica) per workgroup
     int total_waves = 0;
     size_t lds = 0;
     std::vector<pgg::EnsRep> host_reps;
@@ -291,7 +301,7 @@ void ens_release(pgg_ensemble* e) {
 
 hipError_t enqueue_chunk(pgg_ensemble* e, int len) {
     return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts,
-                                 e->stream);
+                                 e->stream, e->wpg);
 }
 
 hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
@@ -336,11 +346,13 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
 extern "C" {
 
 pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk,
-                               void* hip_stream, pgg_ensemble** out) {
+                               uint32_t waves_per_group, void* hip_stream, pgg_ensemble** out) {
     if (!out) { eerr("out is NULL"); return PGG_E_INVAL; }
     *out = nullptr;
     const pgg_status vs = validate_reps(reps, n_reps, tiles, chunk);
     if (vs != PGG_OK) return vs;
+    const int wpg = waves_per_group ? (int)waves_per_group : pgg::kWavesPerGroup;
+    if (!pgg::ens_wpg_valid(wpg)) { eerr("waves_per_group must be 0, 2, 4 or 8"); return PGG_E_INVAL; }
     pgg_ensemble* e = new (std::nothrow) pgg_ensemble();
     if (!e) { eerr("host allocation failed"); return PGG_E_NOMEM; }
     e->stream = (hipStream_t)hip_stream;
@@ -350,6 +362,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     }
     e->n = (int)n_reps;
     e->chunk = (int)chunk;
+    e->wpg = wpg;
     if (hipGetDevice(&e->device) != hipSuccess) { eerr("no HIP device"); ens_release(e); return PGG_E_DEVICE; }
 
     // Layout: lattices back to back (256-byte aligned), tables, per-replica waves.
@@ -367,13 +380,13 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         rp.k1 = (uint32_t)(p.seed >> 32);
         rp.t0 = 0;
         rp.wave_base = waves;
-        waves += pgg::ens_waves(rp);
+        waves += pgg::ens_waves(rp, wpg);
         lat_off[k] = lat_words;
         lat_words += 2 * (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);  // lat and lat2
         max_segw = std::max(max_segw, rp.segw);
     }
     e->total_waves = waves;
-    e->lds = pgg::ens_lds_bytes(max_segw);
+    e->lds = pgg::ens_lds_bytes(max_segw, wpg);
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t err = hipMalloc(ptr, bytes);
@@ -482,8 +495,8 @@ pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* hos
 void pgg_ensemble_destroy(pgg_ensemble* e) { ens_release(e); }
 
 pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps, void* hip_stream,
-                                 uint32_t* tiles_out, uint32_t* chunk_out, double* ms_out) {
-    if (!reps || !tiles_out || !chunk_out) { eerr("NULL argument"); return PGG_E_INVAL; }
+                                 uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out, double* ms_out) {
+    if (!reps || !tiles_out || !chunk_out || !wpg_out) { eerr("NULL argument"); return PGG_E_INVAL; }
     if (probe_sweeps == 0 || probe_sweeps > 4096) { eerr("probe_sweeps must lie in [1, 4096]"); return PGG_E_INVAL; }
     const pgg_status vs = validate_reps(reps, n_reps, nullptr, 1);
     if (vs != PGG_OK) return vs;
@@ -492,7 +505,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         if (std::find(sizes.begin(), sizes.end(), reps[k].L) == sizes.end()) sizes.push_back(reps[k].L);
     std::map<uint32_t, uint32_t> width;  // current choice per L (0 = automatic)
     for (uint32_t L : sizes) width[L] = 0;
-    uint32_t chunk = 32;
+    uint32_t chunk = 32, wpg = (uint32_t)pgg::kWavesPerGroup;
     std::vector<uint64_t> fingerprint, nc(n_reps);
     std::vector<uint32_t> tiles(n_reps);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -505,7 +518,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     auto trial = [&](double* ms) -> pgg_status {
         for (uint32_t k = 0; k < n_reps; ++k) tiles[k] = width[reps[k].L];
         pgg_ensemble* e = nullptr;
-        pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.data(), chunk, hip_stream, &e);
+        pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.data(), chunk, wpg, hip_stream, &e);
         if (st != PGG_OK) return st;
         st = pgg_ensemble_sweep(e, 2, nullptr);
         double best = 1e300;
@@ -553,6 +566,16 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         }
         width[L] = best_w;
     }
+    const uint32_t wpgs[] = {2, 4, 8};
+    uint32_t best_wpg = wpg;
+    for (uint32_t g : wpgs) {
+        if (st != PGG_OK || g == best_wpg) continue;
+        wpg = g;
+        double ms = 0.0;
+        st = trial(&ms);
+        if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_wpg = g; }
+    }
+    wpg = best_wpg;
     const uint32_t chunks[] = {8, 16, 32, 64, 128};
     uint32_t best_chunk = chunk;
     for (uint32_t c : chunks) {
@@ -576,6 +599,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         tiles_out[k] = w;
     }
     *chunk_out = best_chunk;
+    *wpg_out = best_wpg;
     if (ms_out) *ms_out = best_ms;
     return PGG_OK;
 }

@@ -79,7 +79,7 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 // per row segment.  Out of place within a sweep: launch a reads residues < a
 // from the buffer it writes and the rest from the other one; after the 4
 // launches of a sweep the written buffer holds the whole lattice.
-constexpr int kSegmentThreads = 256;
+constexpr int kWavesPerGroup = 4;  // default waves (segments) per workgroup; 2, 4 or 8
 
 // Ensemble replica descriptor (pgg_ensemble.hip): replica lattice, its
 // threshold table, its per-sweep counters (chunk x kSweepWords), geometry,
@@ -96,24 +96,24 @@ struct EnsRep {
     uint32_t k0, k1, t0;
 };
 
-constexpr int kWavesPerGroup = kSegmentThreads / 64;
 // Fill in segw, nseg, stride, nw of a replica of side L (segw 0 = automatic).
 void ens_geometry(EnsRep& rp, int L, int segw);
-// Waves of one launch for this replica, padded to whole workgroups.
-int ens_waves(const EnsRep& rp);
-size_t ens_lds_bytes(int max_segw);
+// Waves of one launch for this replica, padded to whole workgroups of wpg waves.
+int ens_waves(const EnsRep& rp, int wpg = kWavesPerGroup);
+size_t ens_lds_bytes(int max_segw, int wpg = kWavesPerGroup);
+bool ens_wpg_valid(int wpg);
 // Enqueue one chunk of `len` sweeps (len <= chunk) for the n replicas of
 // d_reps on st: (if set_active) n_active = len for every replica, zero their
 // counters, 4 segment launches per sweep (replicas run q < n_active), the
 // per-replica scan into counts[n][chunk] (and rp.nc), the copy of the final
 // state back to rp.lat when it lies in rp.lat2, the advance of t0.
 hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
-                            bool set_active, unsigned long long* counts, hipStream_t st);
+                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg = kWavesPerGroup);
 // The same chunk in three parts, for callers that bracket each segment
 // launch (residue a of sweep q of the chunk) with events of their own.
 hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_active, hipStream_t st);
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
-                              hipStream_t st);
+                              hipStream_t st, int wpg = kWavesPerGroup);
 hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st);
 // Set the sweep index t0 of every replica (graph-safe, no host memory).
 hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st);

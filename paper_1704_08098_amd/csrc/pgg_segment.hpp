@@ -60,15 +60,9 @@ __device__ __forceinline__ uint32_t global_window(const uint32_t* __restrict__ r
     return out;
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
-__device__ __forceinline__ int wave_inclusive_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
-    }
-    return v;
+// Number of set bits of a wave-wide mask below the calling lane.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 }  // namespace seg
@@ -162,8 +156,9 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         const int m = 9 - 3 * b;
         const int lo = 64 - m, hi = 64 + (e - s) + m;
         const int wlo = lo >> 5, whi = (hi + 31) >> 5;
-        // 1. candidates per word, 2. compacted list.
-        int total = 0;
+        // 1. candidates per word (8 class-b bits, at 4q + b), 2. compacted
+        // list: one ballot per bit position, entries placed by lane rank.
+        int total = 0;  // wave-uniform
         for (int wbase = wlo; wbase < whi; wbase += 64) {
             const int w = wbase + lane;
             uint32_t act = 0;
@@ -177,15 +172,15 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
                 if (p0 < lo) act &= 0xFFFFFFFFu << (lo - p0);
                 if (p0 + 32 > hi) act &= (hi - p0) >= 32 ? 0xFFFFFFFFu : ((1u << (hi - p0)) - 1u);
             }
-            const int cnt = __popc(act);
-            const int incl = wave_inclusive_scan(cnt);
-            int pos = total + incl - cnt;
-            while (act) {
-                const int bit = __ffs(act) - 1;
-                act &= act - 1u;
-                list[pos++] = (uint32_t)(32 * w + bit);
+            act >>= b;
+            const uint32_t base = (uint32_t)(32 * w + b);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool on = (act >> (4 * q)) & 1u;
+                const unsigned long long m = __ballot(on);
+                if (on) list[total + lanes_below(m)] = base + 4u * (uint32_t)q;
+                total += __popcll(m);
             }
-            total += __shfl(incl, 63, 64);
         }
         __builtin_amdgcn_wave_barrier();
         my_drawn += lane == 0 ? total : 0;

@@ -85,15 +85,15 @@ def load():
         "pgg_set_strip_wait": (ctypes.c_int, [vp, ctypes.c_double]),
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
-        "pgg_ensemble_create": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, u32p, ctypes.c_uint32, vp,
-                                               P(vp)]),
+        "pgg_ensemble_create": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, u32p, ctypes.c_uint32,
+                                               ctypes.c_uint32, vp, P(vp)]),
         "pgg_ensemble_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, u64p]),
         "pgg_ensemble_coop_counts": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_read_lattice": (ctypes.c_int, [vp, ctypes.c_uint32, u8p]),
         "pgg_ensemble_destroy": (None, [vp]),
         "pgg_ensemble_autotune": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, vp, u32p, u32p,
-                                                 P(ctypes.c_double)]),
+                                                 u32p, P(ctypes.c_double)]),
         "pgg_server_job_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
         "pgg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                              vp, P(vp)]),
@@ -280,16 +280,17 @@ def _replica_params(replicas):
 
 
 def ensemble_autotune(replicas, probe_sweeps=8, stream=None):
-    """pgg_ensemble_autotune: (tiles per replica, chunk, ms per sweep)."""
+    """pgg_ensemble_autotune: (tiles per replica, chunk, waves per group, ms per sweep)."""
     n = len(replicas)
     arr = _replica_params(replicas)
     tiles = np.zeros(n, dtype=np.uint32)
     chunk = ctypes.c_uint32()
+    wpg = ctypes.c_uint32()
     ms = ctypes.c_double()
     _check(load().pgg_ensemble_autotune(arr, n, int(probe_sweeps), _stream_handle(stream),
                                         tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
-                                        ctypes.byref(chunk), ctypes.byref(ms)))
-    return tiles, int(chunk.value), float(ms.value)
+                                        ctypes.byref(chunk), ctypes.byref(wpg), ctypes.byref(ms)))
+    return tiles, int(chunk.value), int(wpg.value), float(ms.value)
 
 
 class Ensemble:
@@ -297,9 +298,10 @@ class Ensemble:
 
     replicas: sequence of dicts with L, r and optionally K, p0, seed.
     tiles: optional per-replica segment widths (0 = automatic).
+    waves_per_group: segment waves per workgroup, 2, 4 or 8 (0 = 4).
     """
 
-    def __init__(self, replicas, tiles=None, chunk=32, stream=None):
+    def __init__(self, replicas, tiles=None, chunk=32, stream=None, waves_per_group=0):
         lib = load()
         n = len(replicas)
         arr = _replica_params(replicas)
@@ -313,7 +315,8 @@ class Ensemble:
         h = ctypes.c_void_p()
         _check(lib.pgg_ensemble_create(arr, n,
                                        tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None
-                                       else None, int(chunk), _stream_handle(stream), ctypes.byref(h)))
+                                       else None, int(chunk), int(waves_per_group), _stream_handle(stream),
+                                       ctypes.byref(h)))
         self.handle = h
 
     def sweep(self, n_sweeps, want_counts=True):

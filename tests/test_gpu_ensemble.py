@@ -73,6 +73,20 @@ def test_tiles_do_not_change_results(pgg, tile):
             assert np.array_equal(ens.read_lattice(k), ref[k][1])
 
 
+@pytest.mark.parametrize("wpg", [2, 4, 8])
+def test_waves_per_group_do_not_change_results(pgg, wpg):
+    """Uneven replicas whose wave counts are not multiples of the group size
+    (padding waves idle), each equal to its solo run."""
+    reps = [dict(L=100, r=3.85, seed=31), dict(L=132, r=4.2, seed=32), dict(L=64, r=3.7, seed=33)]
+    ref = [_solo(pgg, rp, 9) for rp in reps]
+    say("waves per group", wpg)
+    with pgg.Ensemble(reps, chunk=4, waves_per_group=wpg) as ens:
+        c = ens.sweep(9)
+        for k in range(len(reps)):
+            assert np.array_equal(c[k], ref[k][0]), k
+            assert np.array_equal(ens.read_lattice(k), ref[k][1]), k
+
+
 def test_full_ensemble_sample(pgg):
     """The 256-replica ensemble (L = 128..1024), 40 sweeps: sampled replicas
     equal their solo runs; every count equals a recount of the lattice."""
@@ -94,6 +108,9 @@ def test_invalid_replicas_are_rejected(pgg):
         assert e.value.status == pgg.PGG_E_INVAL
     with pytest.raises(pgg.PggError):
         pgg.Ensemble([dict(L=128, r=3.8, seed=1)], tiles=[48])
+    for wpg in (1, 3, 16):
+        with pytest.raises(pgg.PggError):
+            pgg.Ensemble([dict(L=128, r=3.8, seed=1)], waves_per_group=wpg)
 
 
 def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
@@ -103,15 +120,15 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
     reps = [dict(L=128, r=3.8, seed=11), dict(L=256, r=3.7, seed=12), dict(L=128, r=3.9, seed=13),
             dict(L=256, r=3.65, seed=14), dict(L=96, r=4.0, seed=15)]
     say("autotune over", [rp["L"] for rp in reps])
-    tiles, chunk, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
-    assert chunk in (8, 16, 32, 64, 128) and ms > 0.0
+    tiles, chunk, wpg, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
+    assert chunk in (8, 16, 32, 64, 128) and wpg in (2, 4, 8) and ms > 0.0
     by_L = {}
     for rp, w in zip(reps, tiles):
         assert w % 32 == 0 and 32 <= w <= rp["L"] - 32
         by_L.setdefault(rp["L"], set()).add(int(w))
     assert all(len(ws) == 1 for ws in by_L.values())
     n = 21
-    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk) as a, pgg.Ensemble(reps) as b:
+    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk, waves_per_group=wpg) as a, pgg.Ensemble(reps) as b:
         ca, cb = a.sweep(n), b.sweep(n)
         assert np.array_equal(ca, cb)
         ref, _, counts = oracle_lib.run(256, 3.7, 0.5, 0.5, 12, n)
