@@ -118,4 +118,13 @@ __device__ __forceinline__ int sigma_bits(uint32_t a2, uint32_t a1, uint32_t b, 
     return ones + 2 * twos + 5 * fives;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b to XCD
+// b mod 8), each with its own L2.  This bijection of [0, n) makes XCD x run
+// a contiguous range of logical blocks: x * (n / 8) + min(x, n mod 8) + b / 8.
+__device__ __forceinline__ int xcd_major(int b, int n) {
+    const int x = b & 7, k = b >> 3;
+    const int q = n >> 3, rem = n & 7;
+    return x * q + min(x, rem) + k;
+}
+
 }  // namespace pgg

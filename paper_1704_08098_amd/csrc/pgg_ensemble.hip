@@ -43,7 +43,8 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
     __shared__ int s_rep;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
-    const int first_wave = blockIdx.x * WPG;
+    // neighbouring rows (which share window rows) run on the same XCD's L2
+    const int first_wave = xcd_major((int)blockIdx.x, (int)gridDim.x) * WPG;
     if (threadIdx.x == 0) s_rep = replica_of_wave(reps, n_reps, first_wave);
     __syncthreads();
     const EnsRep rp = reps[s_rep];

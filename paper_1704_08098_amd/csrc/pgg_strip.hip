@@ -51,14 +51,6 @@ __device__ __forceinline__ void flag_store(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Block -> task so that consecutive tasks (neighbouring strips) land on the
-// same XCD: workgroups are dispatched round-robin over the 8 XCDs.
-__device__ __forceinline__ int task_of_block(int b, int n) {
-    const int x = b & 7, k = b >> 3;
-    const int q = n >> 3, rem = n & 7;
-    return x * q + min(x, rem) + k;
-}
-
 }  // namespace
 
 __global__ void __launch_bounds__(kStripThreads)
@@ -69,7 +61,7 @@ k_strip(const StripTask* __restrict__ tasks, int n_tasks, uint64_t* __restrict__
     __shared__ int s_delta;
     __shared__ int s_ok;
 
-    const int me = task_of_block((int)blockIdx.x, n_tasks);
+    const int me = xcd_major((int)blockIdx.x, n_tasks);  // neighbouring strips share an XCD
     const StripTask tk = tasks[me];
     const int L = tk.L, nw = tk.nw, ldw = nw + 1, H = tk.H, r0 = tk.r0, q4 = L >> 2;
     const int GQ = G * q4;  // list capacity per class
