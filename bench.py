@@ -60,8 +60,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0):
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile)
+def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0, group=0):
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
     sim.sweep(warmup, want_counts=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -73,9 +73,9 @@ def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, t
     return dt, nc
 
 
-def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0):
+def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0, group=0):
     """Same trajectory with every sweep-kernel launch bracketed by events."""
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile)
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
     sim.sweep(warmup, want_counts=False)
     sim.set_kernel_timing(True)
     sim.sweep(steps, want_counts=False)
@@ -157,7 +157,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel", default="segment",
                     choices=["segment", "strip", "rowband_staged", "rowband_compact", "rowband", "colour"])
-    ap.add_argument("--tile", type=int, default=0, help="strip height / rows per band (0 = auto)")
+    ap.add_argument("--tile", type=int, default=0, help="segment width / strip height / rows per band (0 = auto)")
+    ap.add_argument("--group", type=int, default=0, help="segment kernel: waves per workgroup (0 = 4)")
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -197,7 +198,7 @@ def main():
 
     log("timed pass: L=%d r=%g kernel=%s warmup=%d steps=%d" % (L, r, args.kernel, args.warmup, args.steps))
     dt, nc_end = time_sweeps(pgg, torch, L, r, seed, args.kernel, layout, args.warmup, args.steps, stream,
-                             args.tile)
+                             args.tile, args.group)
     updates = float(L) * L * args.steps
     value = updates / dt
 
@@ -212,7 +213,7 @@ def main():
 
     log("kernel-timing pass")
     launches, kms, drawn = kernel_pass(pgg, torch, L, r, seed, args.kernel, layout, args.warmup,
-                                       args.steps, stream, args.tile)
+                                       args.steps, stream, args.tile, args.group)
     avg_ms = kms / max(launches, 1)
     sites_per_launch = updates / max(launches, 1)  # the strip kernel: one launch per timed call
     if args.kernel == "colour":
@@ -256,7 +257,7 @@ def main():
                                "(seed %d), sweeps %d..%d timed" % (L, L, r, seed, args.warmup,
                                                                  args.warmup + args.steps - 1),
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
-                   "kernel": args.kernel, "parallelism": "single GPU"},
+                   "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
         "roofline": roofline, "hbm": hbm, "dense": dense, "batched": batched, "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }

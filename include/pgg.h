@@ -121,6 +121,9 @@ typedef struct {
                         columns per segment (a multiple of 32, <= L - 32).
                         A value the kernel cannot use is PGG_E_INVAL.  Results
                         never depend on it.                                   */
+    uint32_t group;  /* SEGMENT: segment waves per workgroup, 2, 4 or 8
+                        (0 = 4); other kernels: must be 0.  Results never
+                        depend on it.                                         */
 } pgg_params;
 
 typedef struct pgg_sim pgg_sim; /* opaque handle */

@@ -58,6 +58,7 @@ struct pgg_sim {
     std::vector<hipGraph_t> graph_defs;
     int seg_waves = 0;
     size_t seg_lds = 0;
+    int wpg = pgg::kWavesPerGroup;
     int stride = 0;  // bits layout: 32-bit words per row
     int kernel = PGG_KERNEL_COLOUR;
     int R = 1;       // rows per workgroup (row-band kernels)
@@ -101,12 +102,16 @@ int choose_R(uint32_t L) {
 
 // Columns per segment: about 8 waves per SIMD at large L, at least 128
 // columns (the 18-column margins stay cheap), at most L - 32.
-int choose_segw(uint32_t L) {
-    long w = ((long)L * (long)L / 32768) & ~31L;
+// Columns per segment: about L^2 / 16384 (so a launch has >= 4 waves per
+// SIMD), at least 128, at most L - 32 and L / 2, and small enough that the
+// workgroup's LDS fits.
+int choose_segw(uint32_t L, int wpg) {
+    long w = ((long)L * (long)L / 16384) & ~31L;
     if (w < 128) w = 128;
     const long cap = ((long)L - 32) & ~31L;
     if (w > cap) w = cap;
     if (w > (long)L / 2 && L >= 128) w = ((long)L / 2) & ~31L;
+    while (w > 32 && pgg::ens_lds_bytes((int)w, wpg) > pgg::kMaxDynamicLds) w -= 32;
     if (w < 32) w = 32;
     return (int)w;
 }
@@ -123,6 +128,8 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_INT8 && p->layout != PGG_LAYOUT_BITS) { *why = "unknown layout"; return false; }
     const uint32_t tr = p->tile;
+    const bool segment = p->kernel == PGG_KERNEL_SEGMENT || (p->kernel == PGG_KERNEL_AUTO && p->layout == PGG_LAYOUT_BITS && p->L >= 64);
+    if (p->group != 0 && !segment) { *why = "group applies to the segment kernel only"; return false; }
     switch (p->kernel) {
         case PGG_KERNEL_AUTO:
             if (tr != 0) { *why = "tile needs an explicit kernel"; return false; }
@@ -143,11 +150,18 @@ bool params_valid(const pgg_params* p, const char** why) {
             if (lds > pgg::kMaxDynamicLds) { *why = "the kernel's LDS footprint does not fit at this L and tile"; return false; }
             break;
         }
-        case PGG_KERNEL_SEGMENT:
+        case PGG_KERNEL_SEGMENT: {
             if (p->layout != PGG_LAYOUT_BITS) { *why = "the segment kernel needs the bits layout"; return false; }
             if (p->L < 64) { *why = "the segment kernel needs L >= 64"; return false; }
             if (tr != 0 && (tr % 32 != 0 || tr + 32 > p->L)) { *why = "segment tile must be a multiple of 32 and <= L - 32"; return false; }
+            const int wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
+            if (!pgg::ens_wpg_valid(wpg)) { *why = "group must be 0, 2, 4 or 8"; return false; }
+            if (pgg::ens_lds_bytes(tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::kMaxDynamicLds) {
+                *why = "the segment kernel's LDS footprint does not fit at this tile and group";
+                return false;
+            }
             break;
+        }
         case PGG_KERNEL_STRIP:
             if (p->layout != PGG_LAYOUT_BITS) { *why = "the strip kernel needs the bits layout"; return false; }
             if (tr != 0 && (tr < 4 || tr > p->L)) { *why = "strip tile must lie in [4, L]"; return false; }
@@ -339,8 +353,8 @@ pgg_status plan_segment_graph(pgg_sim* s) {
     rp.delta = s->d_gdelta;
     rp.nc = s->d_nc;
     rp.drawn = nullptr;
-    s->seg_waves = pgg::ens_waves(rp);
-    s->seg_lds = pgg::ens_lds_bytes(rp.segw);
+    s->seg_waves = pgg::ens_waves(rp, s->wpg);
+    s->seg_lds = pgg::ens_lds_bytes(rp.segw, s->wpg);
     const pgg::EnsRep both[2] = {rp, rp};
     e = hipMemcpy(s->d_rep, both, sizeof(both), hipMemcpyHostToDevice);
     if (e != hipSuccess) { set_err("segment graph descriptor: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
@@ -356,7 +370,7 @@ hipError_t segment_graph(pgg_sim* s, int len, hipGraphExec_t* out) {
     hipError_t e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t enq = pgg::launch_ens_chunk(s->d_rep, 1, s->seg_waves, s->seg_lds, len, kGraphChunk, true,
-                                           s->d_gcounts, s->capture_stream);
+                                           s->d_gcounts, s->capture_stream, s->wpg);
     e = hipStreamEndCapture(s->capture_stream, &g);
     if (enq != hipSuccess) { if (g) (void)hipGraphDestroy(g); return enq; }
     if (e != hipSuccess) return e;
@@ -400,7 +414,7 @@ pgg_status sweep_segment_timed(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_cou
         for (int q = 0; q < len; ++q)
             for (int a = 0; a < 4; ++a)
                 PGG_HIP(s, timed_launch(s, [&] {
-                    return pgg::launch_ens_residue(rep, 1, s->seg_waves, s->seg_lds, a, q, s->stream);
+                    return pgg::launch_ens_residue(rep, 1, s->seg_waves, s->seg_lds, a, q, s->stream, s->wpg);
                 }));
         PGG_HIP(s, pgg::launch_ens_end(rep, 1, kGraphChunk, s->d_gcounts, s->stream));
         if (coop_counts)
@@ -468,7 +482,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
         s->kernel = PGG_KERNEL_COLOUR;
     else
         s->kernel = p->L >= 64 ? PGG_KERNEL_SEGMENT : PGG_KERNEL_ROWBAND_COMPACT;
-    if (s->kernel == PGG_KERNEL_SEGMENT) s->segw = p->tile ? (int)p->tile : choose_segw(p->L);
+    s->wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
+    if (s->kernel == PGG_KERNEL_SEGMENT) s->segw = p->tile ? (int)p->tile : choose_segw(p->L, s->wpg);
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t e = hipMalloc(ptr, bytes);

@@ -336,6 +336,7 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
         if (!(p.p0 >= 0.0 && p.p0 <= 1.0)) { eerr("replica %u: p0 must lie in [0, 1]", k); return PGG_E_INVAL; }
         if (p.layout != PGG_LAYOUT_BITS) { eerr("replica %u: ensembles use the bits layout", k); return PGG_E_INVAL; }
         if (p.kernel != PGG_KERNEL_AUTO && p.kernel != PGG_KERNEL_SEGMENT) { eerr("replica %u: ensembles use the segment kernel", k); return PGG_E_INVAL; }
+        if (p.group != 0) { eerr("replica %u: group must be 0 (the ensemble's waves_per_group applies)", k); return PGG_E_INVAL; }
         const uint32_t w = tiles ? tiles[k] : 0;
         if (w != 0 && (w % 32 != 0 || w + 32 > p.L)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32", k); return PGG_E_INVAL; }
     }
@@ -388,6 +389,11 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     }
     e->total_waves = waves;
     e->lds = pgg::ens_lds_bytes(max_segw, wpg);
+    if (e->lds > pgg::kMaxDynamicLds) {
+        eerr("the widest segment (%d columns) does not fit the LDS of %d waves per workgroup", max_segw, wpg);
+        ens_release(e);
+        return PGG_E_INVAL;
+    }
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t err = hipMalloc(ptr, bytes);

@@ -151,6 +151,8 @@ bool job_params_ok(const pgg_params* p, uint32_t max_L, const char** why) {
     if (p->layout != PGG_LAYOUT_BITS) { *why = "jobs use the bits layout"; return false; }
     if (p->kernel != PGG_KERNEL_AUTO && p->kernel != PGG_KERNEL_SEGMENT) { *why = "jobs use the segment kernel"; return false; }
     if (p->tile != 0 && (p->tile % 32 != 0 || p->tile + 32 > p->L)) { *why = "tile must be a multiple of 32 and <= L - 32"; return false; }
+    if (p->tile != 0 && pgg::ens_lds_bytes((int)p->tile) > pgg::kMaxDynamicLds) { *why = "tile too wide for the workgroup's LDS"; return false; }
+    if (p->group != 0) { *why = "jobs run with the server's workgroup shape (group must be 0)"; return false; }
     return true;
 }
 

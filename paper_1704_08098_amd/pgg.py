@@ -42,7 +42,7 @@ EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop
 class PggParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("r", ctypes.c_double), ("K", ctypes.c_double),
                 ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
-                ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
+                ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("group", ctypes.c_uint32)]
 
 
 class PggServerInfo(ctypes.Structure):
@@ -118,10 +118,10 @@ def _check(status):
         raise PggError(status, load().pgg_last_error().decode())
 
 
-def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto", tile=0) -> PggParams:
+def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto", tile=0, group=0) -> PggParams:
     return PggParams(int(L), float(r), float(K), float(p0), int(seed) & (2**64 - 1),
                      LAYOUTS[layout] if isinstance(layout, str) else int(layout),
-                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(tile))
+                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(tile), int(group))
 
 
 def pgg_device_bytes(params: PggParams) -> int:
@@ -216,8 +216,8 @@ class Sim:
     """One lattice on the GPU.  Mirrors the C calls one to one."""
 
     def __init__(self, L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto",
-                 dev_buf=None, stream=None, tile=0):
-        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile)
+                 dev_buf=None, stream=None, tile=0, group=0):
+        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile, group)
         self.L = int(L)
         self._buf = dev_buf  # keep a caller tensor alive as long as the handle
         self.handle = pgg_init(self.params, dev_buf, stream)

@@ -34,9 +34,10 @@ def test_every_declared_symbol_is_exported(pgg):
 
 
 def test_params_struct_layout(pgg):
-    # uint32 L; double r, K, p0; uint64 seed; uint32 layout, kernel, tile
+    # uint32 L; double r, K, p0; uint64 seed; uint32 layout, kernel, tile, group
     assert ctypes.sizeof(pgg.PggParams) == 56
     assert pgg.PggParams.seed.offset == 32
+    assert pgg.PggParams.group.offset == 52
 
 
 def test_device_bytes(pgg):
@@ -60,7 +61,11 @@ def test_device_bytes(pgg):
                                 dict(kernel="strip", tile=101),
                                 dict(kernel="rowband", tile=26),
                                 dict(L=60, kernel="segment"), dict(kernel="segment", tile=48),
-                                dict(kernel="segment", tile=96), dict(layout="int8", kernel="segment")])
+                                dict(kernel="segment", tile=96), dict(layout="int8", kernel="segment"),
+                                dict(kernel="segment", group=3), dict(kernel="segment", group=16),
+                                dict(kernel="rowband", group=4), dict(layout="int8", group=4),
+                                dict(L=32768, kernel="segment", tile=32736),
+                                dict(L=16384, kernel="segment", tile=8192, group=8)])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")
     args.update(kw)

@@ -251,12 +251,13 @@ def test_kernels_agree_at_benchmark_size(pgg):
 
 
 def test_maximum_size_kernels_agree(pgg):
-    """L = 32768 (the largest accepted): dense and compact row-band kernels
-    give identical device lattices after two sweeps; counts are recounts."""
+    """L = 32768 (the largest accepted): the dense and compact row-band kernels
+    and the automatic choice (the segment kernel) give identical device
+    lattices after two sweeps; counts are recounts."""
     import torch
     L, r, seed = 32768, 3.7443, 5
     bufs, counts = [], []
-    for kernel in ("rowband", "rowband_compact"):
+    for kernel in ("rowband", "rowband_compact", "auto"):
         params = pgg.make_params(L, r, 0.5, 0.5, seed, "bits", kernel)
         buf = torch.empty(pgg.pgg_device_bytes(params), dtype=torch.uint8, device="cuda")
         say("L=32768", kernel)
@@ -264,8 +265,9 @@ def test_maximum_size_kernels_agree(pgg):
             counts.append(sim.sweep(2))
         torch.cuda.synchronize()
         bufs.append(buf)
-    assert torch.equal(bufs[0], bufs[1])
-    assert np.array_equal(counts[0], counts[1])
+    for b, c in zip(bufs[1:], counts[1:]):
+        assert torch.equal(bufs[0], b)
+        assert np.array_equal(counts[0], c)
     pop = int(np.bitwise_count(bufs[0].cpu().numpy()).sum(dtype=np.uint64))
     assert pop == int(counts[0][-1])
 
@@ -314,6 +316,18 @@ def test_segment_widths(pgg, oracle_lib, L, segw):
     ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
     say("segment", L, segw)
     with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=segw) as sim:
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+@pytest.mark.parametrize("group", [2, 4, 8])
+def test_segment_workgroup_shapes(pgg, oracle_lib, group):
+    """2, 4 or 8 segment waves per workgroup (the last workgroup padded with
+    idle waves): same counts and lattice as the oracle."""
+    L, r, seed, n = 196, 3.9, 70 + group, 10
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say("segment group", group)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=64, group=group) as sim:
         assert np.array_equal(sim.sweep(n), counts)
         assert np.array_equal(sim.read_lattice(), ref)
 
