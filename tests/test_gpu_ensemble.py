@@ -134,3 +134,28 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
         ref, _, counts = oracle_lib.run(256, 3.7, 0.5, 0.5, 12, n)
         assert np.array_equal(ca[1], counts)
         assert np.array_equal(a.read_lattice(1), ref)
+
+
+def _oracle_run(args):
+    import oracle
+    L, r, K, p0, seed, n = args
+    lat, nc0, counts = oracle.run(L, r, K, p0, seed, n)
+    return lat, counts
+
+
+def test_r_scan_as_one_ensemble_against_oracle(pgg, oracle_lib):
+    """The L = 1024 r scan (21 values in [3.70, 3.80], seeds 100..120) run as
+    one batched ensemble: every replica's counts after each of 30 sweeps and
+    its final lattice equal the oracle's."""
+    from concurrent.futures import ProcessPoolExecutor
+    cfg, n = wl.SCAN, 30
+    reps = [dict(L=cfg["L"], r=r, K=cfg["K"], p0=cfg["p0"], seed=s)
+            for r, s in zip(cfg["r_values"], cfg["seeds"])]
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(_oracle_run, [(rp["L"], rp["r"], rp["K"], rp["p0"], rp["seed"], n) for rp in reps]))
+    say("r-scan ensemble of", len(reps))
+    with pgg.Ensemble(reps, chunk=16) as ens:
+        c = ens.sweep(n)
+        for k, (lat, counts) in enumerate(refs):
+            assert np.array_equal(c[k], counts), k
+            assert np.array_equal(ens.read_lattice(k), lat), k
