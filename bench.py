@@ -19,6 +19,7 @@ Prints one JSON line:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -51,6 +52,42 @@ SLOTS_PER_DRAWN_UPDATE = round(PHILOX_PRODUCTS * SLOTS_PER_PRODUCT) + 19 + 30 + 
 # Every site also pays the bit-parallel activity test (8 sites per 32-bit
 # word: 4 XOR, 3 OR, 1 AND, 2 window extractions) -> ~2 slots per site.
 SLOTS_PER_SITE_SCAN = 2
+# HBM traffic of the segment kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (separate passes) scaled by what the same counters read for a
+# plain 256 MiB device copy.  The summary records a hash of the kernel's
+# sources and the launch configuration; a changed kernel reads as null.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt")
+KERNEL_SOURCES = ("paper_1704_08098_amd/csrc/pgg_segment.hpp", "paper_1704_08098_amd/csrc/pgg_ensemble.hip",
+                  "paper_1704_08098_amd/csrc/pgg_device.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, L, tile, group):
+    """Bytes per launch from the committed counter summary, or None."""
+    if kernel != "segment" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if (kv["source_hash"] != kernel_source_hash() or int(kv["L"]) != L or int(kv["tile"]) != tile
+                or int(kv["group"]) != group):
+            return None
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 # Algorithmic HBM bytes per site update: the state is read and written once
 # per sweep; bit-packed = 2 bits, int8 = 2 bytes.
 BYTES_PER_UPDATE = {"bits": 0.25, "int8": 2.0}
@@ -61,16 +98,23 @@ def log(*a):
 
 
 def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0, group=0):
+    """Wall time of `steps` sweeps after `warmup`, and the HIP-event time of
+    the same region recorded on the stream the sweep kernels run on."""
     sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
     sim.sweep(warmup, want_counts=False)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     sim.sweep(steps, want_counts=False)
+    ev1.record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
     nc = sim.coop_count()
     sim.close()
-    return dt, nc
+    return dt, nc, ev_ms
 
 
 def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0, group=0):
@@ -167,9 +211,13 @@ def main():
     ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true", help="ensemble pass with automatic widths and "
                     "--ensemble-chunk instead of pgg_ensemble_autotune")
+    ap.add_argument("--source-hash", action="store_true", help="print the segment kernel's source hash and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -197,16 +245,16 @@ def main():
         del a, b
 
     log("timed pass: L=%d r=%g kernel=%s warmup=%d steps=%d" % (L, r, args.kernel, args.warmup, args.steps))
-    dt, nc_end = time_sweeps(pgg, torch, L, r, seed, args.kernel, layout, args.warmup, args.steps, stream,
-                             args.tile, args.group)
+    dt, nc_end, region_ms = time_sweeps(pgg, torch, L, r, seed, args.kernel, layout, args.warmup, args.steps,
+                                        stream, args.tile, args.group)
     updates = float(L) * L * args.steps
     value = updates / dt
 
     dense = None
     if args.kernel in ("segment", "strip", "rowband_compact", "rowband_staged") and args.dense_steps > 0:
         log("dense pass: %d sweeps" % args.dense_steps)
-        ddt, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", layout, args.warmup,
-                             args.dense_steps, stream)
+        ddt, _, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", layout, args.warmup,
+                                args.dense_steps, stream)
         dense = {"value": float(L) * L * args.dense_steps / ddt, "unit": "site updates/s",
                  "kernel": "rowband (every site draws)", "steps": args.dense_steps,
                  "ms_per_step": 1e3 * ddt / args.dense_steps}
@@ -214,7 +262,13 @@ def main():
     log("kernel-timing pass")
     launches, kms, drawn = kernel_pass(pgg, torch, L, r, seed, args.kernel, layout, args.warmup,
                                        args.steps, stream, args.tile, args.group)
-    avg_ms = kms / max(launches, 1)
+    # Average launch duration: the event-timed region of the timed pass over
+    # its launches (same trajectory, same launches as the kernel-timing pass).
+    # It includes the gaps between launches and the per-chunk bookkeeping
+    # kernels, so it bounds the kernel's own duration from above; the
+    # per-launch event pairs of the kernel-timing pass add their own overhead
+    # and are reported beside it.
+    avg_ms = region_ms / max(launches, 1)
     sites_per_launch = updates / max(launches, 1)  # the strip kernel: one launch per timed call
     if args.kernel == "colour":
         drawn = updates
@@ -222,11 +276,15 @@ def main():
     slots = drawn_per_launch * SLOTS_PER_DRAWN_UPDATE + sites_per_launch * SLOTS_PER_SITE_SCAN
     achieved_tops = slots / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved_tops / VALU_PEAK_TOPS, "traffic": None,
+                "frac": achieved_tops / VALU_PEAK_TOPS,
+                "traffic": measured_traffic(args.kernel, L, args.tile, args.group),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": {"segment": "k_ens_segment", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
                            "rowband_compact": "k_rowband_bits<true>",
                            "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,
+                "avg_launch_source": "HIP events around the timed region on the sweep stream / launches",
+                "event_bracketed_launch_us": kms / max(launches, 1) * 1e3,
                 "drawn_fraction": drawn / updates,
                 "slots_per_drawn_update": SLOTS_PER_DRAWN_UPDATE,
                 "slots_per_site_scan": SLOTS_PER_SITE_SCAN}

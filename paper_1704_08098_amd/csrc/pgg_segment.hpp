@@ -60,6 +60,17 @@ __device__ __forceinline__ uint32_t global_window(const uint32_t* __restrict__ r
     return out;
 }
 
+// Sigma of the site in bit 16 of the middle row, without its 5 s term: the
+// rows a2, a1, b, c1, c2 are i-2 .. i+2.  Sigma (the sum of the cooperator
+// counts of the five groups containing the site) counts the site itself 5
+// times, its 4 nearest neighbours twice, its 4 diagonal neighbours twice and
+// the 4 sites at axis distance 2 once.
+__device__ __forceinline__ int sigma_rest16(uint32_t a2, uint32_t a1, uint32_t b, uint32_t c1, uint32_t c2) {
+    const int ones = __popc(b & 0x00044000u) + __popc(a2 & 0x00010000u) + __popc(c2 & 0x00010000u);
+    const int twos = __popc(b & 0x00028000u) + __popc(a1 & 0x00038000u) + __popc(c1 & 0x00038000u);
+    return ones + 2 * twos;
+}
+
 // Number of set bits of a wave-wide mask below the calling lane.
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -156,8 +167,9 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         const int m = 9 - 3 * b;
         const int lo = 64 - m, hi = 64 + (e - s) + m;
         const int wlo = lo >> 5, whi = (hi + 31) >> 5;
-        // 1. candidates per word (8 class-b bits, at 4q + b), 2. compacted
-        // list: one ballot per bit position, entries placed by lane rank.
+        // 1. candidates per word (the class-b bits), 2. compacted list: each
+        // lane's offset is the exclusive prefix sum of the candidate counts
+        // (0..8) of the lanes below it, taken bit-sliced from four ballots.
         int total = 0;  // wave-uniform
         for (int wbase = wlo; wbase < whi; wbase += 64) {
             const int w = wbase + lane;
@@ -172,14 +184,18 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
                 if (p0 < lo) act &= 0xFFFFFFFFu << (lo - p0);
                 if (p0 + 32 > hi) act &= (hi - p0) >= 32 ? 0xFFFFFFFFu : ((1u << (hi - p0)) - 1u);
             }
-            act >>= b;
-            const uint32_t base = (uint32_t)(32 * w + b);
+            const int cnt = __popc(act);
+            int pos = total;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const bool on = (act >> (4 * q)) & 1u;
-                const unsigned long long m = __ballot(on);
-                if (on) list[total + lanes_below(m)] = base + 4u * (uint32_t)q;
-                total += __popcll(m);
+            for (int k = 0; k < 4; ++k) {
+                const unsigned long long m = __ballot((cnt >> k) & 1);
+                pos += lanes_below(m) << k;
+                total += __popcll(m) << k;
+            }
+            while (act) {
+                const int bit = __ffs(act) - 1;
+                act &= act - 1u;
+                list[pos++] = (uint32_t)(32 * w + bit);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -192,28 +208,35 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
             c += (c < 0) ? L : 0;
             c -= (c >= L) ? L : 0;
             const uint2 rnd = philox4x32_10_w01((uint32_t)(i * L + c), t, k, 0u, k0, k1);
-            const int d = (int)(rnd.x >> 30);
             const uint32_t u = rnd.y;
-            const int w = (p - 16) >> 5, sh = (p - 16) & 31;
-            const uint32_t wm3 = funnel(r0[w + 1 - 3 * WB], r0[w - 3 * WB], sh);
-            const uint32_t wm2 = funnel(r0[w + 1 - 2 * WB], r0[w - 2 * WB], sh);
-            const uint32_t wm1 = funnel(r0[w + 1 - WB], r0[w - WB], sh);
-            const uint32_t w00 = funnel(r0[w + 1], r0[w], sh);
-            const uint32_t wp1 = funnel(r0[w + 1 + WB], r0[w + WB], sh);
-            const uint32_t wp2 = funnel(r0[w + 1 + 2 * WB], r0[w + 2 * WB], sh);
-            const uint32_t wp3 = funnel(r0[w + 1 + 3 * WB], r0[w + 3 * WB], sh);
-            const int o = dir_di(d);
-            const int py = 16 + dir_dj(d);
-            const uint32_t y2 = o < 0 ? wm3 : (o > 0 ? wm1 : wm2);
-            const uint32_t y1 = o < 0 ? wm2 : (o > 0 ? w00 : wm1);
-            const uint32_t y0 = o < 0 ? wm1 : (o > 0 ? wp1 : w00);
-            const uint32_t z1 = o < 0 ? w00 : (o > 0 ? wp2 : wp1);
-            const uint32_t z2 = o < 0 ? wp1 : (o > 0 ? wp3 : wp2);
-            const int sx = (int)((w00 >> 16) & 1u);
-            const int sy = (int)((y0 >> py) & 1u);
+            // neighbour y = x + (di, dj) for d = w0 >> 30: 0 E, 1 W, 2 S, 3 N
+            const uint32_t d2 = (rnd.x >> 30) << 1;
+            const int di = (int)__builtin_amdgcn_ubfe(0x25u, d2, 2u) - 1;
+            const int dj = (int)__builtin_amdgcn_ubfe(0x52u, d2, 2u) - 1;
+            // Rows i-2 .. i+2 around x and around y, each a 32-column window
+            // with the centre column in bit 16.
+            const int px = p - 16, py = px + dj;
+            const uint32_t* rx = r0 + (px >> 5);
+            const uint32_t* ry = r0 + __mul24(di, WB) + (py >> 5);
+            const int shx = px & 31, shy = py & 31;
+            const uint32_t x0 = funnel(rx[1], rx[0], shx);
+            const uint32_t y0 = funnel(ry[1], ry[0], shy);
+            const int sx = (int)((x0 >> 16) & 1u);
+            const int sy = (int)((y0 >> 16) & 1u);
             if (sx != sy) {
-                const int dsig = sigma_bits(wm2, wm1, w00, wp1, wp2, 16) - sigma_bits(y2, y1, y0, z1, z2, py);
-                if (u < sT[(dsig + 25) * 3 + (sx - sy + 1)]) {
+                const uint32_t xm2 = funnel(rx[1 - 2 * WB], rx[-2 * WB], shx);
+                const uint32_t xm1 = funnel(rx[1 - WB], rx[-WB], shx);
+                const uint32_t xp1 = funnel(rx[1 + WB], rx[WB], shx);
+                const uint32_t xp2 = funnel(rx[1 + 2 * WB], rx[2 * WB], shx);
+                const uint32_t ym2 = funnel(ry[1 - 2 * WB], ry[-2 * WB], shy);
+                const uint32_t ym1 = funnel(ry[1 - WB], ry[-WB], shy);
+                const uint32_t yp1 = funnel(ry[1 + WB], ry[WB], shy);
+                const uint32_t yp2 = funnel(ry[1 + 2 * WB], ry[2 * WB], shy);
+                const int ds = sx - sy;  // +1 or -1
+                // Sigma = rest + 5 s, so Sigma_x - Sigma_y = rest_x - rest_y + 5 ds
+                const int dsig = seg::sigma_rest16(xm2, xm1, x0, xp1, xp2) - seg::sigma_rest16(ym2, ym1, y0, yp1, yp2) +
+                                 5 * ds;
+                if (u < sT[__mul24(dsig, 3) + 76 + ds]) {  // T[(dsig + 25) * 3 + ds + 1]
                     atomicXor(&r0[p >> 5], 1u << (p & 31));
                     if (p >= 64 && p < 64 + (e - s)) my_delta += sy ? 1 : -1;
                 }
