@@ -124,8 +124,9 @@ def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, t
     sim.set_kernel_timing(True)
     sim.sweep(steps, want_counts=False)
     launches, ms, drawn = sim.kernel_timing()
+    span_n, span_us = sim.kernel_span()
     sim.close()
-    return launches, ms, drawn
+    return launches, ms, drawn, (span_us / span_n if span_n else None)
 
 
 def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
@@ -260,14 +261,14 @@ def main():
                  "ms_per_step": 1e3 * ddt / args.dense_steps}
 
     log("kernel-timing pass")
-    launches, kms, drawn = kernel_pass(pgg, torch, L, r, seed, args.kernel, layout, args.warmup,
-                                       args.steps, stream, args.tile, args.group)
+    launches, kms, drawn, span_us = kernel_pass(pgg, torch, L, r, seed, args.kernel, layout, args.warmup,
+                                                args.steps, stream, args.tile, args.group)
     # Average launch duration: the event-timed region of the timed pass over
     # its launches (same trajectory, same launches as the kernel-timing pass).
     # It includes the gaps between launches and the per-chunk bookkeeping
-    # kernels, so it bounds the kernel's own duration from above; the
-    # per-launch event pairs of the kernel-timing pass add their own overhead
-    # and are reported beside it.
+    # kernels, so it bounds the kernel's own duration from above.  The
+    # kernel-timing pass also reports each launch's own span (device wall
+    # clock, first workgroup start to last workgroup end).
     avg_ms = region_ms / max(launches, 1)
     sites_per_launch = updates / max(launches, 1)  # the strip kernel: one launch per timed call
     if args.kernel == "colour":
@@ -284,7 +285,8 @@ def main():
                            "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,
                 "avg_launch_source": "HIP events around the timed region on the sweep stream / launches",
-                "event_bracketed_launch_us": kms / max(launches, 1) * 1e3,
+                "timing_pass_event_us_per_launch": kms / max(launches, 1) * 1e3,
+                "kernel_span_us": span_us,
                 "drawn_fraction": drawn / updates,
                 "slots_per_drawn_update": SLOTS_PER_DRAWN_UPDATE,
                 "slots_per_site_scan": SLOTS_PER_SITE_SCAN}

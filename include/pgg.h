@@ -181,19 +181,31 @@ pgg_status pgg_write_lattice(pgg_sim* s, const uint8_t* host_LxL, uint64_t t);
  * device uses to host_T (host, 153 entries).  Synchronises the stream. */
 pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T);
 
-/* Diagnostics for measurement.  With enable != 0, every later launch of the
- * sweep kernel by pgg_sweep on this handle is bracketed by a pair of HIP
- * events on the handle's stream, and the row-band kernels count the site
- * updates that drew random numbers.  Resets the totals.  Timing adds event
- * records between launches, so a throughput measurement should run with it
+/* Diagnostics for measurement.  With enable != 0, later pgg_sweep calls on
+ * this handle time their sweep-kernel launches with HIP events on the
+ * handle's stream and count the site updates that drew random numbers.
+ * Row-band, strip and colour kernels: a pair of events around every launch.
+ * Segment kernel: its graph replays (timing mode has graphs of its own)
+ * are bracketed per chunk, the stream is synchronised after every chunk,
+ * and every launch records its own span (see pgg_kernel_span).  Resets the
+ * totals.  Timing adds work, so a throughput measurement should run with it
  * disabled.  Synchronises the stream. */
 pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable);
 
 /* Totals since the last pgg_set_kernel_timing: number of timed sweep-kernel
- * launches, their summed event-to-event duration in ms, and the number of
- * site updates that drew random numbers (row-band kernels; 0 otherwise).
+ * launches, their summed event-to-event duration in ms (segment kernel: of
+ * the chunks holding them, with the chunks' bookkeeping kernels), and the
+ * number of site updates that drew random numbers (0 for the colour kernel,
+ * where every update draws).
  * All three pointers are host and must be non-NULL.  Synchronises. */
 pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, uint64_t* drawn);
+
+/* Segment kernel, totals since the last pgg_set_kernel_timing: number of
+ * timed launches and the sum over them of the launch's own span -- latest
+ * workgroup end minus earliest workgroup start, read from the device wall
+ * clock.  0 launches for the other kernels.  Host pointers, non-NULL.
+ * Host only. */
+pgg_status pgg_kernel_span(pgg_sim* s, uint64_t* launches, double* total_us);
 
 /* Diagnostics for failure handling: the longest time (seconds, >= 0) a
  * workgroup of the STRIP kernel waits for a neighbouring strip before it

@@ -77,6 +77,11 @@ struct pgg_sim {
     uint64_t timed_launches = 0;
     double timed_ms = 0.0;
     unsigned long long* d_drawn = nullptr;
+    unsigned long long* d_span = nullptr;  // segment kernel, timing mode: kGraphChunk x 4 launches x kSpanWords
+    double wall_khz = 0.0;
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // segment kernel, timing mode
+    uint64_t span_launches = 0;
+    double span_us = 0.0;
     // Persistent strip kernel plan.
     pgg::StripTask* d_tasks = nullptr;
     int n_tasks = 0;
@@ -102,18 +107,12 @@ int choose_R(uint32_t L) {
 
 // Columns per segment: about 8 waves per SIMD at large L, at least 128
 // columns (the 18-column margins stay cheap), at most L - 32.
-// Columns per segment: about L^2 / 16384 (so a launch has >= 4 waves per
-// SIMD), at least 128, at most L - 32 and L / 2, and small enough that the
+// Columns per segment: the automatic width, narrowed until the
 // workgroup's LDS fits.
 int choose_segw(uint32_t L, int wpg) {
-    long w = ((long)L * (long)L / 16384) & ~31L;
-    if (w < 128) w = 128;
-    const long cap = ((long)L - 32) & ~31L;
-    if (w > cap) w = cap;
-    if (w > (long)L / 2 && L >= 128) w = ((long)L / 2) & ~31L;
-    while (w > 32 && pgg::ens_lds_bytes((int)w, wpg) > pgg::kMaxDynamicLds) w -= 32;
-    if (w < 32) w = 32;
-    return (int)w;
+    int w = pgg::auto_segw((int)L);
+    while (w > 32 && pgg::ens_lds_bytes(w, wpg) > pgg::kMaxDynamicLds) w -= 32;
+    return w;
 }
 
 bool strip_fits(uint32_t L, uint32_t H) {
@@ -225,6 +224,9 @@ void release(pgg_sim* s) {
     if (s->d_delta) (void)hipFree(s->d_delta);
     if (s->d_counts) (void)hipFree(s->d_counts);
     if (s->d_drawn) (void)hipFree(s->d_drawn);
+    if (s->d_span) (void)hipFree(s->d_span);
+    for (hipEvent_t ev : s->chunk_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (s->d_tasks) (void)hipFree(s->d_tasks);
     if (s->d_ring) (void)hipFree(s->d_ring);
     if (s->d_abort) (void)hipFree(s->d_abort);
@@ -362,15 +364,20 @@ pgg_status plan_segment_graph(pgg_sim* s) {
 }
 
 // The captured chunk of `len` sweeps (captured on the handle's own capture
-// stream -- the null stream cannot be captured -- and launched on its stream).
-hipError_t segment_graph(pgg_sim* s, int len, hipGraphExec_t* out) {
-    auto it = s->graphs.find(len);
+// stream -- the null stream cannot be captured -- and launched on its
+// stream).  Timing mode has graphs of its own: they run the timing
+// descriptor (which counts draws) and record each launch's span.
+hipError_t segment_graph(pgg_sim* s, int len, bool timing, hipGraphExec_t* out) {
+    const int key = 2 * len + (timing ? 1 : 0);
+    auto it = s->graphs.find(key);
     if (it != s->graphs.end()) { *out = it->second; return hipSuccess; }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t enq = pgg::launch_ens_chunk(s->d_rep, 1, s->seg_waves, s->seg_lds, len, kGraphChunk, true,
-                                           s->d_gcounts, s->capture_stream, s->wpg);
+    hipError_t enq = timing ? pgg::launch_span_reset(s->d_span, 4 * len, s->capture_stream) : hipSuccess;
+    if (enq == hipSuccess)
+        enq = pgg::launch_ens_chunk(s->d_rep + (timing ? 1 : 0), 1, s->seg_waves, s->seg_lds, len, kGraphChunk, true,
+                                    s->d_gcounts, s->capture_stream, s->wpg, timing ? s->d_span : nullptr);
     e = hipStreamEndCapture(s->capture_stream, &g);
     if (enq != hipSuccess) { if (g) (void)hipGraphDestroy(g); return enq; }
     if (e != hipSuccess) return e;
@@ -378,48 +385,68 @@ hipError_t segment_graph(pgg_sim* s, int len, hipGraphExec_t* out) {
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (e != hipSuccess) { (void)hipGraphDestroy(g); return e; }
     s->graph_defs.push_back(g);
-    s->graphs[len] = ex;
+    s->graphs[key] = ex;
+    e = hipGraphUpload(ex, s->stream);  // device-side setup now, not at the first (possibly timed) launch
+    if (e != hipSuccess) return e;
     *out = ex;
     return hipSuccess;
 }
 
-// pgg_sweep for the segment kernel outside timing mode: graph replays.
-pgg_status sweep_segment_graph(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
-    PGG_HIP(s, pgg::launch_ens_set_t0(s->d_rep, 1, (uint32_t)s->t, s->stream));
-    uint32_t done = 0;
-    while (done < n_sweeps) {
-        const int len = (int)std::min<uint32_t>((uint32_t)kGraphChunk, n_sweeps - done);
-        hipGraphExec_t g = nullptr;
-        PGG_HIP(s, segment_graph(s, len, &g));
-        PGG_HIP(s, hipGraphLaunch(g, s->stream));
-        if (coop_counts)
-            PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_gcounts, (size_t)len * sizeof(uint64_t),
-                                      hipMemcpyDeviceToHost, s->stream));
-        done += (uint32_t)len;
+// Timing mode, after a chunk of `len` sweeps has completed: add the chunk's
+// event time and every launch's span (latest end minus earliest start over
+// its records) to the totals.
+pgg_status fold_segment_timing(pgg_sim* s, int len) {
+    std::vector<unsigned long long> span((size_t)4 * len * pgg::kSpanWords);
+    PGG_HIP(s, hipMemcpyAsync(span.data(), s->d_span, span.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              s->stream));
+    PGG_HIP(s, hipStreamSynchronize(s->stream));
+    float ms = 0.f;
+    PGG_HIP(s, hipEventElapsedTime(&ms, s->chunk_ev[0], s->chunk_ev[1]));
+    s->timed_ms += ms;
+    s->timed_launches += 4 * (uint64_t)len;
+    for (int l = 0; l < 4 * len; ++l) {
+        unsigned long long lo = ~0ull, hi = 0ull;
+        for (int x = 0; x < pgg::kSpanSlots; ++x) {
+            lo = std::min(lo, span[(size_t)pgg::kSpanWords * l + 2 * x]);
+            hi = std::max(hi, span[(size_t)pgg::kSpanWords * l + 2 * x + 1]);
+        }
+        if (lo != ~0ull && hi >= lo) {
+            s->span_us += (double)(hi - lo) * 1e3 / s->wall_khz;
+            s->span_launches += 1;
+        }
     }
-    if (coop_counts) PGG_HIP(s, hipStreamSynchronize(s->stream));
-    s->t += n_sweeps;
     return PGG_OK;
 }
 
-// pgg_sweep for the segment kernel in timing mode: the same launches as a
-// replayed chunk, issued one by one between events.
-pgg_status sweep_segment_timed(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
-    pgg::EnsRep* rep = s->d_rep + 1;
-    PGG_HIP(s, pgg::launch_ens_set_t0(rep, 1, (uint32_t)s->t, s->stream));
+// pgg_sweep for the segment kernel: graph replays.  Chunks are kGraphChunk
+// sweeps, the rest is split into powers of two, and the graphs of all these
+// lengths are captured on the first call of a mode, so no later (timed) call
+// instantiates one.  Timing mode synchronises after every chunk.
+pgg_status sweep_segment(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
+    static_assert((kGraphChunk & (kGraphChunk - 1)) == 0, "kGraphChunk must be a power of two");
+    const bool timing = s->timing;
+    for (int len = kGraphChunk; len >= 1; len >>= 1) {
+        hipGraphExec_t g = nullptr;
+        PGG_HIP(s, segment_graph(s, len, timing, &g));
+    }
+    PGG_HIP(s, pgg::launch_ens_set_t0(s->d_rep + (timing ? 1 : 0), 1, (uint32_t)s->t, s->stream));
     uint32_t done = 0;
     while (done < n_sweeps) {
-        const int len = (int)std::min<uint32_t>((uint32_t)kGraphChunk, n_sweeps - done);
-        PGG_HIP(s, pgg::launch_ens_begin(rep, 1, len, kGraphChunk, true, s->stream));
-        for (int q = 0; q < len; ++q)
-            for (int a = 0; a < 4; ++a)
-                PGG_HIP(s, timed_launch(s, [&] {
-                    return pgg::launch_ens_residue(rep, 1, s->seg_waves, s->seg_lds, a, q, s->stream, s->wpg);
-                }));
-        PGG_HIP(s, pgg::launch_ens_end(rep, 1, kGraphChunk, s->d_gcounts, s->stream));
+        const uint32_t rem = n_sweeps - done;
+        const int len = rem >= (uint32_t)kGraphChunk ? kGraphChunk : (int)(1u << (31 - __builtin_clz(rem)));
+        hipGraphExec_t g = nullptr;
+        PGG_HIP(s, segment_graph(s, len, timing, &g));
+        if (timing) PGG_HIP(s, hipEventRecord(s->chunk_ev[0], s->stream));
+        PGG_HIP(s, hipGraphLaunch(g, s->stream));
+        if (timing) PGG_HIP(s, hipEventRecord(s->chunk_ev[1], s->stream));
         if (coop_counts)
             PGG_HIP(s, hipMemcpyAsync(coop_counts + done, s->d_gcounts, (size_t)len * sizeof(uint64_t),
                                       hipMemcpyDeviceToHost, s->stream));
+        if (timing) {
+            PGG_HIP(s, hipStreamSynchronize(s->stream));
+            pgg_status fs = fold_segment_timing(s, len);
+            if (fs != PGG_OK) return fs;
+        }
         done += (uint32_t)len;
     }
     if (coop_counts) PGG_HIP(s, hipStreamSynchronize(s->stream));
@@ -531,8 +558,7 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     }
     if (n_sweeps == 0) return PGG_OK;
     DeviceGuard guard(s->device);
-    if (s->kernel == PGG_KERNEL_SEGMENT)
-        return s->timing ? sweep_segment_timed(s, n_sweeps, coop_counts) : sweep_segment_graph(s, n_sweeps, coop_counts);
+    if (s->kernel == PGG_KERNEL_SEGMENT) return sweep_segment(s, n_sweeps, coop_counts);
     const int L = (int)s->p.L;
     uint32_t done = 0;
     while (done < n_sweeps) {
@@ -682,6 +708,16 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable) {
         hipError_t e = hipMalloc((void**)&s->d_drawn, pgg::kSweepWords * sizeof(unsigned long long));
         if (e != hipSuccess) { set_err("hipMalloc failed: %s", hipGetErrorString(e)); return PGG_E_NOMEM; }
     }
+    if (enable && s->d_rep && !s->d_span) {
+        hipError_t e = hipMalloc((void**)&s->d_span, (size_t)kGraphChunk * 4 * pgg::kSpanWords * sizeof(unsigned long long));
+        if (e != hipSuccess) { set_err("hipMalloc failed: %s", hipGetErrorString(e)); return PGG_E_NOMEM; }
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        s->wall_khz = (double)khz;
+        for (hipEvent_t& ev : s->chunk_ev)
+            if (!ev) PGG_HIP(s, hipEventCreate(&ev));
+    }
     PGG_HIP(s, fold_timing(s));
     if (enable) PGG_HIP(s, pgg::launch_fill_u64(s->d_drawn, pgg::kSweepWords, 0ull, s->stream));
     if (enable && s->d_rep) {  // the timing descriptor of the segment kernel counts draws
@@ -693,6 +729,8 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable) {
     s->timing = enable != 0;
     s->timed_launches = 0;
     s->timed_ms = 0.0;
+    s->span_launches = 0;
+    s->span_us = 0.0;
     return PGG_OK;
 }
 
@@ -714,6 +752,14 @@ pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, u
     *launches = s->timed_launches;
     *total_ms = s->timed_ms;
     *drawn = d;
+    return PGG_OK;
+}
+
+pgg_status pgg_kernel_span(pgg_sim* s, uint64_t* launches, double* total_us) {
+    PGG_LIVE(s);
+    if (!launches || !total_us) { set_err("NULL argument"); return PGG_E_INVAL; }
+    *launches = s->span_launches;
+    *total_us = s->span_us;
     return PGG_OK;
 }
 

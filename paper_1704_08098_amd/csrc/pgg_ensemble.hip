@@ -37,10 +37,11 @@ __device__ __forceinline__ int replica_of_wave(const EnsRep* __restrict__ reps, 
 
 template <int WPG>
 __global__ void __launch_bounds__(64 * WPG)
-k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
+k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigned long long* __restrict__ span) {
     extern __shared__ uint32_t smem[];
     __shared__ int s_part[2 * WPG];
     __shared__ int s_rep;
+    const unsigned long long t_begin = span ? wall_clock64() : 0ull;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     // neighbouring rows (which share window rows) run on the same XCD's L2
@@ -82,6 +83,11 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q) {
             atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
                       (unsigned long long)(long long)dsum);
         if (rp.drawn && nsum) atomicAdd(slot_of(rp.drawn, (int)blockIdx.x), (unsigned long long)nsum);
+        if (span) {  // diagnostics: earliest start and latest end over kSpanSlots spread pairs
+            unsigned long long* sp = span + 2 * (blockIdx.x & (kSpanSlots - 1));
+            atomicMin(sp, t_begin);
+            atomicMax(sp + 1, wall_clock64());
+        }
     }
 }
 
@@ -147,8 +153,8 @@ __global__ void k_ens_copyback(const EnsRep* __restrict__ reps) {
 // Zero the per-sweep counters of every replica (one block per replica).
 __global__ void k_ens_zero(const EnsRep* __restrict__ reps, int chunk) {
     unsigned long long* d = reps[blockIdx.x].delta;
-    const int n = chunk * kSweepWords;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) d[k] = 0ull;
+    const int n = chunk * kSlots;  // only the slot words of each sweep's row are used
+    for (int k = threadIdx.x; k < n; k += blockDim.x) d[(size_t)(k / kSlots) * kSweepWords + (k % kSlots) * kSlotStride] = 0ull;
 }
 
 // Sweep bookkeeping of every replica: n_active for the next chunk, or the
@@ -168,20 +174,36 @@ __global__ void k_ens_set_t0(EnsRep* __restrict__ reps, int n_reps, uint32_t t0)
     if (k < n_reps) reps[k].t0 = t0;
 }
 
+__global__ void k_span_reset(unsigned long long* span, int n_words) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_words) span[k] = (k & 1) ? 0ull : ~0ull;
+}
+
+hipError_t launch_span_reset(unsigned long long* span, int n_launches, hipStream_t st) {
+    const int n = kSpanWords * n_launches;
+    hipLaunchKernelGGL(k_span_reset, dim3((n + 255) / 256), dim3(256), 0, st, span, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st) {
     hipLaunchKernelGGL(k_ens_set_t0, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n, t0);
     return hipGetLastError();
 }
 
+int auto_segw(int L) {
+    // About 1376 columns: at the drawn fraction of a lattice near r_c (about
+    // 15 % of the sites) a class then lists about 50 sites, most of one
+    // 64-lane pass; the row is split into equal segments of that order.
+    const int nseg = (L + 1375) / 1376;
+    int w = (L / nseg + 31) & ~31;
+    const int cap = (L - 32) & ~31;
+    if (w > cap) w = cap;
+    if (w < 32) w = 32;
+    return w;
+}
+
 void ens_geometry(EnsRep& rp, int L, int segw) {
-    if (segw == 0) {
-        // Columns per segment: about L / 8, at least 64, at most L - 32.
-        segw = (L / 8) & ~31;
-        if (segw < 64) segw = 64;
-        const int cap = (L - 32) & ~31;
-        if (segw > cap) segw = cap;
-        if (segw < 32) segw = 32;
-    }
+    if (segw == 0) segw = auto_segw(L);
     rp.L = L;
     rp.stride = 2 * ((L + 63) / 64);
     rp.nw = (L + 31) / 32;
@@ -211,12 +233,12 @@ hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_
 }
 
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
-                              hipStream_t st, int wpg) {
+                              hipStream_t st, int wpg, unsigned long long* span) {
     const dim3 grid(total_waves / wpg), block(64 * wpg);
     switch (wpg) {
-        case 2: hipLaunchKernelGGL(k_ens_segment<2>, grid, block, lds, st, d_reps, n, a, q); break;
-        case 4: hipLaunchKernelGGL(k_ens_segment<4>, grid, block, lds, st, d_reps, n, a, q); break;
-        case 8: hipLaunchKernelGGL(k_ens_segment<8>, grid, block, lds, st, d_reps, n, a, q); break;
+        case 2: hipLaunchKernelGGL(k_ens_segment<2>, grid, block, lds, st, d_reps, n, a, q, span); break;
+        case 4: hipLaunchKernelGGL(k_ens_segment<4>, grid, block, lds, st, d_reps, n, a, q, span); break;
+        case 8: hipLaunchKernelGGL(k_ens_segment<8>, grid, block, lds, st, d_reps, n, a, q, span); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -233,11 +255,13 @@ hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* 
 }
 
 hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
-                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg) {
+                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg,
+                            unsigned long long* span) {
     hipError_t err = launch_ens_begin(d_reps, n, len, chunk, set_active, st);
     for (int q = 0; err == hipSuccess && q < len; ++q)
         for (int a = 0; err == hipSuccess && a < 4; ++a)
-            err = launch_ens_residue(d_reps, n, total_waves, lds, a, q, st, wpg);
+            err = launch_ens_residue(d_reps, n, total_waves, lds, a, q, st, wpg,
+                                     span ? span + kSpanWords * (4 * q + a) : nullptr);
     if (err != hipSuccess) return err;
     return launch_ens_end(d_reps, n, chunk, counts, st);
 }
@@ -320,6 +344,8 @@ hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
     if (err != hipSuccess) { (void)hipGraphDestroy(g); return err; }
     e->graph_defs.push_back(g);
     e->graphs[len] = ex;
+    err = hipGraphUpload(ex, e->stream);
+    if (err != hipSuccess) return err;
     *out = ex;
     return hipSuccess;
 }

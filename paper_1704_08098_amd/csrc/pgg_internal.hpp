@@ -96,6 +96,8 @@ struct EnsRep {
     uint32_t k0, k1, t0;
 };
 
+// Automatic segment width for side L (a multiple of 32, <= L - 32).
+int auto_segw(int L);
 // Fill in segw, nseg, stride, nw of a replica of side L (segw 0 = automatic).
 void ens_geometry(EnsRep& rp, int L, int segw);
 // Waves of one launch for this replica, padded to whole workgroups of wpg waves.
@@ -108,13 +110,22 @@ bool ens_wpg_valid(int wpg);
 // per-replica scan into counts[n][chunk] (and rp.nc), the copy of the final
 // state back to rp.lat when it lies in rp.lat2, the advance of t0.
 hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
-                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg = kWavesPerGroup);
+                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg = kWavesPerGroup,
+                            unsigned long long* span = nullptr);
 // The same chunk in three parts, for callers that bracket each segment
 // launch (residue a of sweep q of the chunk) with events of their own.
 hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_active, hipStream_t st);
+// span: NULL, or kSpanWords words: kSpanSlots (earliest start, latest end)
+// pairs in wall-clock ticks, set to (~0, 0) beforehand, workgroup b updating
+// pair b mod kSpanSlots -- a diagnostic of the launch's own span.  Spread so
+// that the atomics of one address stay few.
+constexpr int kSpanSlots = 256;
+constexpr int kSpanWords = 2 * kSpanSlots;
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
-                              hipStream_t st, int wpg = kWavesPerGroup);
+                              hipStream_t st, int wpg = kWavesPerGroup, unsigned long long* span = nullptr);
 hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st);
+// Set n_launches span records (kSpanWords words each) to (~0, 0) pairs.
+hipError_t launch_span_reset(unsigned long long* span, int n_launches, hipStream_t st);
 // Set the sweep index t0 of every replica (graph-safe, no host memory).
 hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st);
 

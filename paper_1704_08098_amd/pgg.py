@@ -30,7 +30,7 @@ KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBA
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
-           "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_set_strip_wait", "pgg_destroy",
+           "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_kernel_span", "pgg_set_strip_wait", "pgg_destroy",
            "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
            "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy",
            "pgg_ensemble_autotune",
@@ -82,6 +82,7 @@ def load():
         "pgg_threshold_table": (ctypes.c_int, [vp, u32p]),
         "pgg_set_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "pgg_kernel_timing": (ctypes.c_int, [vp, u64p, P(ctypes.c_double), u64p]),
+        "pgg_kernel_span": (ctypes.c_int, [vp, u64p, P(ctypes.c_double)]),
         "pgg_set_strip_wait": (ctypes.c_int, [vp, ctypes.c_double]),
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
@@ -249,6 +250,13 @@ class Sim:
 
     def kernel_timing(self):
         return pgg_kernel_timing(self.handle)
+
+    def kernel_span(self):
+        """(launches, total span in microseconds) of the segment kernel's timed launches."""
+        n = ctypes.c_uint64()
+        us = ctypes.c_double()
+        _check(load().pgg_kernel_span(self.handle, ctypes.byref(n), ctypes.byref(us)))
+        return int(n.value), float(us.value)
 
     def set_strip_wait(self, seconds):
         pgg_set_strip_wait(self.handle, seconds)

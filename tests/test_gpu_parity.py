@@ -347,12 +347,12 @@ def test_segment_many_waves_out_of_place(pgg):
         assert np.array_equal(a.read_lattice(), b.read_lattice())
 
 
-def test_segment_graph_and_eager_paths_agree(pgg, oracle_lib):
-    """Outside timing mode the segment kernel replays captured chunks of
-    sweeps (sweep index in device memory); in timing mode it launches each
-    residue eagerly.  Calls of ragged lengths (odd, one, several chunks, a
-    chunk and a tail) switch between the two on one lattice and must follow
-    the oracle sweep for sweep."""
+def test_segment_plain_and_timing_graphs_agree(pgg, oracle_lib):
+    """The segment kernel replays captured chunks of 64 sweeps and power-of-two
+    tails; timing mode replays graphs of its own (draw counters, launch
+    spans).  Calls of ragged lengths (odd, one, several chunks, a chunk and a
+    tail) switch between the two on one lattice and must follow the oracle
+    sweep for sweep; timing mode reports 4 launches per sweep."""
     L, r, K, p0, seed = 200, 3.8, 0.5, 0.5, 23
     lengths = [1, 63, 64, 65, 130, 3, 2]
     n = sum(lengths)
@@ -367,3 +367,9 @@ def test_segment_graph_and_eager_paths_agree(pgg, oracle_lib):
         assert np.array_equal(np.concatenate(got), counts)
         assert np.array_equal(sim.read_lattice(), ref)
         assert sim.t == n
+        sim.set_kernel_timing(True)
+        sim.sweep(5)
+        launches, ms, drawn = sim.kernel_timing()
+        span_n, span_us = sim.kernel_span()
+        assert launches == 20 and span_n == 20 and ms > 0.0 and span_us > 0.0
+        assert 0 < drawn <= 5 * L * L
