@@ -14,6 +14,11 @@ Prints one JSON line:
               the state (read + write once per sweep)
   dense       the data-independent rate with every site drawing its random
               numbers (no skipping of no-op updates)
+  late        the same lattice later in its decay (sweeps 10^4 .. 10^4+K-1)
+  batched     256 replicas of uneven L, r, seed in one graph-replayed ensemble
+              (autotuned) vs the same replicas one lattice at a time
+  serving     a Poisson trace of simulation jobs through the job server:
+              p50/p99 latency and aggregate site updates/s
   cpu_baseline  the oracle, single-threaded, on a bounded sample
 """
 from __future__ import annotations
@@ -180,6 +185,43 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
             "mean_final_density": float(sum(int(v) / reps[k]["L"] ** 2 for k, v in enumerate(nc)) / len(reps))}
 
 
+def late_window(pgg, torch, L, r, seed, kernel, layout, t_start, steps, stream, tile=0, group=0):
+    """The same lattice later in its decay: sweeps t_start .. t_start+steps-1
+    (fewer active sites, so fewer draws per sweep)."""
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
+    sim.sweep(t_start, want_counts=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(steps, want_counts=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rho = sim.density()
+    sim.close()
+    return {"t_start": t_start, "steps": steps, "value": float(L) * L * steps / dt, "unit": "site updates/s",
+            "ms_per_step": 1e3 * dt / steps, "density_at_end": rho}
+
+
+def serving_pass(pgg, n_jobs, capacity, stream, budget_mib=256):
+    """Poisson arrivals of simulation jobs through the C job server at 70 %
+    of `capacity` (site updates/s) on the trace's mean job size."""
+    from paper_1704_08098_amd import server
+    probe = wl.serving_trace(n_jobs, 1.0)
+    mean_work = sum(float(j["L"]) ** 2 * j["sweeps"] for j in probe) / n_jobs
+    rate = 0.7 * capacity / mean_work
+    jobs = wl.serving_trace(n_jobs, rate)
+    engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, chunk=16, stream=stream)
+    try:
+        rep = server.serve(engine, jobs)
+    finally:
+        engine.close()
+    rep.pop("engine", None)
+    rep.update({"arrival_rate_per_s": rate, "offered_load": 0.7, "capacity_basis": capacity,
+                "hbm_budget_MiB": budget_mib, "chunk": 16,
+                "trace": "Poisson arrivals; L log-uniform in [64, 2048] (multiples of 4), r ~ U[3.5, 5.6], "
+                         "MCS ~ U{1000..10000}, p0 ~ U[0.1, 0.9], seed 7"})
+    return rep
+
+
 def cpu_baseline(L, r, seed, n_sweeps):
     import oracle
     oracle.build(force=False)
@@ -210,6 +252,8 @@ def main():
     ap.add_argument("--ensemble-sweeps", type=int, default=5000, help="0 skips the ensemble pass")
     ap.add_argument("--ensemble-chunk", type=int, default=50)
     ap.add_argument("--plain-per-size", type=int, default=4)
+    ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
+    ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
     ap.add_argument("--no-autotune", action="store_true", help="ensemble pass with automatic widths and "
                     "--ensemble-chunk instead of pgg_ensemble_autotune")
     ap.add_argument("--source-hash", action="store_true", help="print the segment kernel's source hash and exit")
@@ -303,6 +347,18 @@ def main():
         batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream,
                                 not args.no_autotune)
 
+    late = None
+    if args.late_start > 0:
+        log("late window: sweeps %d..%d" % (args.late_start, args.late_start + args.steps - 1))
+        late = late_window(pgg, torch, L, r, seed, args.kernel, layout, args.late_start, args.steps, stream,
+                           args.tile, args.group)
+
+    serving = None
+    if args.serve_jobs > 0:
+        capacity = batched["value"] if batched else value
+        log("serving pass: %d jobs" % args.serve_jobs)
+        serving = serving_pass(pgg, args.serve_jobs, capacity, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, %d sweep(s) at L=%d" % (args.cpu_sweeps, L))
@@ -318,7 +374,8 @@ def main():
                                                                  args.warmup + args.steps - 1),
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
-        "roofline": roofline, "hbm": hbm, "dense": dense, "batched": batched, "cpu_baseline": cpu,
+        "roofline": roofline, "hbm": hbm, "dense": dense, "late": late, "batched": batched, "serving": serving,
+        "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }
     print(json.dumps(line), flush=True)

@@ -40,15 +40,15 @@ __global__ void __launch_bounds__(64 * WPG)
 k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigned long long* __restrict__ span) {
     extern __shared__ uint32_t smem[];
     __shared__ int s_part[2 * WPG];
-    __shared__ int s_rep;
     const unsigned long long t_begin = span ? wall_clock64() : 0ull;
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
+    // Everything below that depends only on the wave (its replica, row and
+    // segment) is wave-uniform: readfirstlane keeps it in scalar registers.
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // neighbouring rows (which share window rows) run on the same XCD's L2
     const int first_wave = xcd_major((int)blockIdx.x, (int)gridDim.x) * WPG;
-    if (threadIdx.x == 0) s_rep = replica_of_wave(reps, n_reps, first_wave);
-    __syncthreads();
-    const EnsRep rp = reps[s_rep];
+    const int rep_id = __builtin_amdgcn_readfirstlane(replica_of_wave(reps, n_reps, first_wave));
+    const EnsRep rp = reps[rep_id];
     uint32_t* sT = smem;
     uint32_t* win = smem + 160 + wid * seg_wave_words(rp.segw);
     const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica

@@ -170,6 +170,9 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         // 1. candidates per word (the class-b bits), 2. compacted list: each
         // lane's offset is the exclusive prefix sum of the candidate counts
         // (0..8) of the lanes below it, taken bit-sliced from four ballots.
+        // positions [lo, hi): only the first and the last word are partial
+        const uint32_t m_first = 0xFFFFFFFFu << (lo & 31);
+        const uint32_t m_last = (hi & 31) ? (1u << (hi & 31)) - 1u : 0xFFFFFFFFu;
         int total = 0;  // wave-uniform
         for (int wbase = wlo; wbase < whi; wbase += 64) {
             const int w = wbase + lane;
@@ -179,10 +182,8 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
                 const uint32_t E = funnel(r0[w + 1], X, 1);
                 const uint32_t Wn = funnel(X, r0[w - 1], 31);
                 act = ((X ^ E) | (X ^ Wn) | (X ^ r0[w - WB]) | (X ^ r0[w + WB])) & (0x11111111u << b);
-                // keep positions in [lo, hi)
-                const int p0 = 32 * w;
-                if (p0 < lo) act &= 0xFFFFFFFFu << (lo - p0);
-                if (p0 + 32 > hi) act &= (hi - p0) >= 32 ? 0xFFFFFFFFu : ((1u << (hi - p0)) - 1u);
+                if (w == wlo) act &= m_first;
+                if (w == whi - 1) act &= m_last;
             }
             const int cnt = __popc(act);
             int pos = total;
@@ -204,10 +205,11 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         const uint32_t k = k_first + (uint32_t)b;
         for (int q = lane; q < total; q += 64) {
             const int p = (int)list[q];
-            int c = c0 + p;
-            c += (c < 0) ? L : 0;
-            c -= (c >= L) ? L : 0;
-            const uint2 rnd = philox4x32_10_w01((uint32_t)(i * L + c), t, k, 0u, k0, k1);
+            // column c0 + p modulo L (it lies in [-L, 2L)): the wrapped value is
+            // the least of c, c + L and c - L taken as unsigned numbers
+            const uint32_t c = (uint32_t)(c0 + p);
+            const uint32_t cw = min(min(c, c + (uint32_t)L), c - (uint32_t)L);
+            const uint2 rnd = philox4x32_10_w01((uint32_t)(i * L) + cw, t, k, 0u, k0, k1);
             const uint32_t u = rnd.y;
             // neighbour y = x + (di, dj) for d = w0 >> 30: 0 E, 1 W, 2 S, 3 N
             const uint32_t d2 = (rnd.x >> 30) << 1;
