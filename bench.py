@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T full-rate lane-ops/s
 
 # Algorithmic VALU cost of one elementary step that draws its random numbers,
-# in full-rate 32-bit lane-op slots (derivation in the design doc):
+# in full-rate 32-bit lane-op slots:
 #   Philox4x32-10: 19 products 32x32->64 (two per round, the last round
 #   needs one); a v_mad_u64_u32 issues at about 1.3 slots on gfx950
 #   (throughput micro-kernel) -> 25; the two 3-input XORs per round -> 19
@@ -267,8 +267,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the sweep of one lattice is not split across "
-              "GPUs in this build (see DESIGN.md for how it would shard); got --gpus %d" % args.gpus,
-              file=sys.stderr)
+              "GPUs here; got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
