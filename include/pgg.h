@@ -118,9 +118,11 @@ typedef struct {
     uint32_t kernel; /* pgg_kernel; must match the layout unless AUTO         */
     uint32_t tile;   /* work split; 0 = chosen by the library.  STRIP: rows
                         per strip (>= 4); ROWBAND*: rows per band; SEGMENT:
-                        columns per segment (a multiple of 32, <= L - 32).
-                        A value the kernel cannot use is PGG_E_INVAL.  Results
-                        never depend on it.                                   */
+                        columns per segment (a multiple of 32, <= L - 32),
+                        or L itself when L is a multiple of 32: whole rows
+                        per wave (min(L/4, max(1, 1024/L)) of them).  A value
+                        the kernel cannot use is PGG_E_INVAL.  Results never
+                        depend on it.                                         */
     uint32_t group;  /* SEGMENT: segment waves per workgroup, 2, 4 or 8
                         (0 = 4); other kernels: must be 0.  Results never
                         depend on it.                                         */
@@ -233,8 +235,9 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
 /* Create n_reps replicas and draw their initial states (t = 0).
  *   reps       host array of n_reps parameter sets: 64 <= L <= 32768, L % 4
  *              == 0, layout BITS, kernel AUTO or SEGMENT; copied.
- *   tiles      host array of n_reps segment widths (multiple of 32,
- *              <= L - 32; 0 = automatic) or NULL for all automatic.
+ *   tiles      host array of n_reps work splits as pgg_params.tile of
+ *              the segment kernel (0 = automatic), or NULL for all
+ *              automatic.
  *   chunk      sweeps per graph replay, 1..1024 (device counters hold
  *              chunk x n_reps x 4 KiB).
  *   waves_per_group  segment waves per workgroup: 2, 4 or 8 (0 = 4).  A
@@ -279,7 +282,8 @@ void pgg_ensemble_destroy(pgg_ensemble* e);
  *   ms_out        NULL, or the best time per sweep of the whole ensemble.
  * Trials run on trial ensembles created from reps (fresh initial states
  * each): first the width of each distinct L in turn over the doublings
- * 64, 128, ... below L - 32 plus L - 32 rounded down to a multiple of 32,
+ * 64, 128, ... below L - 32, L - 32 rounded down to a multiple of 32, and
+ * whole rows (L, when L is a multiple of 32),
  * the other sizes held at their best so far, then the waves per workgroup
  * over 2, 4, 8, then the chunk over 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
  * trial's final cooperator counts must equal the first trial's, else

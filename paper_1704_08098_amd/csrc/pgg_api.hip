@@ -107,11 +107,21 @@ int choose_R(uint32_t L) {
 
 // Columns per segment: about 8 waves per SIMD at large L, at least 128
 // columns (the 18-column margins stay cheap), at most L - 32.
-// Columns per segment: the automatic width, narrowed until the
-// workgroup's LDS fits.
+// LDS bytes of a segment-kernel workgroup for side L, width segw, wpg waves.
+size_t segment_lds(uint32_t L, int segw, int wpg) {
+    pgg::EnsRep rp;
+    std::memset(&rp, 0, sizeof(rp));
+    pgg::ens_geometry(rp, (int)L, segw);
+    return pgg::ens_lds_bytes(pgg::ens_wave_words(rp), wpg);
+}
+
+// Work split of the segment kernel: the automatic one, with segments
+// narrowed until the workgroup's LDS fits.
 int choose_segw(uint32_t L, int wpg) {
     int w = pgg::auto_segw((int)L);
-    while (w > 32 && pgg::ens_lds_bytes(w, wpg) > pgg::kMaxDynamicLds) w -= 32;
+    if (w == (int)L && segment_lds(L, w, wpg) <= pgg::kMaxDynamicLds) return w;
+    if (w == (int)L) w = ((int)L - 32) & ~31;
+    while (w > 32 && segment_lds(L, w, wpg) > pgg::kMaxDynamicLds) w -= 32;
     return w;
 }
 
@@ -152,10 +162,10 @@ bool params_valid(const pgg_params* p, const char** why) {
         case PGG_KERNEL_SEGMENT: {
             if (p->layout != PGG_LAYOUT_BITS) { *why = "the segment kernel needs the bits layout"; return false; }
             if (p->L < 64) { *why = "the segment kernel needs L >= 64"; return false; }
-            if (tr != 0 && (tr % 32 != 0 || tr + 32 > p->L)) { *why = "segment tile must be a multiple of 32 and <= L - 32"; return false; }
+            if (tr != 0 && !pgg::segw_valid((int)p->L, (int)tr)) { *why = "segment tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)"; return false; }
             const int wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
             if (!pgg::ens_wpg_valid(wpg)) { *why = "group must be 0, 2, 4 or 8"; return false; }
-            if (pgg::ens_lds_bytes(tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::kMaxDynamicLds) {
+            if (segment_lds(p->L, tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::kMaxDynamicLds) {
                 *why = "the segment kernel's LDS footprint does not fit at this tile and group";
                 return false;
             }
@@ -356,7 +366,7 @@ pgg_status plan_segment_graph(pgg_sim* s) {
     rp.nc = s->d_nc;
     rp.drawn = nullptr;
     s->seg_waves = pgg::ens_waves(rp, s->wpg);
-    s->seg_lds = pgg::ens_lds_bytes(rp.segw, s->wpg);
+    s->seg_lds = pgg::ens_lds_bytes(pgg::ens_wave_words(rp), s->wpg);
     const pgg::EnsRep both[2] = {rp, rp};
     e = hipMemcpy(s->d_rep, both, sizeof(both), hipMemcpyHostToDevice);
     if (e != hipSuccess) { set_err("segment graph descriptor: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }

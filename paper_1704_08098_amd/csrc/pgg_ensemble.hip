@@ -21,6 +21,7 @@
 
 #include "pgg.h"
 #include "pgg_internal.hpp"
+#include "pgg_fullrow.hpp"
 #include "pgg_segment.hpp"
 
 namespace pgg {
@@ -50,22 +51,31 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigne
     const int rep_id = __builtin_amdgcn_readfirstlane(replica_of_wave(reps, n_reps, first_wave));
     const EnsRep rp = reps[rep_id];
     uint32_t* sT = smem;
-    uint32_t* win = smem + 160 + wid * seg_wave_words(rp.segw);
+    uint32_t* win = smem + 160 + wid * rep_wave_words(rp);
     const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica
-    const bool active = q < rp.n_active && lw < (rp.L >> 2) * rp.nseg;
     // sweep q of the chunk reads the state after sweep q - 1: lat for even q,
     // lat2 for odd q, and writes the other buffer.
     const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
     uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
-    const SegPos g = seg_pos(rp.L, a, rp.segw, active ? lw / rp.nseg : 0, active ? lw % rp.nseg : 0);
-    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
-    if (active) segment_fill(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, g, win);
-    __syncthreads();
-
+    const uint32_t t = rp.t0 + (uint32_t)q;
     int my_delta = 0, my_drawn = 0;
-    if (active)
-        segment_run(next, rp.L, rp.stride, a, rp.segw, g, rp.t0 + (uint32_t)q, rp.k0, rp.k1, sT, win, my_delta,
-                    my_drawn);
+    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    if (rp.rpw > 0) {
+        // whole rows: wave lw owns rows a + 4 (lw R + r), r < nrows
+        const int R = rp.rpw, rows = rp.L >> 2;
+        const bool active = q < rp.n_active && lw * R < rows;
+        const int i0 = a + 4 * lw * R;
+        const int nrows = min(R, rows - lw * R);
+        if (active) fullrow_fill(cur, next, rp.L, rp.stride, a, i0, R, win);
+        __syncthreads();
+        if (active) fullrow_run(next, rp.L, rp.stride, a, i0, R, nrows, t, rp.k0, rp.k1, sT, win, my_delta, my_drawn);
+    } else {
+        const bool active = q < rp.n_active && lw < (rp.L >> 2) * rp.nseg;
+        const SegPos g = seg_pos(rp.L, a, rp.segw, active ? lw / rp.nseg : 0, active ? lw % rp.nseg : 0);
+        if (active) segment_fill(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, g, win);
+        __syncthreads();
+        if (active) segment_run(next, rp.L, rp.stride, a, rp.segw, g, t, rp.k0, rp.k1, sT, win, my_delta, my_drawn);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
     if (lane == 0) {
@@ -191,6 +201,7 @@ hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st)
 }
 
 int auto_segw(int L) {
+    if (L % 32 == 0 && L <= 1024) return L;  // whole rows
     // About 1376 columns: at the drawn fraction of a lattice near r_c (about
     // 15 % of the sites) a class then lists about 50 sites, most of one
     // 64-lane pass; the row is split into equal segments of that order.
@@ -202,22 +213,37 @@ int auto_segw(int L) {
     return w;
 }
 
+bool segw_valid(int L, int segw) {
+    if (segw == L) return L % 32 == 0;
+    return segw > 0 && segw % 32 == 0 && segw + 32 <= L;
+}
+
 void ens_geometry(EnsRep& rp, int L, int segw) {
     if (segw == 0) segw = auto_segw(L);
     rp.L = L;
     rp.stride = 2 * ((L + 63) / 64);
     rp.nw = (L + 31) / 32;
     rp.segw = segw;
-    rp.nseg = (L + segw - 1) / segw;
+    if (segw == L) {
+        rp.nseg = 1;
+        const int R = L >= 1024 ? 1 : 1024 / L;
+        rp.rpw = R < L / 4 ? R : L / 4;
+    } else {
+        rp.nseg = (L + segw - 1) / segw;
+        rp.rpw = 0;
+    }
 }
 
 int ens_waves(const EnsRep& rp, int wpg) {
-    const int wv = (rp.L / 4) * rp.nseg;
+    const int rows = rp.L / 4;
+    const int wv = rp.rpw > 0 ? (rows + rp.rpw - 1) / rp.rpw : rows * rp.nseg;
     return (wv + wpg - 1) / wpg * wpg;
 }
 
-size_t ens_lds_bytes(int max_segw, int wpg) {
-    return (160 + (size_t)wpg * seg_wave_words(max_segw)) * sizeof(uint32_t);
+int ens_wave_words(const EnsRep& rp) { return rep_wave_words(rp); }
+
+size_t ens_lds_bytes(int max_wave_words, int wpg) {
+    return (160 + (size_t)wpg * max_wave_words) * sizeof(uint32_t);
 }
 
 bool ens_wpg_valid(int wpg) { return wpg == 2 || wpg == 4 || wpg == 8; }
@@ -364,7 +390,7 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
         if (p.kernel != PGG_KERNEL_AUTO && p.kernel != PGG_KERNEL_SEGMENT) { eerr("replica %u: ensembles use the segment kernel", k); return PGG_E_INVAL; }
         if (p.group != 0) { eerr("replica %u: group must be 0 (the ensemble's waves_per_group applies)", k); return PGG_E_INVAL; }
         const uint32_t w = tiles ? tiles[k] : 0;
-        if (w != 0 && (w % 32 != 0 || w + 32 > p.L)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32", k); return PGG_E_INVAL; }
+        if (w != 0 && !pgg::segw_valid((int)p.L, (int)w)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)", k); return PGG_E_INVAL; }
     }
     return PGG_OK;
 }
@@ -396,7 +422,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     // Layout: lattices back to back (256-byte aligned), tables, per-replica waves.
     std::vector<size_t> lat_off(n_reps);
     size_t lat_words = 0;
-    int max_segw = 0;
+    int max_words = 0;
     e->host_reps.resize(n_reps);
     int waves = 0;
     for (uint32_t k = 0; k < n_reps; ++k) {
@@ -411,12 +437,12 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         waves += pgg::ens_waves(rp, wpg);
         lat_off[k] = lat_words;
         lat_words += 2 * (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);  // lat and lat2
-        max_segw = std::max(max_segw, rp.segw);
+        max_words = std::max(max_words, pgg::ens_wave_words(rp));
     }
     e->total_waves = waves;
-    e->lds = pgg::ens_lds_bytes(max_segw, wpg);
+    e->lds = pgg::ens_lds_bytes(max_words, wpg);
     if (e->lds > pgg::kMaxDynamicLds) {
-        eerr("the widest segment (%d columns) does not fit the LDS of %d waves per workgroup", max_segw, wpg);
+        eerr("the widest replica layout (%d LDS words per wave) does not fit %d waves per workgroup", max_words, wpg);
         ens_release(e);
         return PGG_E_INVAL;
     }
@@ -585,6 +611,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         std::vector<uint32_t> cand;
         for (uint32_t w = 64; w < cap; w *= 2) cand.push_back(w);
         if (cap >= 32) cand.push_back(cap);
+        if (L % 32 == 0) cand.push_back(L);  // whole rows
         pgg::EnsRep geo;
         std::memset(&geo, 0, sizeof(geo));
         pgg::ens_geometry(geo, (int)L, 0);

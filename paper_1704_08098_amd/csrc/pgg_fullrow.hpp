@@ -1,0 +1,162 @@
+// Full-row sweep on the bit-packed layout (gfx950): one wave owns R whole
+// rows of the launch's residue a (rows i0, i0 + 4, ..., i0 + 4 (R - 1)),
+// for L a multiple of 32.  Owning whole rows, the wave needs no column
+// margins and recomputes nothing: the classes 4a..4a+3 run on the full
+// periodic rows.  Small lattices take several rows per wave so that a
+// class still lists enough sites to fill a 64-lane pass.
+//
+// The wave's LDS window holds rows i0 - 3 .. i0 + 4 (R - 1) + 3 (4R + 3 rows,
+// periodic), each as its nw = L / 32 words plus one pad word on each side
+// that repeats the word across the wrap (pad left = word nw - 1, pad right =
+// word 0), so neighbour and stencil windows never index modulo L.  Only the
+// owned rows change in a launch, and a flip in word 0 or nw - 1 is applied
+// to the pad copy as well.  A row of residue a never reads another row of
+// residue a (they are 4 apart, the stencil reaches 3), so copies of a row
+// that the window holds twice (R = L / 4) are never read stale.
+// Same update rule, lists and out-of-place double buffering as the segment
+// sweep (pgg_segment.hpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pgg_device.hpp"
+#include "pgg_internal.hpp"
+#include "pgg_segment.hpp"
+
+namespace pgg {
+
+// Words of a full-row wave's LDS: the window rows, then one class list.
+__host__ __device__ constexpr int fr_window_ldw(int L) { return L / 32 + 2; }
+__host__ __device__ constexpr int fr_wave_words(int L, int R) {
+    return (4 * R + 3) * fr_window_ldw(L) + R * (L / 4) + 8;
+}
+
+// LDS words one wave of this replica uses (whole rows or a segment).
+__host__ __device__ inline int rep_wave_words(const EnsRep& rp) {
+    return rp.rpw > 0 ? fr_wave_words(rp.L, rp.rpw) : seg_wave_words(rp.segw);
+}
+
+// Fill the window: rows of residue below a from next (updated earlier in
+// this sweep), the others from cur.
+__device__ __forceinline__ void fullrow_fill(const uint32_t* __restrict__ cur, const uint32_t* __restrict__ next,
+                                             int L, int stride, int a, int i0, int R, uint32_t* __restrict__ win) {
+    const int lane = threadIdx.x & 63;
+    const int nw = L >> 5, ldw = nw + 2;
+    const int n = (4 * R + 3) * ldw;
+    for (int q = lane; q < n; q += 64) {
+        const int o = q / ldw;
+        int w = q - o * ldw - 1;  // -1 .. nw
+        w += (w < 0) ? nw : 0;
+        w -= (w >= nw) ? nw : 0;
+        int gi = i0 - 3 + o;  // in [-3, 2L)
+        gi += (gi < 0) ? L : 0;
+        gi -= (gi >= L) ? L : 0;
+        const uint32_t* src = ((gi & 3) < a) ? next : cur;
+        win[q] = src[(size_t)gi * stride + w];
+    }
+}
+
+// The four classes on the nrows (<= R) owned rows, then the rows written to
+// next.  Adds the net change of the cooperator count to my_delta (every
+// lane) and the number of draws to my_drawn (lane 0).
+__device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, int stride, int a, int i0, int R,
+                                            int nrows, uint32_t t, uint32_t k0, uint32_t k1,
+                                            const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
+                                            int& my_delta, int& my_drawn) {
+    const int lane = threadIdx.x & 63;
+    const int nw = L >> 5, ldw = nw + 2;
+    uint32_t* list = win + (4 * R + 3) * ldw;
+    uint32_t* row0 = win + 3 * ldw + 1;  // word 0 of owned row 0; owned row r starts 4 ldw later per r
+    const int nwords = nrows * nw;
+    const uint32_t k_first = (uint32_t)(4 * a);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+        // 1. candidates: class-b sites with a differing neighbour, per word
+        int total = 0;  // wave-uniform
+        for (int qb = 0; qb < nwords; qb += 64) {
+            const int q = qb + lane;
+            uint32_t act = 0;
+            int r = 0, w = 0;
+            if (q < nwords) {
+                r = q / nw;
+                w = q - r * nw;
+                const uint32_t* rp = row0 + 4 * r * ldw;
+                const uint32_t X = rp[w];
+                const uint32_t E = funnel(rp[w + 1], X, 1);
+                const uint32_t Wn = funnel(X, rp[w - 1], 31);
+                act = ((X ^ E) | (X ^ Wn) | (X ^ rp[w - ldw]) | (X ^ rp[w + ldw])) & (0x11111111u << b);
+            }
+            // 2. compacted list: entry = r << 16 | column
+            const int cnt = __popc(act);
+            int pos = total;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned long long m = __ballot((cnt >> k) & 1);
+                pos += seg::lanes_below(m) << k;
+                total += __popcll(m) << k;
+            }
+            const uint32_t tag = ((uint32_t)r << 16) | (uint32_t)(32 * w);
+            while (act) {
+                const int bit = __ffs(act) - 1;
+                act &= act - 1u;
+                list[pos++] = tag | (uint32_t)bit;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        my_drawn += lane == 0 ? total : 0;
+        // 3. the elementary steps of the listed sites
+        const uint32_t k = k_first + (uint32_t)b;
+        for (int q = lane; q < total; q += 64) {
+            const uint32_t en = list[q];
+            const int r = (int)(en >> 16), p = (int)(en & 0xFFFFu);
+            uint32_t* rp = row0 + 4 * r * ldw;
+            const uint2 rnd = philox4x32_10_w01((uint32_t)((i0 + 4 * r) * L + p), t, k, 0u, k0, k1);
+            const uint32_t u = rnd.y;
+            // neighbour y = x + (di, dj) for d = w0 >> 30: 0 E, 1 W, 2 S, 3 N
+            const uint32_t d2 = (rnd.x >> 30) << 1;
+            const int di = (int)__builtin_amdgcn_ubfe(0x25u, d2, 2u) - 1;
+            const int dj = (int)__builtin_amdgcn_ubfe(0x52u, d2, 2u) - 1;
+            // rows i-2 .. i+2 around x and around y, centre column in bit 16
+            // (columns p - 16 .. p + 15 lie within the pad words)
+            const int px = p - 16, py = px + dj;
+            const uint32_t* rx = rp + (px >> 5);
+            const uint32_t* ry = rp + __mul24(di, ldw) + (py >> 5);
+            const int shx = px & 31, shy = py & 31;
+            const uint32_t x0 = funnel(rx[1], rx[0], shx);
+            const uint32_t y0 = funnel(ry[1], ry[0], shy);
+            const int sx = (int)((x0 >> 16) & 1u);
+            const int sy = (int)((y0 >> 16) & 1u);
+            if (sx != sy) {
+                const uint32_t xm2 = funnel(rx[1 - 2 * ldw], rx[-2 * ldw], shx);
+                const uint32_t xm1 = funnel(rx[1 - ldw], rx[-ldw], shx);
+                const uint32_t xp1 = funnel(rx[1 + ldw], rx[ldw], shx);
+                const uint32_t xp2 = funnel(rx[1 + 2 * ldw], rx[2 * ldw], shx);
+                const uint32_t ym2 = funnel(ry[1 - 2 * ldw], ry[-2 * ldw], shy);
+                const uint32_t ym1 = funnel(ry[1 - ldw], ry[-ldw], shy);
+                const uint32_t yp1 = funnel(ry[1 + ldw], ry[ldw], shy);
+                const uint32_t yp2 = funnel(ry[1 + 2 * ldw], ry[2 * ldw], shy);
+                const int ds = sx - sy;  // +1 or -1
+                const int dsig = seg::sigma_rest16(xm2, xm1, x0, xp1, xp2) - seg::sigma_rest16(ym2, ym1, y0, yp1, yp2) +
+                                 5 * ds;
+                if (u < sT[__mul24(dsig, 3) + 76 + ds]) {  // T[(dsig + 25) * 3 + ds + 1]
+                    const int wx = p >> 5;
+                    const uint32_t bit = 1u << (p & 31);
+                    atomicXor(&rp[wx], bit);
+                    if (wx == 0) atomicXor(&rp[nw], bit);        // right pad repeats word 0
+                    if (wx == nw - 1) atomicXor(&rp[-1], bit);   // left pad repeats word nw - 1
+                    my_delta += sy ? 1 : -1;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // Write back the owned rows.
+    for (int q = lane; q < nwords; q += 64) {
+        const int r = q / nw, w = q - r * nw;
+        next[(size_t)(i0 + 4 * r) * stride + w] = row0[4 * r * ldw + w];
+    }
+}
+
+}  // namespace pgg

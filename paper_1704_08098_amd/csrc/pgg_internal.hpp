@@ -93,16 +93,26 @@ struct EnsRep {
     unsigned long long* nc;     // N_C after the last completed sweep
     unsigned long long* drawn;  // kSweepWords spread counters of draws, or null
     int L, stride, nw, segw, nseg, wave_base, n_active;
+    int rpw;                    // full-row sweep (segw == L): rows per wave; 0 = segments
     uint32_t k0, k1, t0;
 };
 
-// Automatic segment width for side L (a multiple of 32, <= L - 32).
+// Automatic work split for side L: L itself (whole rows per wave) when L is
+// a multiple of 32 and at most 1024, else a segment width (a multiple of 32,
+// <= L - 32).
 int auto_segw(int L);
-// Fill in segw, nseg, stride, nw of a replica of side L (segw 0 = automatic).
+// Whether a width is usable at side L: a multiple of 32 up to L - 32
+// (segments), or L itself when L is a multiple of 32 (whole rows).
+bool segw_valid(int L, int segw);
+// Fill in segw, nseg, rpw, stride, nw of a replica of side L (segw 0 =
+// automatic; segw == L: whole rows, min(L / 4, max(1, 1024 / L)) per wave).
 void ens_geometry(EnsRep& rp, int L, int segw);
 // Waves of one launch for this replica, padded to whole workgroups of wpg waves.
 int ens_waves(const EnsRep& rp, int wpg = kWavesPerGroup);
-size_t ens_lds_bytes(int max_segw, int wpg = kWavesPerGroup);
+// LDS words one wave of this replica uses.
+int ens_wave_words(const EnsRep& rp);
+// Dynamic LDS of a workgroup of wpg waves of at most max_wave_words each.
+size_t ens_lds_bytes(int max_wave_words, int wpg = kWavesPerGroup);
 bool ens_wpg_valid(int wpg);
 // Enqueue one chunk of `len` sweeps (len <= chunk) for the n replicas of
 // d_reps on st: (if set_active) n_active = len for every replica, zero their

@@ -150,8 +150,13 @@ bool job_params_ok(const pgg_params* p, uint32_t max_L, const char** why) {
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_BITS) { *why = "jobs use the bits layout"; return false; }
     if (p->kernel != PGG_KERNEL_AUTO && p->kernel != PGG_KERNEL_SEGMENT) { *why = "jobs use the segment kernel"; return false; }
-    if (p->tile != 0 && (p->tile % 32 != 0 || p->tile + 32 > p->L)) { *why = "tile must be a multiple of 32 and <= L - 32"; return false; }
-    if (p->tile != 0 && pgg::ens_lds_bytes((int)p->tile) > pgg::kMaxDynamicLds) { *why = "tile too wide for the workgroup's LDS"; return false; }
+    if (p->tile != 0 && !pgg::segw_valid((int)p->L, (int)p->tile)) { *why = "tile must be a multiple of 32 and <= L - 32, or L for whole rows (L a multiple of 32)"; return false; }
+    {
+        pgg::EnsRep rp;
+        std::memset(&rp, 0, sizeof(rp));
+        pgg::ens_geometry(rp, (int)p->L, (int)p->tile);
+        if (pgg::ens_lds_bytes(pgg::ens_wave_words(rp)) > pgg::kMaxDynamicLds) { *why = "tile too wide for the workgroup's LDS"; return false; }
+    }
     if (p->group != 0) { *why = "jobs run with the server's workgroup shape (group must be 0)"; return false; }
     return true;
 }
@@ -276,7 +281,7 @@ pgg_status pgg_server_step(pgg_server* s, uint32_t* n_resident) {
     if (n == 0) return PGG_OK;
 
     // (2) one chunk for every resident job, each at its own sweep index.
-    int waves = 0, max_segw = 0, len_max = 0;
+    int waves = 0, max_words = 0, len_max = 0;
     for (int k = 0; k < n; ++k) {
         Job& j = s->jobs[s->resident[k]];
         pgg::EnsRep rp = j.rep;
@@ -284,14 +289,14 @@ pgg_status pgg_server_step(pgg_server* s, uint32_t* n_resident) {
         rp.n_active = (int)std::min<uint32_t>(s->chunk, j.n_sweeps - j.done);
         rp.wave_base = waves;
         waves += pgg::ens_waves(rp);
-        max_segw = std::max(max_segw, rp.segw);
+        max_words = std::max(max_words, pgg::ens_wave_words(rp));
         len_max = std::max(len_max, (int)std::min<uint32_t>(s->chunk, j.n_sweeps - j.done));
         s->h_reps[k] = rp;
     }
     SRV_HIP(s, hipMemcpyAsync(s->d_reps, s->h_reps, (size_t)n * sizeof(pgg::EnsRep), hipMemcpyHostToDevice, s->stream));
     // Launches cover len_max sweeps; a job with fewer remaining sweeps runs
     // only its own n_active of them.
-    SRV_HIP(s, pgg::launch_ens_chunk(s->d_reps, n, waves, pgg::ens_lds_bytes(max_segw), len_max, (int)s->chunk,
+    SRV_HIP(s, pgg::launch_ens_chunk(s->d_reps, n, waves, pgg::ens_lds_bytes(max_words), len_max, (int)s->chunk,
                                      false, s->d_counts, s->stream));
     SRV_HIP(s, hipMemcpyAsync(s->h_counts.data(), s->d_counts, (size_t)n * s->chunk * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s->stream));

@@ -373,3 +373,30 @@ def test_segment_plain_and_timing_graphs_agree(pgg, oracle_lib):
         span_n, span_us = sim.kernel_span()
         assert launches == 20 and span_n == 20 and ms > 0.0 and span_us > 0.0
         assert 0 < drawn <= 5 * L * L
+
+
+@pytest.mark.parametrize("L,group", [(64, 4), (96, 4), (128, 2), (160, 8), (256, 4), (512, 4), (1024, 4),
+                                     (2048, 4)])
+def test_whole_row_waves(pgg, oracle_lib, L, group):
+    """Whole rows per wave (tile = L): several rows per wave below L = 1024,
+    ragged last waves (L = 96, 160), pad words across the periodic wrap."""
+    r, seed, n = 3.85, 90 + L, 9
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say("whole rows", L, group)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=L, group=group) as sim:
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_whole_rows_and_segments_agree_at_L1024(pgg):
+    """L = 1024, 40 sweeps near r_c: whole rows (automatic), 512- and
+    992-column segments give identical counts and lattices."""
+    L, r, seed, n = 1024, 3.7443, 44, 40
+    out = []
+    for tile in (0, 512, 992):
+        say("L=1024 tile", tile)
+        with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment", tile=tile) as sim:
+            out.append((sim.sweep(n), sim.read_lattice()))
+    for c, lat in out[1:]:
+        assert np.array_equal(c, out[0][0])
+        assert np.array_equal(lat, out[0][1])
