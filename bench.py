@@ -62,8 +62,8 @@ SLOTS_PER_SITE_SCAN = 2
 # plain 256 MiB device copy.  The summary records a hash of the kernel's
 # sources and the launch configuration; a changed kernel reads as null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt")
-KERNEL_SOURCES = ("paper_1704_08098_amd/csrc/pgg_segment.hpp", "paper_1704_08098_amd/csrc/pgg_ensemble.hip",
-                  "paper_1704_08098_amd/csrc/pgg_device.hpp")
+KERNEL_SOURCES = ("paper_1704_08098_amd/csrc/pgg_segment.hpp", "paper_1704_08098_amd/csrc/pgg_fullrow.hpp",
+                  "paper_1704_08098_amd/csrc/pgg_ensemble.hip", "paper_1704_08098_amd/csrc/pgg_device.hpp")
 
 
 def kernel_source_hash():
@@ -201,21 +201,32 @@ def late_window(pgg, torch, L, r, seed, kernel, layout, t_start, steps, stream, 
             "ms_per_step": 1e3 * dt / steps, "density_at_end": rho}
 
 
-def serving_pass(pgg, n_jobs, capacity, stream, budget_mib=256):
+def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64):
     """Poisson arrivals of simulation jobs through the C job server at 70 %
-    of `capacity` (site updates/s) on the trace's mean job size."""
+    of its capacity.  The capacity is measured first: calib_jobs jobs of the
+    same distribution all submitted at once (a closed batch)."""
     from paper_1704_08098_amd import server
+
+    def run(jobs):
+        engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, chunk=16, stream=stream)
+        try:
+            rep = server.serve(engine, jobs)
+        finally:
+            engine.close()
+        rep.pop("engine", None)
+        return rep
+
+    calib = wl.serving_trace(calib_jobs, 1.0, master_seed=11)
+    for j in calib:
+        j["arrival"] = 0.0
+    cal = run(calib)
+    capacity = cal["site_updates_per_s"]
     probe = wl.serving_trace(n_jobs, 1.0)
     mean_work = sum(float(j["L"]) ** 2 * j["sweeps"] for j in probe) / n_jobs
     rate = 0.7 * capacity / mean_work
-    jobs = wl.serving_trace(n_jobs, rate)
-    engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, chunk=16, stream=stream)
-    try:
-        rep = server.serve(engine, jobs)
-    finally:
-        engine.close()
-    rep.pop("engine", None)
-    rep.update({"arrival_rate_per_s": rate, "offered_load": 0.7, "capacity_basis": capacity,
+    rep = run(wl.serving_trace(n_jobs, rate))
+    rep.update({"arrival_rate_per_s": rate, "offered_load": 0.7, "capacity_site_updates_per_s": capacity,
+                "capacity_basis": "%d jobs of the same distribution submitted at once (closed batch)" % calib_jobs,
                 "hbm_budget_MiB": budget_mib, "chunk": 16,
                 "trace": "Poisson arrivals; L log-uniform in [64, 2048] (multiples of 4), r ~ U[3.5, 5.6], "
                          "MCS ~ U{1000..10000}, p0 ~ U[0.1, 0.9], seed 7"})
@@ -354,9 +365,8 @@ def main():
 
     serving = None
     if args.serve_jobs > 0:
-        capacity = batched["value"] if batched else value
-        log("serving pass: %d jobs" % args.serve_jobs)
-        serving = serving_pass(pgg, args.serve_jobs, capacity, stream)
+        log("serving pass: capacity batch, then %d jobs" % args.serve_jobs)
+        serving = serving_pass(pgg, args.serve_jobs, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
