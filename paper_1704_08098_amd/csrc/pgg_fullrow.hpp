@@ -106,48 +106,36 @@ __device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, 
         }
         __builtin_amdgcn_wave_barrier();
         my_drawn += lane == 0 ? total : 0;
-        // 3. the elementary steps of the listed sites
+        // 3. the elementary steps of the listed sites, two per lane per step
+        // (both decided before either flips: sites of one class never read
+        // each other's strategy).  Columns p - 16 .. p + 15 lie within the
+        // pad words.
         const uint32_t k = k_first + (uint32_t)b;
-        for (int q = lane; q < total; q += 64) {
-            const uint32_t en = list[q];
+        auto step = [&](uint32_t en) {
+            const int r = (int)(en >> 16), p = (int)(en & 0xFFFFu);
+            return site_step(row0 + 4 * r * ldw, ldw, p, (uint32_t)((i0 + 4 * r) * L + p), t, k, k0, k1, sT);
+        };
+        auto apply = [&](uint32_t en, int f) {
             const int r = (int)(en >> 16), p = (int)(en & 0xFFFFu);
             uint32_t* rp = row0 + 4 * r * ldw;
-            const uint2 rnd = philox4x32_10_w01((uint32_t)((i0 + 4 * r) * L + p), t, k, 0u, k0, k1);
-            const uint32_t u = rnd.y;
-            // neighbour y = x + (di, dj) for d = w0 >> 30: 0 E, 1 W, 2 S, 3 N
-            const uint32_t d2 = (rnd.x >> 30) << 1;
-            const int di = (int)__builtin_amdgcn_ubfe(0x25u, d2, 2u) - 1;
-            const int dj = (int)__builtin_amdgcn_ubfe(0x52u, d2, 2u) - 1;
-            // rows i-2 .. i+2 around x and around y, centre column in bit 16
-            // (columns p - 16 .. p + 15 lie within the pad words)
-            const int px = p - 16, py = px + dj;
-            const uint32_t* rx = rp + (px >> 5);
-            const uint32_t* ry = rp + __mul24(di, ldw) + (py >> 5);
-            const int shx = px & 31, shy = py & 31;
-            const uint32_t x0 = funnel(rx[1], rx[0], shx);
-            const uint32_t y0 = funnel(ry[1], ry[0], shy);
-            const int sx = (int)((x0 >> 16) & 1u);
-            const int sy = (int)((y0 >> 16) & 1u);
-            if (sx != sy) {
-                const uint32_t xm2 = funnel(rx[1 - 2 * ldw], rx[-2 * ldw], shx);
-                const uint32_t xm1 = funnel(rx[1 - ldw], rx[-ldw], shx);
-                const uint32_t xp1 = funnel(rx[1 + ldw], rx[ldw], shx);
-                const uint32_t xp2 = funnel(rx[1 + 2 * ldw], rx[2 * ldw], shx);
-                const uint32_t ym2 = funnel(ry[1 - 2 * ldw], ry[-2 * ldw], shy);
-                const uint32_t ym1 = funnel(ry[1 - ldw], ry[-ldw], shy);
-                const uint32_t yp1 = funnel(ry[1 + ldw], ry[ldw], shy);
-                const uint32_t yp2 = funnel(ry[1 + 2 * ldw], ry[2 * ldw], shy);
-                const int ds = sx - sy;  // +1 or -1
-                const int dsig = seg::sigma_rest16(xm2, xm1, x0, xp1, xp2) - seg::sigma_rest16(ym2, ym1, y0, yp1, yp2) +
-                                 5 * ds;
-                if (u < sT[__mul24(dsig, 3) + 76 + ds]) {  // T[(dsig + 25) * 3 + ds + 1]
-                    const int wx = p >> 5;
-                    const uint32_t bit = 1u << (p & 31);
-                    atomicXor(&rp[wx], bit);
-                    if (wx == 0) atomicXor(&rp[nw], bit);        // right pad repeats word 0
-                    if (wx == nw - 1) atomicXor(&rp[-1], bit);   // left pad repeats word nw - 1
-                    my_delta += sy ? 1 : -1;
-                }
+            const int wx = p >> 5;
+            const uint32_t bit = 1u << (p & 31);
+            atomicXor(&rp[wx], bit);
+            if (wx == 0) atomicXor(&rp[nw], bit);       // right pad repeats word 0
+            if (wx == nw - 1) atomicXor(&rp[-1], bit);  // left pad repeats word nw - 1
+            my_delta += f;
+        };
+        for (int qb = 0; qb < total; qb += 128) {
+            const int q1 = qb + lane, q2 = q1 + 64;
+            if (qb + 64 < total) {  // wave-uniform: some lanes have a second entry
+                const uint32_t e1 = list[min(q1, total - 1)], e2 = list[min(q2, total - 1)];
+                const int f1 = step(e1), f2 = step(e2);
+                if (q1 < total && f1) apply(e1, f1);
+                if (q2 < total && f2) apply(e2, f2);
+            } else if (q1 < total) {
+                const uint32_t e1 = list[q1];
+                const int f1 = step(e1);
+                if (f1) apply(e1, f1);
             }
         }
         __builtin_amdgcn_wave_barrier();

@@ -83,6 +83,45 @@ __host__ __device__ constexpr int seg_window_words(int segw) { return segw / 32 
 __host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 8; }
 __host__ __device__ constexpr int seg_wave_words(int segw) { return 7 * seg_window_words(segw) + seg_list_cap(segw); }
 
+// The elementary step of the listed site at window position p of the row
+// that rp points at (rows ld words apart, the window covering columns
+// p - 16 .. p + 15 of the rows i - 3 .. i + 3), global site index x, sweep t,
+// colour k: 0 if it keeps its strategy, else +1 (it becomes C) or -1 (D).
+// Branch-free, so that two calls interleave.
+__device__ __forceinline__ int site_step(const uint32_t* __restrict__ rp, int ld, int p, uint32_t x, uint32_t t,
+                                         uint32_t k, uint32_t k0, uint32_t k1, const uint32_t* __restrict__ sT) {
+    const uint2 rnd = philox4x32_10_w01(x, t, k, 0u, k0, k1);
+    // neighbour y = x + (di, dj) for d = w0 >> 30: 0 E, 1 W, 2 S, 3 N
+    const uint32_t d2 = (rnd.x >> 30) << 1;
+    const int di = (int)__builtin_amdgcn_ubfe(0x25u, d2, 2u) - 1;
+    const int dj = (int)__builtin_amdgcn_ubfe(0x52u, d2, 2u) - 1;
+    // rows i-2 .. i+2 around x and around y, each a 32-column window with the
+    // centre column in bit 16
+    const int px = p - 16, py = px + dj;
+    const uint32_t* rx = rp + (px >> 5);
+    const uint32_t* ry = rp + __mul24(di, ld) + (py >> 5);
+    const int shx = px & 31, shy = py & 31;
+    const uint32_t xm2 = funnel(rx[1 - 2 * ld], rx[-2 * ld], shx);
+    const uint32_t xm1 = funnel(rx[1 - ld], rx[-ld], shx);
+    const uint32_t x0 = funnel(rx[1], rx[0], shx);
+    const uint32_t xp1 = funnel(rx[1 + ld], rx[ld], shx);
+    const uint32_t xp2 = funnel(rx[1 + 2 * ld], rx[2 * ld], shx);
+    const uint32_t ym2 = funnel(ry[1 - 2 * ld], ry[-2 * ld], shy);
+    const uint32_t ym1 = funnel(ry[1 - ld], ry[-ld], shy);
+    const uint32_t y0 = funnel(ry[1], ry[0], shy);
+    const uint32_t yp1 = funnel(ry[1 + ld], ry[ld], shy);
+    const uint32_t yp2 = funnel(ry[1 + 2 * ld], ry[2 * ld], shy);
+    const int sx = (int)((x0 >> 16) & 1u);
+    const int sy = (int)((y0 >> 16) & 1u);
+    const int ds = sx - sy;
+    // Sigma = rest + 5 s, so Sigma_x - Sigma_y = rest_x - rest_y + 5 ds; the
+    // index stays inside the table for ds = 0 too (rest lies in [0, 20])
+    const int dsig = seg::sigma_rest16(xm2, xm1, x0, xp1, xp2) - seg::sigma_rest16(ym2, ym1, y0, yp1, yp2) + 5 * ds;
+    const uint32_t thr = sT[__mul24(dsig, 3) + 76 + ds];  // T[(dsig + 25) * 3 + ds + 1]
+    const bool flip = (ds != 0) & (rnd.y < thr);
+    return flip ? (sy ? 1 : -1) : 0;
+}
+
 // Segment geometry of one wave: row i of residue a, owned columns [s, e),
 // window bit 0 at column c0 = s - 64.
 struct SegPos {
@@ -201,47 +240,34 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         }
         __builtin_amdgcn_wave_barrier();
         my_drawn += lane == 0 ? total : 0;
-        // 3. the elementary steps of the listed sites.
+        // 3. the elementary steps of the listed sites, two per lane per step
+        // (both decided before either flips: sites of one class never read
+        // each other's strategy).
         const uint32_t k = k_first + (uint32_t)b;
-        for (int q = lane; q < total; q += 64) {
-            const int p = (int)list[q];
-            // column c0 + p modulo L (it lies in [-L, 2L)): the wrapped value is
-            // the least of c, c + L and c - L taken as unsigned numbers
+        const uint32_t row_base = (uint32_t)(i * L);
+        auto site_of = [&](int p) {
+            // column c0 + p modulo L (it lies in [-L, 2L)): the least of c,
+            // c + L and c - L taken as unsigned numbers
             const uint32_t c = (uint32_t)(c0 + p);
-            const uint32_t cw = min(min(c, c + (uint32_t)L), c - (uint32_t)L);
-            const uint2 rnd = philox4x32_10_w01((uint32_t)(i * L) + cw, t, k, 0u, k0, k1);
-            const uint32_t u = rnd.y;
-            // neighbour y = x + (di, dj) for d = w0 >> 30: 0 E, 1 W, 2 S, 3 N
-            const uint32_t d2 = (rnd.x >> 30) << 1;
-            const int di = (int)__builtin_amdgcn_ubfe(0x25u, d2, 2u) - 1;
-            const int dj = (int)__builtin_amdgcn_ubfe(0x52u, d2, 2u) - 1;
-            // Rows i-2 .. i+2 around x and around y, each a 32-column window
-            // with the centre column in bit 16.
-            const int px = p - 16, py = px + dj;
-            const uint32_t* rx = r0 + (px >> 5);
-            const uint32_t* ry = r0 + __mul24(di, WB) + (py >> 5);
-            const int shx = px & 31, shy = py & 31;
-            const uint32_t x0 = funnel(rx[1], rx[0], shx);
-            const uint32_t y0 = funnel(ry[1], ry[0], shy);
-            const int sx = (int)((x0 >> 16) & 1u);
-            const int sy = (int)((y0 >> 16) & 1u);
-            if (sx != sy) {
-                const uint32_t xm2 = funnel(rx[1 - 2 * WB], rx[-2 * WB], shx);
-                const uint32_t xm1 = funnel(rx[1 - WB], rx[-WB], shx);
-                const uint32_t xp1 = funnel(rx[1 + WB], rx[WB], shx);
-                const uint32_t xp2 = funnel(rx[1 + 2 * WB], rx[2 * WB], shx);
-                const uint32_t ym2 = funnel(ry[1 - 2 * WB], ry[-2 * WB], shy);
-                const uint32_t ym1 = funnel(ry[1 - WB], ry[-WB], shy);
-                const uint32_t yp1 = funnel(ry[1 + WB], ry[WB], shy);
-                const uint32_t yp2 = funnel(ry[1 + 2 * WB], ry[2 * WB], shy);
-                const int ds = sx - sy;  // +1 or -1
-                // Sigma = rest + 5 s, so Sigma_x - Sigma_y = rest_x - rest_y + 5 ds
-                const int dsig = seg::sigma_rest16(xm2, xm1, x0, xp1, xp2) - seg::sigma_rest16(ym2, ym1, y0, yp1, yp2) +
-                                 5 * ds;
-                if (u < sT[__mul24(dsig, 3) + 76 + ds]) {  // T[(dsig + 25) * 3 + ds + 1]
-                    atomicXor(&r0[p >> 5], 1u << (p & 31));
-                    if (p >= 64 && p < 64 + (e - s)) my_delta += sy ? 1 : -1;
-                }
+            return row_base + min(min(c, c + (uint32_t)L), c - (uint32_t)L);
+        };
+        auto apply = [&](int p, int f) {
+            atomicXor(&r0[p >> 5], 1u << (p & 31));
+            if (p >= 64 && p < 64 + (e - s)) my_delta += f;
+        };
+        for (int qb = 0; qb < total; qb += 128) {
+            const int q1 = qb + lane, q2 = q1 + 64;
+            if (qb + 64 < total) {  // wave-uniform: some lanes have a second entry
+                const int p1 = (int)list[min(q1, total - 1)];
+                const int p2 = (int)list[min(q2, total - 1)];
+                const int f1 = site_step(r0, WB, p1, site_of(p1), t, k, k0, k1, sT);
+                const int f2 = site_step(r0, WB, p2, site_of(p2), t, k, k0, k1, sT);
+                if (q1 < total && f1) apply(p1, f1);
+                if (q2 < total && f2) apply(p2, f2);
+            } else if (q1 < total) {
+                const int p1 = (int)list[q1];
+                const int f1 = site_step(r0, WB, p1, site_of(p1), t, k, k0, k1, sT);
+                if (f1) apply(p1, f1);
             }
         }
         __builtin_amdgcn_wave_barrier();
