@@ -254,7 +254,8 @@ def main():
     ap.add_argument("--r", type=float, default=wl.R_CRITICAL)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel", default="segment",
-                    choices=["segment", "strip", "rowband_staged", "rowband_compact", "rowband", "colour"])
+                    choices=["segment", "segment_pair", "strip", "rowband_staged", "rowband_compact", "rowband",
+                             "colour"])
     ap.add_argument("--tile", type=int, default=0, help="segment width / strip height / rows per band (0 = auto)")
     ap.add_argument("--group", type=int, default=0, help="segment kernel: waves per workgroup (0 = 4)")
     ap.add_argument("--dense-steps", type=int, default=200)
@@ -306,7 +307,7 @@ def main():
     value = updates / dt
 
     dense = None
-    if args.kernel in ("segment", "strip", "rowband_compact", "rowband_staged") and args.dense_steps > 0:
+    if args.kernel in ("segment", "segment_pair", "strip", "rowband_compact", "rowband_staged") and args.dense_steps > 0:
         log("dense pass: %d sweeps" % args.dense_steps)
         ddt, _, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", layout, args.warmup,
                                 args.dense_steps, stream)
@@ -334,7 +335,7 @@ def main():
                 "frac": achieved_tops / VALU_PEAK_TOPS,
                 "traffic": measured_traffic(args.kernel, L, args.tile, args.group),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": {"segment": "k_ens_segment", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
+                "kernel": {"segment": "k_ens_segment", "segment_pair": "k_ens_pair", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
                            "rowband_compact": "k_rowband_bits<true>",
                            "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,

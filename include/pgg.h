@@ -104,7 +104,19 @@ typedef enum {
                                on the segment plus a margin of 9/6/3/0 columns
                                (recomputed by both neighbouring segments) and
                                writes back its own columns; sites without a
-                               differing neighbour draw nothing                  */
+                               differing neighbour draw nothing.  With L a
+                               multiple of 32 (automatic up to L = 1024, or
+                               tile = L) a wave owns whole rows instead and
+                               recomputes nothing                                */,
+    PGG_KERNEL_SEGMENT_PAIR = 7 /* bits only, L a multiple of 32, L >= 512: the
+                               segment update with two row residues per launch
+                               (two launches per sweep): a workgroup stages a
+                               band of 32 rows plus 6 halo rows each side once,
+                               runs residue a on its rows and the 3-row halos
+                               (with 12 more margin columns), synchronises, and
+                               runs residue a + 1 on its rows.  tile: segment
+                               width, a multiple of 32 up to L - 64 (0 =
+                               automatic); group must be 0                       */
 } pgg_kernel;
 
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */

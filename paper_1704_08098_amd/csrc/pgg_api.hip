@@ -58,6 +58,8 @@ struct pgg_sim {
     std::vector<hipGraph_t> graph_defs;
     int seg_waves = 0;
     size_t seg_lds = 0;
+    bool pair = false;  // SEGMENT_PAIR: two residues per launch
+    int launches_per_sweep = 4;
     int wpg = pgg::kWavesPerGroup;
     int stride = 0;  // bits layout: 32-bit words per row
     int kernel = PGG_KERNEL_COLOUR;
@@ -125,6 +127,16 @@ int choose_segw(uint32_t L, int wpg) {
     return w;
 }
 
+// Paired kernel: segments of about 1376 columns, at most L - 64.
+int choose_pair_segw(uint32_t L) {
+    const int nseg = ((int)L + 1375) / 1376;
+    int w = ((int)L / nseg + 31) & ~31;
+    const int cap = ((int)L - 64) & ~31;
+    if (w > cap) w = cap;
+    while (w > 32 && pgg::pair_lds_bytes(w) > pgg::kMaxDynamicLds) w -= 32;
+    return w;
+}
+
 bool strip_fits(uint32_t L, uint32_t H) {
     return pgg::strip_lds_bytes((int)L, (int)H, 1) <= pgg::kMaxDynamicLds;
 }
@@ -167,6 +179,17 @@ bool params_valid(const pgg_params* p, const char** why) {
             if (!pgg::ens_wpg_valid(wpg)) { *why = "group must be 0, 2, 4 or 8"; return false; }
             if (segment_lds(p->L, tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::kMaxDynamicLds) {
                 *why = "the segment kernel's LDS footprint does not fit at this tile and group";
+                return false;
+            }
+            break;
+        }
+        case PGG_KERNEL_SEGMENT_PAIR: {
+            if (p->layout != PGG_LAYOUT_BITS) { *why = "the paired segment kernel needs the bits layout"; return false; }
+            if (p->L < 512 || p->L % 32 != 0) { *why = "the paired segment kernel needs L >= 512, a multiple of 32"; return false; }
+            if (tr != 0 && (tr % 32 != 0 || tr + 64 > p->L)) { *why = "paired segment tile must be a multiple of 32 and <= L - 64"; return false; }
+            if (p->group != 0) { *why = "the paired segment kernel takes no group"; return false; }
+            if (pgg::pair_lds_bytes(tr ? (int)tr : choose_pair_segw(p->L)) > pgg::kMaxDynamicLds) {
+                *why = "the paired segment kernel's LDS footprint does not fit at this tile";
                 return false;
             }
             break;
@@ -365,8 +388,15 @@ pgg_status plan_segment_graph(pgg_sim* s) {
     rp.delta = s->d_gdelta;
     rp.nc = s->d_nc;
     rp.drawn = nullptr;
-    s->seg_waves = pgg::ens_waves(rp, s->wpg);
-    s->seg_lds = pgg::ens_lds_bytes(pgg::ens_wave_words(rp), s->wpg);
+    if (s->pair) {
+        s->seg_waves = pgg::pair_blocks(rp);  // workgroups of one launch
+        s->seg_lds = pgg::pair_lds_bytes(rp.segw);
+        s->launches_per_sweep = 2;
+    } else {
+        s->seg_waves = pgg::ens_waves(rp, s->wpg);
+        s->seg_lds = pgg::ens_lds_bytes(pgg::ens_wave_words(rp), s->wpg);
+        s->launches_per_sweep = 4;
+    }
     const pgg::EnsRep both[2] = {rp, rp};
     e = hipMemcpy(s->d_rep, both, sizeof(both), hipMemcpyHostToDevice);
     if (e != hipSuccess) { set_err("segment graph descriptor: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
@@ -384,8 +414,12 @@ hipError_t segment_graph(pgg_sim* s, int len, bool timing, hipGraphExec_t* out) 
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t enq = timing ? pgg::launch_span_reset(s->d_span, 4 * len, s->capture_stream) : hipSuccess;
-    if (enq == hipSuccess)
+    hipError_t enq =
+        timing ? pgg::launch_span_reset(s->d_span, s->launches_per_sweep * len, s->capture_stream) : hipSuccess;
+    if (enq == hipSuccess && s->pair)
+        enq = pgg::launch_pair_chunk(s->d_rep + (timing ? 1 : 0), s->seg_waves, s->seg_lds, len, kGraphChunk,
+                                     s->d_gcounts, s->capture_stream, timing ? s->d_span : nullptr);
+    else if (enq == hipSuccess)
         enq = pgg::launch_ens_chunk(s->d_rep + (timing ? 1 : 0), 1, s->seg_waves, s->seg_lds, len, kGraphChunk, true,
                                     s->d_gcounts, s->capture_stream, s->wpg, timing ? s->d_span : nullptr);
     e = hipStreamEndCapture(s->capture_stream, &g);
@@ -406,15 +440,16 @@ hipError_t segment_graph(pgg_sim* s, int len, bool timing, hipGraphExec_t* out) 
 // event time and every launch's span (latest end minus earliest start over
 // its records) to the totals.
 pgg_status fold_segment_timing(pgg_sim* s, int len) {
-    std::vector<unsigned long long> span((size_t)4 * len * pgg::kSpanWords);
+    const int nl = s->launches_per_sweep * len;
+    std::vector<unsigned long long> span((size_t)nl * pgg::kSpanWords);
     PGG_HIP(s, hipMemcpyAsync(span.data(), s->d_span, span.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                               s->stream));
     PGG_HIP(s, hipStreamSynchronize(s->stream));
     float ms = 0.f;
     PGG_HIP(s, hipEventElapsedTime(&ms, s->chunk_ev[0], s->chunk_ev[1]));
     s->timed_ms += ms;
-    s->timed_launches += 4 * (uint64_t)len;
-    for (int l = 0; l < 4 * len; ++l) {
+    s->timed_launches += (uint64_t)nl;
+    for (int l = 0; l < nl; ++l) {
         unsigned long long lo = ~0ull, hi = 0ull;
         for (int x = 0; x < pgg::kSpanSlots; ++x) {
             lo = std::min(lo, span[(size_t)pgg::kSpanWords * l + 2 * x]);
@@ -521,6 +556,11 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
         s->kernel = p->L >= 64 ? PGG_KERNEL_SEGMENT : PGG_KERNEL_ROWBAND_COMPACT;
     s->wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
     if (s->kernel == PGG_KERNEL_SEGMENT) s->segw = p->tile ? (int)p->tile : choose_segw(p->L, s->wpg);
+    if (s->kernel == PGG_KERNEL_SEGMENT_PAIR) {
+        s->segw = p->tile ? (int)p->tile : choose_pair_segw(p->L);
+        s->pair = true;
+    }
+    const bool segment_path = s->kernel == PGG_KERNEL_SEGMENT || s->kernel == PGG_KERNEL_SEGMENT_PAIR;
 
     auto alloc = [&](void** ptr, size_t bytes) -> pgg_status {
         hipError_t e = hipMalloc(ptr, bytes);
@@ -542,8 +582,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK) st = alloc((void**)&s->d_delta, (size_t)kChunk * pgg::kSweepWords * sizeof(unsigned long long));
     if (st == PGG_OK) st = alloc((void**)&s->d_counts, kChunk * sizeof(unsigned long long));
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
-    if (st == PGG_OK && s->kernel == PGG_KERNEL_SEGMENT) st = alloc((void**)&s->lattice2, lattice_bytes(p));
-    if (st == PGG_OK && s->kernel == PGG_KERNEL_SEGMENT) st = plan_segment_graph(s);
+    if (st == PGG_OK && segment_path) st = alloc((void**)&s->lattice2, lattice_bytes(p));
+    if (st == PGG_OK && segment_path) st = plan_segment_graph(s);
     if (st != PGG_OK) { release(s); return st; }
 
     hipError_t e = pgg::launch_build_table(p->r, p->K, s->d_table, s->stream);
@@ -568,7 +608,8 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     }
     if (n_sweeps == 0) return PGG_OK;
     DeviceGuard guard(s->device);
-    if (s->kernel == PGG_KERNEL_SEGMENT) return sweep_segment(s, n_sweeps, coop_counts);
+    if (s->kernel == PGG_KERNEL_SEGMENT || s->kernel == PGG_KERNEL_SEGMENT_PAIR)
+        return sweep_segment(s, n_sweeps, coop_counts);
     const int L = (int)s->p.L;
     uint32_t done = 0;
     while (done < n_sweeps) {

@@ -77,7 +77,10 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigne
         if (active) segment_run(next, rp.L, rp.stride, a, rp.segw, g, t, rp.k0, rp.k1, sT, win, my_delta, my_drawn);
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        my_delta += __shfl_xor(my_delta, off, 64);
+        my_drawn += __shfl_xor(my_drawn, off, 64);
+    }
     if (lane == 0) {
         s_part[wid] = my_delta;
         s_part[WPG + wid] = my_drawn;
@@ -94,6 +97,104 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigne
                       (unsigned long long)(long long)dsum);
         if (rp.drawn && nsum) atomicAdd(slot_of(rp.drawn, (int)blockIdx.x), (unsigned long long)nsum);
         if (span) {  // diagnostics: earliest start and latest end over kSpanSlots spread pairs
+            unsigned long long* sp = span + 2 * (blockIdx.x & (kSpanSlots - 1));
+            atomicMin(sp, t_begin);
+            atomicMax(sp + 1, wall_clock64());
+        }
+    }
+}
+
+// Two row residues per launch (residues a and a + 1, a = 0 or 2) for one
+// lattice (reps[0], segments of rp.segw columns, L a multiple of 32).  A
+// workgroup stages rows R0 - 6 .. R1 + 5 of its band [R0, R1) (kPairBand rows)
+// and its segment's columns s - 64 .. e + 63 once.  Residue a then runs on its
+// rows in [R0 - 1, R1 + 3) -- those a row of residue a + 1 in the band reads
+// (rows i - 1 and i + 3) -- each class with 12 more margin columns, so that
+// every row and column the second residue reads is exact; after a workgroup
+// barrier residue a + 1 runs on the band's rows.
+// Only band rows and owned columns are written back and counted.  Rows of
+// residue below a come from next (this sweep), the others from cur.
+template <int B>
+__global__ void __launch_bounds__(64 * (B / 4 + 1))
+k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __restrict__ span) {
+    constexpr int NW = B / 4 + 1;
+    extern __shared__ uint32_t smem[];
+    __shared__ int s_part[2 * NW];
+    const unsigned long long t_begin = span ? wall_clock64() : 0ull;
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const EnsRep rp = reps[0];
+    const int L = rp.L, segw = rp.segw, nseg = rp.nseg, stride = rp.stride, nw = rp.nw;
+    const int WB = seg_window_words(segw), cap = seg_list_cap(segw);
+    const int blk = xcd_major((int)blockIdx.x, (int)gridDim.x);  // neighbouring bands share an XCD
+    const int band = blk / nseg, sg = blk - band * nseg;
+    const int R0 = band * B, R1 = min(R0 + B, L);
+    const int s = sg * segw, e = min(L, s + segw), c0 = s - 64;
+    uint32_t* sT = smem;
+    uint32_t* wwin = smem + 160;            // (B + 12) rows x WB
+    uint32_t* lists = wwin + (B + 12) * WB;  // NW x cap
+    const bool on = q < rp.n_active;
+    const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
+    uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
+    const uint32_t t = rp.t0 + (uint32_t)q;
+    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    if (on) {
+        const int w0 = c0 >> 5;  // segments start on word boundaries (L % 32 == 0)
+        for (int k = threadIdx.x; k < (B + 12) * WB; k += blockDim.x) {
+            const int o = k / WB, w = k - o * WB;
+            int gi = R0 - 6 + o;  // in [-6, L + B + 6)
+            gi += (gi < 0) ? L : 0;
+            gi -= (gi >= L) ? L : 0;
+            int widx = w0 + w;  // in [-2, nw + 2)
+            widx += (widx < 0) ? nw : 0;
+            widx -= (widx >= nw) ? nw : 0;
+            const uint32_t* src = ((gi & 3) < a) ? next : cur;
+            wwin[k] = src[(size_t)gi * stride + widx];
+        }
+    }
+    __syncthreads();
+    int my_delta = 0, my_drawn = 0;
+    // residue a: rows in [R0 - 1, R1 + 3) (R0 is a multiple of 4)
+    {
+        const int i = R0 - 1 + ((a + 1) & 3) + 4 * wid;
+        if (on && i < R1 + 3) {
+            const int gi = i < 0 ? i + L : (i >= L ? i - L : i);
+            const SegPos g = {gi, s, e, c0};
+            segment_run_row(next, L, stride, a, segw, g, t, rp.k0, rp.k1, sT, wwin + (i - (R0 - 6)) * WB,
+                            lists + wid * cap, 12, i >= R0 && i < R1, my_delta, my_drawn);
+        }
+    }
+    __syncthreads();
+    // residue a + 1: band rows (R0 is a multiple of 4)
+    {
+        const int i = R0 + a + 1 + 4 * wid;
+        if (on && i < R1) {
+            const SegPos g = {i, s, e, c0};
+            segment_run_row(next, L, stride, a + 1, segw, g, t, rp.k0, rp.k1, sT, wwin + (i - (R0 - 6)) * WB,
+                            lists + wid * cap, 0, true, my_delta, my_drawn);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        my_delta += __shfl_xor(my_delta, off, 64);
+        my_drawn += __shfl_xor(my_drawn, off, 64);
+    }
+    if (lane == 0) {
+        s_part[wid] = my_delta;
+        s_part[NW + wid] = my_drawn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int dsum = 0, nsum = 0;
+        for (int k = 0; k < NW; ++k) {
+            dsum += s_part[k];
+            nsum += s_part[NW + k];
+        }
+        if (dsum)
+            atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
+                      (unsigned long long)(long long)dsum);
+        if (rp.drawn && nsum) atomicAdd(slot_of(rp.drawn, (int)blockIdx.x), (unsigned long long)nsum);
+        if (span) {
             unsigned long long* sp = span + 2 * (blockIdx.x & (kSpanSlots - 1));
             atomicMin(sp, t_begin);
             atomicMax(sp + 1, wall_clock64());
@@ -290,6 +391,26 @@ hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, 
                                      span ? span + kSpanWords * (4 * q + a) : nullptr);
     if (err != hipSuccess) return err;
     return launch_ens_end(d_reps, n, chunk, counts, st);
+}
+
+size_t pair_lds_bytes(int segw) {
+    return (160 + (size_t)(kPairBand + 12) * seg_window_words(segw) +
+            (size_t)(kPairBand / 4 + 1) * seg_list_cap(segw)) * sizeof(uint32_t);
+}
+
+int pair_blocks(const EnsRep& rp) { return (rp.L + kPairBand - 1) / kPairBand * rp.nseg; }
+
+hipError_t launch_pair_chunk(EnsRep* d_rep, int blocks, size_t lds, int len, int chunk, unsigned long long* counts,
+                             hipStream_t st, unsigned long long* span) {
+    hipError_t err = launch_ens_begin(d_rep, 1, len, chunk, true, st);
+    for (int q = 0; err == hipSuccess && q < len; ++q)
+        for (int h = 0; err == hipSuccess && h < 2; ++h) {
+            hipLaunchKernelGGL(k_ens_pair<kPairBand>, dim3(blocks), dim3(64 * (kPairBand / 4 + 1)), lds, st, d_rep,
+                               2 * h, q, span ? span + kSpanWords * (2 * q + h) : nullptr);
+            err = hipGetLastError();
+        }
+    if (err != hipSuccess) return err;
+    return launch_ens_end(d_rep, 1, chunk, counts, st);
 }
 
 }  // namespace pgg

@@ -59,7 +59,8 @@ __device__ __forceinline__ void fullrow_fill(const uint32_t* __restrict__ cur, c
 
 // The four classes on the nrows (<= R) owned rows, then the rows written to
 // next.  Adds the net change of the cooperator count to my_delta (every
-// lane) and the number of draws to my_drawn (lane 0).
+// lane) and the number of draws to my_drawn (per lane; the caller sums over
+// the wave).
 __device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, int stride, int a, int i0, int R,
                                             int nrows, uint32_t t, uint32_t k0, uint32_t k1,
                                             const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
@@ -90,6 +91,7 @@ __device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, 
             }
             // 2. compacted list: entry = r << 16 | column
             const int cnt = __popc(act);
+            my_drawn += cnt;
             int pos = total;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -105,7 +107,6 @@ __device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, 
             }
         }
         __builtin_amdgcn_wave_barrier();
-        my_drawn += lane == 0 ? total : 0;
         // 3. the elementary steps of the listed sites, two per lane per step
         // (both decided before either flips: sites of one class never read
         // each other's strategy).  Columns p - 16 .. p + 15 lie within the

@@ -134,6 +134,15 @@ constexpr int kSpanWords = 2 * kSpanSlots;
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
                               hipStream_t st, int wpg = kWavesPerGroup, unsigned long long* span = nullptr);
 hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st);
+// Two residues per launch for one lattice (pgg_ensemble.hip, k_ens_pair):
+// workgroups of kPairBand rows x one segment; d_rep holds the one replica.
+constexpr int kPairBand = 32;
+size_t pair_lds_bytes(int segw);
+int pair_blocks(const EnsRep& rp);
+// One chunk of len sweeps, 2 launches per sweep (residues 0-1, then 2-3).
+hipError_t launch_pair_chunk(EnsRep* d_rep, int blocks, size_t lds, int len, int chunk, unsigned long long* counts,
+                             hipStream_t st, unsigned long long* span);
+
 // Set n_launches span records (kSpanWords words each) to (~0, 0) pairs.
 hipError_t launch_span_reset(unsigned long long* span, int n_launches, hipStream_t st);
 // Set the sweep index t0 of every replica (graph-safe, no host memory).

@@ -71,6 +71,11 @@ __device__ __forceinline__ int sigma_rest16(uint32_t a2, uint32_t a1, uint32_t b
     return ones + 2 * twos;
 }
 
+// Bits [lo, hi) of a 32-bit word (0 <= lo <= hi <= 32).
+__device__ __forceinline__ uint32_t bit_range(int lo, int hi) {
+    return (uint32_t)((1ull << hi) - (1ull << lo));
+}
+
 // Number of set bits of a wave-wide mask below the calling lane.
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -80,7 +85,8 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 
 // Window words per row and list capacity per class for a segment width.
 __host__ __device__ constexpr int seg_window_words(int segw) { return segw / 32 + 4; }
-__host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 8; }
+// (class-b sites of a segment plus margins of up to 21 columns each side)
+__host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 16; }
 __host__ __device__ constexpr int seg_wave_words(int segw) { return 7 * seg_window_words(segw) + seg_list_cap(segw); }
 
 // The elementary step of the listed site at window position p of the row
@@ -186,24 +192,31 @@ __device__ __forceinline__ void segment_fill(const uint32_t* __restrict__ cur, c
 // The four colour classes on the filled window, then the owned columns
 // written to next.  sT: the threshold table in LDS.  Adds the net change of
 // the cooperator count over the owned columns to my_delta (every lane) and
-// the number of draws to my_drawn (lane 0).
-__device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, int stride, int a, int segw,
-                                            const SegPos& g, uint32_t t, uint32_t k0, uint32_t k1,
-                                            const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
-                                            int& my_delta, int& my_drawn) {
+// the number of draws of owned sites to my_drawn (per lane; the caller sums
+// over the wave).
+//
+// r0: the row's window (rows r0 - 3 WB .. r0 + 3 WB hold rows i-3 .. i+3);
+// list: seg_list_cap(segw) words of the wave's own.  extra widens every
+// class's margin (a launch that runs a second residue after this one needs
+// this row exact on 3 x 4 more columns each side).  A row that is not owned
+// (a halo row another workgroup owns) is updated in LDS only: no counts, no
+// write-back.
+__device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int L, int stride, int a, int segw,
+                                                const SegPos& g, uint32_t t, uint32_t k0, uint32_t k1,
+                                                const uint32_t* __restrict__ sT, uint32_t* __restrict__ r0,
+                                                uint32_t* __restrict__ list, int extra, bool owned_row,
+                                                int& my_delta, int& my_drawn) {
     using namespace seg;
     const int lane = threadIdx.x & 63;
     const int WB = seg_window_words(segw);
-    uint32_t* list = win + 7 * WB;
     const int i = g.i, s = g.s, e = g.e, c0 = g.c0;
     __builtin_amdgcn_wave_barrier();
 
-    uint32_t* r0 = win + 3 * WB;  // the row being updated
     const uint32_t k_first = (uint32_t)(4 * a);
 #pragma unroll 1
     for (int b = 0; b < 4; ++b) {
         // Class-b sites on window positions [lo, hi).
-        const int m = 9 - 3 * b;
+        const int m = extra + 9 - 3 * b;
         const int lo = 64 - m, hi = 64 + (e - s) + m;
         const int wlo = lo >> 5, whi = (hi + 31) >> 5;
         // 1. candidates per word (the class-b bits), 2. compacted list: each
@@ -223,6 +236,9 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
                 act = ((X ^ E) | (X ^ Wn) | (X ^ r0[w - WB]) | (X ^ r0[w + WB])) & (0x11111111u << b);
                 if (w == wlo) act &= m_first;
                 if (w == whi - 1) act &= m_last;
+                // draws of owned sites (margin sites are recomputed copies)
+                const int own_lo = max(64 - 32 * w, 0), own_hi = min(64 + (e - s) - 32 * w, 32);
+                if (owned_row && own_hi > own_lo) my_drawn += __popc(act & bit_range(own_lo, own_hi));
             }
             const int cnt = __popc(act);
             int pos = total;
@@ -239,7 +255,6 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
             }
         }
         __builtin_amdgcn_wave_barrier();
-        my_drawn += lane == 0 ? total : 0;
         // 3. the elementary steps of the listed sites, two per lane per step
         // (both decided before either flips: sites of one class never read
         // each other's strategy).
@@ -253,7 +268,7 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         };
         auto apply = [&](int p, int f) {
             atomicXor(&r0[p >> 5], 1u << (p & 31));
-            if (p >= 64 && p < 64 + (e - s)) my_delta += f;
+            if (owned_row && p >= 64 && p < 64 + (e - s)) my_delta += f;
         };
         for (int qb = 0; qb < total; qb += 128) {
             const int q1 = qb + lane, q2 = q1 + 64;
@@ -274,6 +289,7 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
     }
 
     // Write back the owned columns [s, e): window words 2 .. 2 + ceil((e-s)/32).
+    if (!owned_row) return;
     const int nown = (e - s + 31) >> 5;
     for (int q = lane; q < nown; q += 64) {
         uint32_t v = r0[2 + q];
@@ -281,6 +297,17 @@ __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, 
         if (valid < 32) v &= (1u << valid) - 1u;
         next[(size_t)i * stride + (s >> 5) + q] = v;
     }
+}
+
+// One wave's segment with its private 7-row window (win: 7 WB words, then
+// the list).
+__device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, int stride, int a, int segw,
+                                            const SegPos& g, uint32_t t, uint32_t k0, uint32_t k1,
+                                            const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
+                                            int& my_delta, int& my_drawn) {
+    const int WB = seg_window_words(segw);
+    segment_run_row(next, L, stride, a, segw, g, t, k0, k1, sT, win + 3 * WB, win + 7 * WB, 0, true, my_delta,
+                    my_drawn);
 }
 
 }  // namespace pgg

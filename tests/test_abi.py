@@ -66,6 +66,10 @@ def test_device_bytes(pgg):
                                 dict(kernel="rowband", group=4), dict(layout="int8", group=4),
                                 dict(L=32768, kernel="segment", tile=32736),
                                 dict(L=100, kernel="segment", tile=100),
+                                dict(L=480, kernel="segment_pair"), dict(L=516, kernel="segment_pair"),
+                                dict(L=512, kernel="segment_pair", tile=480),
+                                dict(L=512, kernel="segment_pair", group=4),
+                                dict(layout="int8", L=512, kernel="segment_pair"),
                                 dict(L=16384, kernel="segment", tile=8192, group=8)])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")

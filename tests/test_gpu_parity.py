@@ -14,6 +14,8 @@ pytestmark = pytest.mark.gpu
 
 VARIANTS = [("int8", "colour"), ("bits", "rowband"), ("bits", "rowband_compact"),
             ("bits", "rowband_staged"), ("bits", "strip"), ("bits", "segment")]
+# kernels for lattices of L >= 512, a multiple of 32, beside all the others
+LARGE_VARIANTS = VARIANTS + [("bits", "segment_pair")]
 
 
 def say(*a):
@@ -203,7 +205,7 @@ def test_caller_buffer_and_stream(pgg, oracle_lib):
     assert np.array_equal(bits, ref)
 
 
-@pytest.mark.parametrize("layout,kernel", VARIANTS)
+@pytest.mark.parametrize("layout,kernel", LARGE_VARIANTS)
 def test_scan_size_against_oracle(pgg, oracle_lib, layout, kernel):
     """L = 1024 (the r-scan lattice) at r = 3.75: 12 sweeps, bit for bit."""
     L, r, seed, n = 1024, 3.75, 110, 12
@@ -221,7 +223,7 @@ def decay_reference(oracle_lib):
     return oracle_lib.run(L, r, 0.5, 0.5, seed, n)
 
 
-@pytest.mark.parametrize("layout,kernel", VARIANTS)
+@pytest.mark.parametrize("layout,kernel", LARGE_VARIANTS)
 def test_full_size_L4096_against_oracle(pgg, decay_reference, layout, kernel):
     """L = 4096 at r_c: init and the first two sweeps, bit for bit."""
     L, r, seed = wl.DECAY["L"], wl.DECAY["r_values"][1], wl.DECAY["seeds"][0]
@@ -238,7 +240,7 @@ def test_kernels_agree_at_benchmark_size(pgg):
     the running count equals a recount of the lattice (any-size properties)."""
     L, r, seed, n = wl.DECAY["L"], wl.DECAY["r_values"][1], 1, 400
     results = []
-    for layout, kernel in VARIANTS:
+    for layout, kernel in LARGE_VARIANTS:
         say("bench size", layout, kernel)
         with pgg.Sim(L, r, 0.5, 0.5, seed, layout, kernel) as sim:
             c = sim.sweep(n)
@@ -400,3 +402,23 @@ def test_whole_rows_and_segments_agree_at_L1024(pgg):
     for c, lat in out[1:]:
         assert np.array_equal(c, out[0][0])
         assert np.array_equal(lat, out[0][1])
+
+
+@pytest.mark.parametrize("L,tile", [(512, 0), (512, 448), (544, 96), (640, 576), (1024, 256), (2048, 0)])
+def test_segment_pair_against_oracle(pgg, oracle_lib, L, tile):
+    """Two residues per launch: bands of 32 rows with their halo rows, 12
+    extra margin columns for the first residue; every sweep bit for bit,
+    including segments that do not divide L and the last segment's wrap."""
+    r, seed, n = 3.8, 300 + L + tile, 10
+    s0, _ = oracle_lib.init(L, 0.5, seed)
+    say("segment_pair", L, tile)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "segment_pair", tile=tile) as sim:
+        ref = s0
+        for t in range(n):
+            ref, c = oracle_lib.sweep(ref, r, 0.5, seed, t, 1)
+            assert int(sim.sweep(1)[0]) == int(c[0]), t
+        assert np.array_equal(sim.read_lattice(), ref)
+        sim.set_kernel_timing(True)
+        sim.sweep(3)
+        launches, ms, drawn = sim.kernel_timing()
+        assert launches == 6 and sim.kernel_span()[0] == 6
