@@ -57,11 +57,12 @@ SLOTS_PER_DRAWN_UPDATE = round(PHILOX_PRODUCTS * SLOTS_PER_PRODUCT) + 19 + 30 + 
 # Every site also pays the bit-parallel activity test (8 sites per 32-bit
 # word: 4 XOR, 3 OR, 1 AND, 2 window extractions) -> ~2 slots per site.
 SLOTS_PER_SITE_SCAN = 2
-# HBM traffic of the segment kernel per launch, from rocprofv3 FETCH_SIZE and
+# HBM traffic of the segment kernels per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (separate passes) scaled by what the same counters read for a
 # plain 256 MiB device copy.  The summary records a hash of the kernel's
 # sources and the launch configuration; a changed kernel reads as null.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt")
+TRAFFIC_PROFILES = {"segment": os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt"),
+                    "segment_pair": os.path.join(ROOT, "profiles", "k_ens_pair_L4096_traffic.txt")}
 KERNEL_SOURCES = ("paper_1704_08098_amd/csrc/pgg_segment.hpp", "paper_1704_08098_amd/csrc/pgg_fullrow.hpp",
                   "paper_1704_08098_amd/csrc/pgg_ensemble.hip", "paper_1704_08098_amd/csrc/pgg_device.hpp")
 
@@ -76,10 +77,11 @@ def kernel_source_hash():
 
 def measured_traffic(kernel, L, tile, group):
     """Bytes per launch from the committed counter summary, or None."""
-    if kernel != "segment" or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get(kernel)
+    if path is None or not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_PROFILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -253,7 +255,7 @@ def main():
     ap.add_argument("--L", type=int, default=wl.DECAY["L"])
     ap.add_argument("--r", type=float, default=wl.R_CRITICAL)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--kernel", default="segment",
+    ap.add_argument("--kernel", default="segment_pair",
                     choices=["segment", "segment_pair", "strip", "rowband_staged", "rowband_compact", "rowband",
                              "colour"])
     ap.add_argument("--tile", type=int, default=0, help="segment width / strip height / rows per band (0 = auto)")

@@ -69,8 +69,11 @@ typedef enum {
 
 /* Sweep kernel selection (a tuning choice; results never depend on it). */
 typedef enum {
-    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR; bits -> SEGMENT for L >= 64,
-                               ROWBAND_COMPACT below                           */
+    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR; bits -> SEGMENT_PAIR when its
+                               workgroups all fit the device at once with one
+                               or two per CU (L = 4096 on 256 CUs) and group
+                               is 0, else SEGMENT for L >= 64, ROWBAND_COMPACT
+                               below                                             */
     PGG_KERNEL_COLOUR = 1,  /* int8 only: one launch per colour class, global
                                memory, every site evaluated (reference path)   */
     PGG_KERNEL_ROWBAND = 2, /* bits only: one launch per row residue i mod 4

@@ -127,14 +127,30 @@ int choose_segw(uint32_t L, int wpg) {
     return w;
 }
 
-// Paired kernel: segments of about 1376 columns, at most L - 64.
+// Paired kernel: segments of about 1024 columns (at L = 4096: 128 bands x 4
+// segments = 512 workgroups, 2 per CU, all resident at once), at most L - 64.
 int choose_pair_segw(uint32_t L) {
-    const int nseg = ((int)L + 1375) / 1376;
+    const int nseg = ((int)L + 512) / 1024 > 0 ? ((int)L + 512) / 1024 : 1;
     int w = ((int)L / nseg + 31) & ~31;
     const int cap = ((int)L - 64) & ~31;
     if (w > cap) w = cap;
     while (w > 32 && pgg::pair_lds_bytes(w) > pgg::kMaxDynamicLds) w -= 32;
     return w;
+}
+
+// Automatic choice between the segment kernel and its paired form: the
+// paired launch (two residues) wins when its workgroups are all resident at
+// once with one or two per CU (measured: L = 4096, 512 workgroups on 256
+// CUs, 3.88e11 against 3.67e11 site updates/s); with fewer workgroups both
+// are latency-bound alike, with more the paired launch runs in rounds.
+bool pair_fits(const pgg_params* p, int device) {
+    if (p->layout != PGG_LAYOUT_BITS || p->group != 0 || p->L < 512 || p->L % 32 != 0) return false;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        return false;
+    const int segw = choose_pair_segw(p->L);
+    const long blocks = (long)((p->L + pgg::kPairBand - 1) / pgg::kPairBand) * (long)((p->L + segw - 1) / segw);
+    return blocks >= cus && blocks <= 2L * cus && pgg::pair_lds_bytes(segw) <= pgg::kMaxDynamicLds;
 }
 
 bool strip_fits(uint32_t L, uint32_t H) {
@@ -552,8 +568,10 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
         s->kernel = (int)p->kernel;
     else if (p->layout == PGG_LAYOUT_INT8)
         s->kernel = PGG_KERNEL_COLOUR;
+    else if (p->L < 64)
+        s->kernel = PGG_KERNEL_ROWBAND_COMPACT;
     else
-        s->kernel = p->L >= 64 ? PGG_KERNEL_SEGMENT : PGG_KERNEL_ROWBAND_COMPACT;
+        s->kernel = pair_fits(p, s->device) ? PGG_KERNEL_SEGMENT_PAIR : PGG_KERNEL_SEGMENT;
     s->wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
     if (s->kernel == PGG_KERNEL_SEGMENT) s->segw = p->tile ? (int)p->tile : choose_segw(p->L, s->wpg);
     if (s->kernel == PGG_KERNEL_SEGMENT_PAIR) {
