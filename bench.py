@@ -258,6 +258,9 @@ def main():
     ap.add_argument("--kernel", default="segment_pair",
                     choices=["segment", "segment_pair", "strip", "rowband_staged", "rowband_compact", "rowband",
                              "colour"])
+    ap.add_argument("--layout", default="auto", choices=["auto", "int8", "bits"],
+                    help="lattice storage (auto: int8 for the colour kernel, else bits); the segment kernels "
+                         "run an int8 lattice through a bit-packed working copy")
     ap.add_argument("--tile", type=int, default=0, help="segment width / strip height / rows per band (0 = auto)")
     ap.add_argument("--group", type=int, default=0, help="segment kernel: waves per workgroup (0 = 4)")
     ap.add_argument("--dense-steps", type=int, default=200)
@@ -290,7 +293,7 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     pgg.load()
-    layout = "int8" if args.kernel == "colour" else "bits"
+    layout = args.layout if args.layout != "auto" else ("int8" if args.kernel == "colour" else "bits")
     stream = torch.cuda.Stream()
     L, r, seed = args.L, args.r, args.seed
 
@@ -311,7 +314,7 @@ def main():
     dense = None
     if args.kernel in ("segment", "segment_pair", "strip", "rowband_compact", "rowband_staged") and args.dense_steps > 0:
         log("dense pass: %d sweeps" % args.dense_steps)
-        ddt, _, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", layout, args.warmup,
+        ddt, _, _ = time_sweeps(pgg, torch, L, r, seed, "rowband", "bits", args.warmup,
                                 args.dense_steps, stream)
         dense = {"value": float(L) * L * args.dense_steps / ddt, "unit": "site updates/s",
                  "kernel": "rowband (every site draws)", "steps": args.dense_steps,
@@ -348,7 +351,8 @@ def main():
                 "slots_per_drawn_update": SLOTS_PER_DRAWN_UPDATE,
                 "slots_per_site_scan": SLOTS_PER_SITE_SCAN}
     kernel_rate = sites_per_launch / (avg_ms * 1e-3)
-    hbm_bytes = BYTES_PER_UPDATE[layout]
+    # the segment kernels sweep a bit-packed lattice whatever the layout
+    hbm_bytes = BYTES_PER_UPDATE["bits" if args.kernel in ("segment", "segment_pair") else layout]
     hbm = {"bytes_per_update": hbm_bytes, "achieved_GBs": value * hbm_bytes / 1e9,
            "peak_GBs": HBM_PEAK_GBS, "frac": value * hbm_bytes / 1e9 / HBM_PEAK_GBS,
            "frac_int8_equivalent": value * 2.0 / 1e9 / HBM_PEAK_GBS,

@@ -69,11 +69,11 @@ typedef enum {
 
 /* Sweep kernel selection (a tuning choice; results never depend on it). */
 typedef enum {
-    PGG_KERNEL_AUTO = 0,    /* int8 -> COLOUR; bits -> SEGMENT_PAIR when its
-                               workgroups all fit the device at once with one
-                               or two per CU (L = 4096 on 256 CUs) and group
-                               is 0, else SEGMENT for L >= 64, ROWBAND_COMPACT
-                               below                                             */
+    PGG_KERNEL_AUTO = 0,    /* SEGMENT_PAIR when its workgroups all fit the
+                               device at once with one or two per CU (L = 4096
+                               on 256 CUs) and group is 0, else SEGMENT for
+                               L >= 64; below L = 64, COLOUR (int8) or
+                               ROWBAND_COMPACT (bits)                            */
     PGG_KERNEL_COLOUR = 1,  /* int8 only: one launch per colour class, global
                                memory, every site evaluated (reference path)   */
     PGG_KERNEL_ROWBAND = 2, /* bits only: one launch per row residue i mod 4
@@ -100,7 +100,7 @@ typedef enum {
                                progress for ~4 s aborts the launch, and the call
                                that observes it returns PGG_E_DEVICE.  Needs the
                                same LDS footprint limit as ROWBAND_STAGED        */,
-    PGG_KERNEL_SEGMENT = 6  /* bits only, L >= 64: one launch per row residue;
+    PGG_KERNEL_SEGMENT = 6  /* L >= 64: one launch per row residue;
                                one wave per row segment, no workgroup barriers:
                                the wave copies the 7 rows it reads into a
                                private LDS window, runs the four colour classes
@@ -110,8 +110,12 @@ typedef enum {
                                differing neighbour draw nothing.  With L a
                                multiple of 32 (automatic up to L = 1024, or
                                tile = L) a wave owns whole rows instead and
-                               recomputes nothing                                */,
-    PGG_KERNEL_SEGMENT_PAIR = 7 /* bits only, L a multiple of 32, L >= 512: the
+                               recomputes nothing.  int8 layout: the sweeps run
+                               on a bit-packed working copy that the library
+                               allocates (two bits-layout lattices); each
+                               pgg_sweep call packs the int8 lattice into it
+                               first and unpacks the result at its end        */,
+    PGG_KERNEL_SEGMENT_PAIR = 7 /* L a multiple of 32, L >= 512: the
                                segment update with two row residues per launch
                                (two launches per sweep): a workgroup stages a
                                band of 32 rows plus 6 halo rows each side once,
@@ -119,7 +123,8 @@ typedef enum {
                                (with 12 more margin columns), synchronises, and
                                runs residue a + 1 on its rows.  tile: segment
                                width, a multiple of 32 up to L - 64 (0 =
-                               automatic); group must be 0                       */
+                               automatic); group must be 0.  int8 layout: as
+                               for SEGMENT, through a bit-packed working copy */
 } pgg_kernel;
 
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
@@ -152,9 +157,9 @@ size_t pgg_device_bytes(const pgg_params* p);
 /* Create a simulation and draw its initial state (Sec. III: every player C
  * with probability p0, D otherwise), t = 0.
  *   p          host; copied, the caller keeps ownership.
- *   dev_buf    device buffer of >= pgg_device_bytes(p) bytes that will hold
- *              the lattice (e.g. a torch tensor's data_ptr()); it must stay
- *              valid until pgg_destroy.  NULL: the library allocates and
+ *   dev_buf    device buffer of >= pgg_device_bytes(p) bytes, 4-byte
+ *              aligned, that will hold the lattice (e.g. a torch tensor's
+ *              data_ptr()); it must stay valid until pgg_destroy.  NULL: the library allocates and
  *              owns the lattice memory.  Small per-handle buffers (the
  *              threshold table, counters, count history) are always
  *              allocated by the library.

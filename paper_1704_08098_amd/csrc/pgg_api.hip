@@ -45,6 +45,7 @@ struct pgg_sim {
     void* lattice = nullptr;
     bool owns_lattice = false;
     uint32_t* lattice2 = nullptr;  // segment kernel: odd sweeps of a call land here
+    uint32_t* shadow = nullptr;    // int8 layout on the segment kernels: bit-packed working lattice
     // Segment kernel: run as a one-replica ensemble.  d_rep[0] serves the
     // captured chunks (one graph per chunk length), d_rep[1] the eager
     // launches of timing mode (it also counts draws); sweep indices live in
@@ -144,7 +145,7 @@ int choose_pair_segw(uint32_t L) {
 // CUs, 3.88e11 against 3.67e11 site updates/s); with fewer workgroups both
 // are latency-bound alike, with more the paired launch runs in rounds.
 bool pair_fits(const pgg_params* p, int device) {
-    if (p->layout != PGG_LAYOUT_BITS || p->group != 0 || p->L < 512 || p->L % 32 != 0) return false;
+    if (p->group != 0 || p->L < 512 || p->L % 32 != 0) return false;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         return false;
@@ -165,7 +166,7 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_INT8 && p->layout != PGG_LAYOUT_BITS) { *why = "unknown layout"; return false; }
     const uint32_t tr = p->tile;
-    const bool segment = p->kernel == PGG_KERNEL_SEGMENT || (p->kernel == PGG_KERNEL_AUTO && p->layout == PGG_LAYOUT_BITS && p->L >= 64);
+    const bool segment = p->kernel == PGG_KERNEL_SEGMENT || (p->kernel == PGG_KERNEL_AUTO && p->L >= 64);
     if (p->group != 0 && !segment) { *why = "group applies to the segment kernel only"; return false; }
     switch (p->kernel) {
         case PGG_KERNEL_AUTO:
@@ -188,7 +189,6 @@ bool params_valid(const pgg_params* p, const char** why) {
             break;
         }
         case PGG_KERNEL_SEGMENT: {
-            if (p->layout != PGG_LAYOUT_BITS) { *why = "the segment kernel needs the bits layout"; return false; }
             if (p->L < 64) { *why = "the segment kernel needs L >= 64"; return false; }
             if (tr != 0 && !pgg::segw_valid((int)p->L, (int)tr)) { *why = "segment tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)"; return false; }
             const int wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
@@ -200,7 +200,6 @@ bool params_valid(const pgg_params* p, const char** why) {
             break;
         }
         case PGG_KERNEL_SEGMENT_PAIR: {
-            if (p->layout != PGG_LAYOUT_BITS) { *why = "the paired segment kernel needs the bits layout"; return false; }
             if (p->L < 512 || p->L % 32 != 0) { *why = "the paired segment kernel needs L >= 512, a multiple of 32"; return false; }
             if (tr != 0 && (tr % 32 != 0 || tr + 64 > p->L)) { *why = "paired segment tile must be a multiple of 32 and <= L - 64"; return false; }
             if (p->group != 0) { *why = "the paired segment kernel takes no group"; return false; }
@@ -262,6 +261,7 @@ void release(pgg_sim* s) {
     (void)hipStreamSynchronize(s->stream);
     if (s->owns_lattice && s->lattice) (void)hipFree(s->lattice);
     if (s->lattice2) (void)hipFree(s->lattice2);
+    if (s->shadow) (void)hipFree(s->shadow);
     for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipGraph_t g : s->graph_defs) (void)hipGraphDestroy(g);
     if (s->d_rep) (void)hipFree(s->d_rep);
@@ -398,7 +398,7 @@ pgg_status plan_segment_graph(pgg_sim* s) {
         set_err("segment graph buffers: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
     }
-    rp.lat = (uint32_t*)s->lattice;
+    rp.lat = s->shadow ? s->shadow : (uint32_t*)s->lattice;
     rp.lat2 = s->lattice2;
     rp.T = s->d_table;
     rp.delta = s->d_gdelta;
@@ -482,7 +482,9 @@ pgg_status fold_segment_timing(pgg_sim* s, int len) {
 // pgg_sweep for the segment kernel: graph replays.  Chunks are kGraphChunk
 // sweeps, the rest is split into powers of two, and the graphs of all these
 // lengths are captured on the first call of a mode, so no later (timed) call
-// instantiates one.  Timing mode synchronises after every chunk.
+// instantiates one.  Timing mode synchronises after every chunk.  int8
+// layout: the graphs run on the bit-packed working copy, packed from the
+// int8 lattice before the first chunk and unpacked into it after the last.
 pgg_status sweep_segment(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     static_assert((kGraphChunk & (kGraphChunk - 1)) == 0, "kGraphChunk must be a power of two");
     const bool timing = s->timing;
@@ -491,6 +493,8 @@ pgg_status sweep_segment(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         PGG_HIP(s, segment_graph(s, len, timing, &g));
     }
     PGG_HIP(s, pgg::launch_ens_set_t0(s->d_rep + (timing ? 1 : 0), 1, (uint32_t)s->t, s->stream));
+    if (s->shadow)
+        PGG_HIP(s, pgg::launch_pack((const uint8_t*)s->lattice, s->shadow, (int)s->p.L, s->stride, s->stream));
     uint32_t done = 0;
     while (done < n_sweeps) {
         const uint32_t rem = n_sweeps - done;
@@ -510,6 +514,8 @@ pgg_status sweep_segment(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         }
         done += (uint32_t)len;
     }
+    if (s->shadow)
+        PGG_HIP(s, pgg::launch_unpack(s->shadow, (uint8_t*)s->lattice, (int)s->p.L, s->stride, s->stream));
     if (coop_counts) PGG_HIP(s, hipStreamSynchronize(s->stream));
     s->t += n_sweeps;
     return PGG_OK;
@@ -549,6 +555,10 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     *out = nullptr;
     const char* why = nullptr;
     if (!params_valid(p, &why)) { set_err("invalid parameters: %s", why); return PGG_E_INVAL; }
+    if (dev_buf && ((uintptr_t)dev_buf & 3u) != 0) {
+        set_err("dev_buf must be 4-byte aligned");
+        return PGG_E_INVAL;
+    }
     if (dev_buf && dev_bytes < lattice_bytes(p)) {
         set_err("dev_buf holds %zu bytes, the lattice needs %zu", dev_bytes, lattice_bytes(p));
         return PGG_E_INVAL;
@@ -566,10 +576,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     s->R = p->tile ? (int)p->tile : choose_R(p->L);
     if (p->kernel != PGG_KERNEL_AUTO)
         s->kernel = (int)p->kernel;
-    else if (p->layout == PGG_LAYOUT_INT8)
-        s->kernel = PGG_KERNEL_COLOUR;
     else if (p->L < 64)
-        s->kernel = PGG_KERNEL_ROWBAND_COMPACT;
+        s->kernel = p->layout == PGG_LAYOUT_INT8 ? PGG_KERNEL_COLOUR : PGG_KERNEL_ROWBAND_COMPACT;
     else
         s->kernel = pair_fits(p, s->device) ? PGG_KERNEL_SEGMENT_PAIR : PGG_KERNEL_SEGMENT;
     s->wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
@@ -600,7 +608,10 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK) st = alloc((void**)&s->d_delta, (size_t)kChunk * pgg::kSweepWords * sizeof(unsigned long long));
     if (st == PGG_OK) st = alloc((void**)&s->d_counts, kChunk * sizeof(unsigned long long));
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
-    if (st == PGG_OK && segment_path) st = alloc((void**)&s->lattice2, lattice_bytes(p));
+    pgg_params bits = *p;
+    bits.layout = PGG_LAYOUT_BITS;
+    if (st == PGG_OK && segment_path && p->layout == PGG_LAYOUT_INT8) st = alloc((void**)&s->shadow, lattice_bytes(&bits));
+    if (st == PGG_OK && segment_path) st = alloc((void**)&s->lattice2, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = plan_segment_graph(s);
     if (st != PGG_OK) { release(s); return st; }
 

@@ -295,28 +295,39 @@ __global__ void k_count_bits(const uint32_t* __restrict__ lat, int64_t nwords, u
     block_add_u64(cnt, nc);
 }
 
-// int8 (0/1 bytes) -> bit-packed rows; padding bits and words are zero.
+// int8 (0/1 bytes) -> bit-packed rows; padding bits and words are zero.  One
+// thread per word, reading its 32 bytes as 4-byte groups (L is a multiple of
+// 4, so a group never crosses a row end and row starts are 4-byte aligned).
+__device__ __forceinline__ uint32_t nibble_of_bytes(uint32_t v) {
+    v &= 0x01010101u;
+    return (v | (v >> 7) | (v >> 14) | (v >> 21)) & 0xFu;
+}
+
 __global__ void k_pack(const uint8_t* __restrict__ s, uint32_t* __restrict__ lat, int L, int stride) {
     const int64_t nwords = (int64_t)L * stride;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nwords;
          q += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(q / stride), w = (int)(q - (q / stride) * stride);
+        const uint32_t* row = (const uint32_t*)(s + (size_t)i * L);
         uint32_t word = 0;
-        for (int bit = 0; bit < 32; ++bit) {
-            const int j = 32 * w + bit;
-            if (j >= L) break;
-            word |= (uint32_t)(s[(size_t)i * L + j] & 1u) << bit;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const int j = 32 * w + 4 * g;
+            if (j < L) word |= nibble_of_bytes(row[j >> 2]) << (4 * g);
         }
         lat[q] = word;
     }
 }
 
+// Bit-packed rows -> int8 bytes, one thread per 4 bytes of a row.
 __global__ void k_unpack(const uint32_t* __restrict__ lat, uint8_t* __restrict__ s, int L, int stride) {
-    const int64_t n = (int64_t)L * L;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+    const int64_t n4 = (int64_t)L * (L / 4);
+    const int q4 = L / 4;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n4;
          x += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(x / L), j = (int)(x - (x / L) * L);
-        s[x] = (uint8_t)((lat[(size_t)i * stride + (j >> 5)] >> (j & 31)) & 1u);
+        const int i = (int)(x / q4), j = 4 * (int)(x - (x / q4) * q4);
+        const uint32_t b = (lat[(size_t)i * stride + (j >> 5)] >> (j & 31)) & 0xFu;
+        ((uint32_t*)s)[x] = (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
     }
 }
 
@@ -416,7 +427,7 @@ hipError_t launch_pack(const uint8_t* s, uint32_t* lat, int L, int stride, hipSt
 }
 
 hipError_t launch_unpack(const uint32_t* lat, uint8_t* s, int L, int stride, hipStream_t st) {
-    hipLaunchKernelGGL(k_unpack, dim3(grid_for((int64_t)L * L, 256)), dim3(256), 0, st, lat, s, L,
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for((int64_t)L * (L / 4), 256)), dim3(256), 0, st, lat, s, L,
                        stride);
     return hipGetLastError();
 }

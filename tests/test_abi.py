@@ -61,15 +61,16 @@ def test_device_bytes(pgg):
                                 dict(kernel="strip", tile=101),
                                 dict(kernel="rowband", tile=26),
                                 dict(L=60, kernel="segment"), dict(kernel="segment", tile=48),
-                                dict(kernel="segment", tile=96), dict(layout="int8", kernel="segment"),
+                                dict(kernel="segment", tile=96), dict(layout="int8", L=60, kernel="segment"),
                                 dict(kernel="segment", group=3), dict(kernel="segment", group=16),
-                                dict(kernel="rowband", group=4), dict(layout="int8", group=4),
+                                dict(kernel="rowband", group=4), dict(layout="int8", L=60, group=4),
                                 dict(L=32768, kernel="segment", tile=32736),
                                 dict(L=100, kernel="segment", tile=100),
                                 dict(L=480, kernel="segment_pair"), dict(L=516, kernel="segment_pair"),
                                 dict(L=512, kernel="segment_pair", tile=480),
                                 dict(L=512, kernel="segment_pair", group=4),
-                                dict(layout="int8", L=512, kernel="segment_pair"),
+                                dict(layout="int8", L=480, kernel="segment_pair"),
+                                dict(layout="int8", kernel="colour", group=2),
                                 dict(L=16384, kernel="segment", tile=8192, group=8)])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")
@@ -79,6 +80,16 @@ def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
         pgg.pgg_init(p)
     assert e.value.status == pgg.PGG_E_INVAL
     assert "invalid parameters" in pgg.load().pgg_last_error().decode()
+
+
+@pytest.mark.parametrize("layout", ["int8", "bits"])
+def test_init_rejects_a_misaligned_caller_buffer_before_touching_the_device(pgg, layout):
+    p = pgg.make_params(100, 3.8, layout=layout)
+    h = pgg.ctypes.c_void_p()
+    lib = pgg.load()
+    st = lib.pgg_init(pgg.ctypes.byref(p), pgg.ctypes.c_void_p(0x10002), 1 << 20, None, pgg.ctypes.byref(h))
+    assert st == pgg.PGG_E_INVAL and not h.value
+    assert "aligned" in lib.pgg_last_error().decode()
 
 
 def test_null_handle_is_rejected(pgg):

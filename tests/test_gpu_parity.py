@@ -13,9 +13,9 @@ from paper_1704_08098_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [("int8", "colour"), ("bits", "rowband"), ("bits", "rowband_compact"),
-            ("bits", "rowband_staged"), ("bits", "strip"), ("bits", "segment")]
+            ("bits", "rowband_staged"), ("bits", "strip"), ("bits", "segment"), ("int8", "segment")]
 # kernels for lattices of L >= 512, a multiple of 32, beside all the others
-LARGE_VARIANTS = VARIANTS + [("bits", "segment_pair")]
+LARGE_VARIANTS = VARIANTS + [("bits", "segment_pair"), ("int8", "segment_pair")]
 
 
 def say(*a):
@@ -203,6 +203,32 @@ def test_caller_buffer_and_stream(pgg, oracle_lib):
     host = buf.cpu().numpy().reshape(L, 16)
     bits = np.unpackbits(host, axis=1, bitorder="little")[:, :L]
     assert np.array_equal(bits, ref)
+
+
+@pytest.mark.parametrize("kernel,L", [("auto", 100), ("segment", 260), ("segment_pair", 512)])
+def test_int8_caller_buffer_on_segment_kernels(pgg, oracle_lib, kernel, L):
+    """int8 layout on the segment kernels (a bit-packed working copy inside the
+    library): the caller's byte buffer holds the oracle's lattice after every
+    call, calls of several lengths in a row, and a lattice written between
+    calls is the one the next call starts from."""
+    import torch
+    r, seed = 3.85, 500 + L
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, 21)
+    params = pgg.make_params(L, r, 0.5, 0.5, seed, "int8", kernel)
+    buf = torch.full((pgg.pgg_device_bytes(params),), 7, dtype=torch.uint8, device="cuda")
+    say("int8 caller buffer", kernel, L)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "int8", kernel, dev_buf=buf) as sim:
+        got = np.concatenate([sim.sweep(1), sim.sweep(13), sim.sweep(7)])
+        assert np.array_equal(got, counts)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy().reshape(L, L), ref)
+        lat = wl.random_lattice(L, 0.3, 8)
+        ref2, counts2 = oracle_lib.sweep(lat, r, 0.5, seed, 40, 9)
+        sim.write_lattice(lat, 40)
+        assert np.array_equal(sim.sweep(9), counts2)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy().reshape(L, L), ref2)
+        assert np.array_equal(sim.read_lattice(), ref2)
 
 
 @pytest.mark.parametrize("layout,kernel", LARGE_VARIANTS)
