@@ -51,7 +51,7 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigne
     const int rep_id = __builtin_amdgcn_readfirstlane(replica_of_wave(reps, n_reps, first_wave));
     const EnsRep rp = reps[rep_id];
     uint32_t* sT = smem;
-    uint32_t* win = smem + 160 + wid * rep_wave_words(rp);
+    uint32_t* win = smem + kSegTableWords + wid * rep_wave_words(rp);
     const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica
     // sweep q of the chunk reads the state after sweep q - 1: lat for even q,
     // lat2 for odd q, and writes the other buffer.
@@ -59,7 +59,7 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigne
     uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
     const uint32_t t = rp.t0 + (uint32_t)q;
     int my_delta = 0, my_drawn = 0;
-    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    seg_load_table(sT, rp.T);
     if (rp.rpw > 0) {
         // whole rows: wave lw owns rows a + 4 (lw R + r), r < nrows
         const int R = rp.rpw, rows = rp.L >> 2;
@@ -74,7 +74,9 @@ k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigne
         const SegPos g = seg_pos(rp.L, a, rp.segw, active ? lw / rp.nseg : 0, active ? lw % rp.nseg : 0);
         if (active) segment_fill(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, g, win);
         __syncthreads();
-        if (active) segment_run(next, rp.L, rp.stride, a, rp.segw, g, t, rp.k0, rp.k1, sT, win, my_delta, my_drawn);
+        if (active)
+            segment_run(next, rp.L, rp.stride, a, rp.segw, g, t, rp.k0, rp.k1, sT, win, rp.drawn != nullptr, my_delta,
+                        my_drawn);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -131,13 +133,13 @@ k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __
     const int R0 = band * B, R1 = min(R0 + B, L);
     const int s = sg * segw, e = min(L, s + segw), c0 = s - 64;
     uint32_t* sT = smem;
-    uint32_t* wwin = smem + 160;            // (B + 12) rows x WB
+    uint32_t* wwin = smem + kSegTableWords;  // (B + 12) rows x WB
     uint32_t* lists = wwin + (B + 12) * WB;  // NW x cap
     const bool on = q < rp.n_active;
     const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
     uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
     const uint32_t t = rp.t0 + (uint32_t)q;
-    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    seg_load_table(sT, rp.T);
     if (on) {
         const int w0 = c0 >> 5;  // segments start on word boundaries (L % 32 == 0)
         for (int k = threadIdx.x; k < (B + 12) * WB; k += blockDim.x) {
@@ -161,7 +163,7 @@ k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __
             const int gi = i < 0 ? i + L : (i >= L ? i - L : i);
             const SegPos g = {gi, s, e, c0};
             segment_run_row(next, L, stride, a, segw, g, t, rp.k0, rp.k1, sT, wwin + (i - (R0 - 6)) * WB,
-                            lists + wid * cap, 12, i >= R0 && i < R1, my_delta, my_drawn);
+                            lists + wid * cap, 12, i >= R0 && i < R1, rp.drawn != nullptr, my_delta, my_drawn);
         }
     }
     __syncthreads();
@@ -171,7 +173,7 @@ k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __
         if (on && i < R1) {
             const SegPos g = {i, s, e, c0};
             segment_run_row(next, L, stride, a + 1, segw, g, t, rp.k0, rp.k1, sT, wwin + (i - (R0 - 6)) * WB,
-                            lists + wid * cap, 0, true, my_delta, my_drawn);
+                            lists + wid * cap, 0, true, rp.drawn != nullptr, my_delta, my_drawn);
         }
     }
 #pragma unroll
@@ -344,7 +346,7 @@ int ens_waves(const EnsRep& rp, int wpg) {
 int ens_wave_words(const EnsRep& rp) { return rep_wave_words(rp); }
 
 size_t ens_lds_bytes(int max_wave_words, int wpg) {
-    return (160 + (size_t)wpg * max_wave_words) * sizeof(uint32_t);
+    return (kSegTableWords + (size_t)wpg * max_wave_words) * sizeof(uint32_t);
 }
 
 bool ens_wpg_valid(int wpg) { return wpg == 2 || wpg == 4 || wpg == 8; }
@@ -394,7 +396,7 @@ hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, 
 }
 
 size_t pair_lds_bytes(int segw) {
-    return (160 + (size_t)(kPairBand + 12) * seg_window_words(segw) +
+    return (kSegTableWords + (size_t)(kPairBand + 12) * seg_window_words(segw) +
             (size_t)(kPairBand / 4 + 1) * seg_list_cap(segw)) * sizeof(uint32_t);
 }
 

@@ -83,6 +83,18 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 
 }  // namespace seg
 
+// The threshold table in LDS, laid out for an index without a multiply:
+// T[dSigma][ds] at word (ds + 1) * 64 + dSigma + 25 (three rows of 64 words,
+// 51 used each).
+constexpr int kSegTableWords = 192;
+
+__device__ __forceinline__ void seg_load_table(uint32_t* __restrict__ sT, const uint32_t* __restrict__ T) {
+    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) {
+        const int dsig = k / 3, ds = k - 3 * dsig;  // T[(dSigma + 25) * 3 + ds + 1]
+        sT[ds * 64 + dsig] = T[k];
+    }
+}
+
 // Window words per row and list capacity per class for a segment width.
 __host__ __device__ constexpr int seg_window_words(int segw) { return segw / 32 + 4; }
 // (class-b sites of a segment plus margins of up to 21 columns each side)
@@ -123,7 +135,7 @@ __device__ __forceinline__ int site_step(const uint32_t* __restrict__ rp, int ld
     // Sigma = rest + 5 s, so Sigma_x - Sigma_y = rest_x - rest_y + 5 ds; the
     // index stays inside the table for ds = 0 too (rest lies in [0, 20])
     const int dsig = seg::sigma_rest16(xm2, xm1, x0, xp1, xp2) - seg::sigma_rest16(ym2, ym1, y0, yp1, yp2) + 5 * ds;
-    const uint32_t thr = sT[__mul24(dsig, 3) + 76 + ds];  // T[(dsig + 25) * 3 + ds + 1]
+    const uint32_t thr = sT[((ds + 1) << 6) + dsig + 25];  // T[(dsig + 25) * 3 + ds + 1], seg_load_table's layout
     const bool flip = (ds != 0) & (rnd.y < thr);
     return flip ? (sy ? 1 : -1) : 0;
 }
@@ -200,12 +212,13 @@ __device__ __forceinline__ void segment_fill(const uint32_t* __restrict__ cur, c
 // class's margin (a launch that runs a second residue after this one needs
 // this row exact on 3 x 4 more columns each side).  A row that is not owned
 // (a halo row another workgroup owns) is updated in LDS only: no counts, no
-// write-back.
+// write-back.  Draws are counted only when count_drawn is set (wave-uniform;
+// the count is a diagnostic).
 __device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int L, int stride, int a, int segw,
                                                 const SegPos& g, uint32_t t, uint32_t k0, uint32_t k1,
                                                 const uint32_t* __restrict__ sT, uint32_t* __restrict__ r0,
                                                 uint32_t* __restrict__ list, int extra, bool owned_row,
-                                                int& my_delta, int& my_drawn) {
+                                                bool count_drawn, int& my_delta, int& my_drawn) {
     using namespace seg;
     const int lane = threadIdx.x & 63;
     const int WB = seg_window_words(segw);
@@ -237,8 +250,10 @@ __device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int
                 if (w == wlo) act &= m_first;
                 if (w == whi - 1) act &= m_last;
                 // draws of owned sites (margin sites are recomputed copies)
-                const int own_lo = max(64 - 32 * w, 0), own_hi = min(64 + (e - s) - 32 * w, 32);
-                if (owned_row && own_hi > own_lo) my_drawn += __popc(act & bit_range(own_lo, own_hi));
+                if (count_drawn && owned_row) {
+                    const int own_lo = max(64 - 32 * w, 0), own_hi = min(64 + (e - s) - 32 * w, 32);
+                    if (own_hi > own_lo) my_drawn += __popc(act & bit_range(own_lo, own_hi));
+                }
             }
             const int cnt = __popc(act);
             int pos = total;
@@ -304,10 +319,10 @@ __device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int
 __device__ __forceinline__ void segment_run(uint32_t* __restrict__ next, int L, int stride, int a, int segw,
                                             const SegPos& g, uint32_t t, uint32_t k0, uint32_t k1,
                                             const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
-                                            int& my_delta, int& my_drawn) {
+                                            bool count_drawn, int& my_delta, int& my_drawn) {
     const int WB = seg_window_words(segw);
-    segment_run_row(next, L, stride, a, segw, g, t, k0, k1, sT, win + 3 * WB, win + 7 * WB, 0, true, my_delta,
-                    my_drawn);
+    segment_run_row(next, L, stride, a, segw, g, t, k0, k1, sT, win + 3 * WB, win + 7 * WB, 0, true, count_drawn,
+                    my_delta, my_drawn);
 }
 
 }  // namespace pgg
