@@ -235,6 +235,23 @@ def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64):
     return rep
 
 
+def scan_pass(pgg, torch, sweeps, stream):
+    """The r scan near the transition (21 values of r in [3.70, 3.80], L =
+    1024, one seed each) as one ensemble: the stationary cooperator density
+    per r (mean over the last half of the sweeps, Eq. (4)) and the rate."""
+    from paper_1704_08098_amd import observables as ob
+    cfg = dict(wl.SCAN, sweeps=sweeps, average_last=max(1, min(wl.SCAN["average_last"], sweeps // 2)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, rho, _ = ob.r_scan(pgg, cfg, stream=stream)
+    dt = time.perf_counter() - t0
+    n_rep = len(cfg["r_values"])
+    return {"L": cfg["L"], "sweeps": sweeps, "average_last": cfg["average_last"], "r": [float(v) for v in r],
+            "stationary_density": [float(v) for v in rho], "seconds": dt,
+            "replica_site_updates_per_s": n_rep * float(cfg["L"]) ** 2 * sweeps / dt,
+            "note": "one batched ensemble; wall time includes the per-block count copies"}
+
+
 def cpu_baseline(L, r, seed, n_sweeps):
     import oracle
     oracle.build(force=False)
@@ -271,6 +288,8 @@ def main():
     ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
+    ap.add_argument("--scan-sweeps", type=int, default=10_000,
+                    help="sweeps of the L = 1024 r scan run as one ensemble (0 skips it)")
     ap.add_argument("--no-autotune", action="store_true", help="ensemble pass with automatic widths and "
                     "--ensemble-chunk instead of pgg_ensemble_autotune")
     ap.add_argument("--source-hash", action="store_true", help="print the segment kernel's source hash and exit")
@@ -375,6 +394,11 @@ def main():
         log("serving pass: capacity batch, then %d jobs" % args.serve_jobs)
         serving = serving_pass(pgg, args.serve_jobs, stream)
 
+    scan = None
+    if args.scan_sweeps > 0:
+        log("r scan: 21 replicas of L=%d, %d sweeps" % (wl.SCAN["L"], args.scan_sweeps))
+        scan = scan_pass(pgg, torch, args.scan_sweeps, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, %d sweep(s) at L=%d" % (args.cpu_sweeps, L))
@@ -391,6 +415,7 @@ def main():
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
         "roofline": roofline, "hbm": hbm, "dense": dense, "late": late, "batched": batched, "serving": serving,
+        "scan": scan,
         "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }
