@@ -160,3 +160,55 @@ def test_r_scan_as_one_ensemble_against_oracle(pgg, oracle_lib):
         for k, (lat, counts) in enumerate(refs):
             assert np.array_equal(c[k], counts), k
             assert np.array_equal(ens.read_lattice(k), lat), k
+
+
+def test_r_scan_ensemble_against_stored_oracle_runs(pgg):
+    """The L = 1024 r scan (21 replicas) as one ensemble through 1000 sweeps,
+    with the tuning the benchmark's ensemble pass uses by default (automatic
+    widths, chunks of 50): every replica's counts after each sweep and its
+    final lattice equal the oracle's (stored digests,
+    tests/golden/make_trajectories.py)."""
+    import hashlib
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "rscan_L1024_1000.txt")
+    rows, n = [], None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "L":
+                assert int(parts[1]) == wl.SCAN["L"]
+            elif parts[0] == "sweeps":
+                n = int(parts[1])
+            else:
+                rows.append((float(parts[0]), int(parts[1]), int(parts[2]), parts[3], parts[4]))
+    cfg = wl.SCAN
+    assert [(r, s) for r, s, *_ in rows] == list(zip(cfg["r_values"], cfg["seeds"]))
+    reps = [dict(L=cfg["L"], r=r, K=cfg["K"], p0=cfg["p0"], seed=s) for r, s, *_ in rows]
+    say("r-scan ensemble vs stored oracle runs,", len(reps), "replicas,", n, "sweeps")
+    with pgg.Ensemble(reps, chunk=50) as ens:
+        c = np.concatenate([ens.sweep(1), ens.sweep(n - 1)], axis=1)
+        for k, (r, seed, final, counts_sha, lat_sha) in enumerate(rows):
+            assert int(c[k, -1]) == final, (k, r)
+            assert hashlib.sha256(np.ascontiguousarray(c[k], dtype="<u8").tobytes()).hexdigest() == counts_sha, (k, r)
+            assert hashlib.sha256(ens.read_lattice(k).tobytes()).hexdigest() == lat_sha, (k, r)
+
+
+
+def test_r_scan_driver_matches_oracle_stationary_densities(pgg, oracle_lib):
+    """observables.r_scan (the r scan as one ensemble, counts fetched in
+    blocks) on a reduced scan -- L = 128, the 21 values of r, 300 sweeps,
+    mean over the last 150 -- gives the oracle's counts and hence exactly the
+    oracle's stationary densities."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1704_08098_amd import observables as ob
+    cfg = dict(wl.SCAN, L=128, sweeps=300, average_last=150)
+    args = [(cfg["L"], r, cfg["K"], cfg["p0"], s, cfg["sweeps"]) for r, s in zip(cfg["r_values"], cfg["seeds"])]
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(_oracle_run, args))
+    say("r_scan driver, L", cfg["L"])
+    r, rho, counts = ob.r_scan(pgg, cfg, block=128)
+    for k, (lat, ref_counts) in enumerate(refs):
+        assert np.array_equal(counts[k], ref_counts), k
+        assert rho[k] == ob.stationary_density(ref_counts, cfg["L"], cfg["average_last"]), k
