@@ -461,3 +461,14 @@ def test_long_trajectory_whole_rows(pgg, oracle_lib):
         got = np.concatenate([sim.sweep(1000), sim.sweep(1), sim.sweep(1999)])
         assert np.array_equal(got, counts)
         assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_decay_driver_matches_oracle(pgg, oracle_lib):
+    """observables.decay (one lattice, counts fetched in blocks, rho_C on the
+    log grid) equals the same grid read off the oracle's counts."""
+    from paper_1704_08098_amd import observables as ob
+    L, r, seed, n = 256, wl.R_CRITICAL, 3, 500
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say("decay driver, L", L, "t_max", n)
+    grid, rho = ob.decay(pgg, L, r, seed, n, block=128)
+    assert np.array_equal(rho, ob.sample_on_grid(counts, L, grid, nc0))
