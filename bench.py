@@ -198,9 +198,37 @@ def late_window(pgg, torch, L, r, seed, kernel, layout, t_start, steps, stream, 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rho = sim.density()
+    # then 100 sweeps in timing mode: the fraction of updates that draw, and launch spans
+    n_diag = 100
+    sim.set_kernel_timing(True)
+    sim.sweep(n_diag, want_counts=False)
+    launches, _, drawn = sim.kernel_timing()
+    span_n, span_us = sim.kernel_span()
     sim.close()
     return {"t_start": t_start, "steps": steps, "value": float(L) * L * steps / dt, "unit": "site updates/s",
-            "ms_per_step": 1e3 * dt / steps, "density_at_end": rho}
+            "ms_per_step": 1e3 * dt / steps, "density_at_end": rho,
+            "drawn_fraction_next_100": drawn / (float(L) * L * n_diag),
+            "kernel_span_us_next_100": span_us / span_n if span_n else None}
+
+
+def decay_batch_pass(pgg, torch, warmup, steps, stream):
+    """The decay runs (L = 4096, r_c and r_c +- 0.005, three seeds each) as
+    one ensemble: sweeps warmup .. warmup + steps - 1 of all nine lattices,
+    timed like the single-lattice pass."""
+    cfg = wl.DECAY
+    reps = [dict(L=cfg["L"], r=r, K=cfg["K"], p0=cfg["p0"], seed=s) for r in cfg["r_values"] for s in cfg["seeds"]]
+    ens = pgg.Ensemble(reps, chunk=64, stream=stream)
+    ens.sweep(warmup, want_counts=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.sweep(steps, want_counts=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ens.close()
+    total = len(reps) * float(cfg["L"]) ** 2 * steps
+    return {"replicas": len(reps), "L": cfg["L"], "r_values": list(cfg["r_values"]), "seeds": list(cfg["seeds"]),
+            "sweeps_timed": "%d..%d" % (warmup, warmup + steps - 1), "value": total / dt,
+            "unit": "replica-site updates/s", "ms_per_sweep_of_all": 1e3 * dt / steps}
 
 
 def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64):
@@ -288,6 +316,8 @@ def main():
     ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
+    ap.add_argument("--no-decay-batch", dest="decay_batch", action="store_false",
+                    help="skip the nine L = 4096 decay lattices run as one ensemble")
     ap.add_argument("--scan-sweeps", type=int, default=10_000,
                     help="sweeps of the L = 1024 r scan run as one ensemble (0 skips it)")
     ap.add_argument("--no-autotune", action="store_true", help="ensemble pass with automatic widths and "
@@ -383,6 +413,11 @@ def main():
         batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream,
                                 not args.no_autotune)
 
+    decay_batch = None
+    if args.decay_batch:
+        log("decay batch: 9 lattices of L=%d as one ensemble" % wl.DECAY["L"])
+        decay_batch = decay_batch_pass(pgg, torch, args.warmup, args.steps, stream)
+
     late = None
     if args.late_start > 0:
         log("late window: sweeps %d..%d" % (args.late_start, args.late_start + args.steps - 1))
@@ -415,7 +450,7 @@ def main():
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
         "roofline": roofline, "hbm": hbm, "dense": dense, "late": late, "batched": batched, "serving": serving,
-        "scan": scan,
+        "scan": scan, "decay_batch": decay_batch,
         "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }
