@@ -1,0 +1,129 @@
+"""Critical point of the C+D -> D transition from an r scan (Sec. V).
+
+Near the absorbing-phase transition the stationary cooperator density
+follows a power law in the distance to the critical multiplication factor,
+rho_C ~ (r - r_c)^beta (Sec. V; beta = 0.584 for directed percolation in
+2 + 1 dimensions, 0.56(2) fitted in the paper at r_c = 3.7443(4) for random
+sequential updating).  This module fits r_c and beta to stationary densities
+and, as a command, measures them for the 16-colour dynamics: a finer r scan
+around the transition, run as one batched ensemble on the GPU.
+
+    python -m paper_1704_08098_amd.critical --L 2048 --sweeps 100000
+
+The fit: for a trial r_c, a least-squares line through (log(r - r_c),
+log rho) over the points with r - r_c in (0, window] and rho > 0; r_c is the
+trial value whose line leaves the smallest mean squared residual (the point
+where the data are most nearly a power law), and beta is that line's slope.
+Only points that have reached their stationary state enter: rho > 0 and the
+means over the two halves of the averaging window agree within a tolerance
+(close to r_c the relaxation outlasts any fixed run, and a point still
+decaying would bend the fit).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import workloads as wl
+
+
+def fit_power_law(r, rho, r_c: float, window: float = 0.1):
+    """Slope, intercept and mean squared residual of log rho against
+    log(r - r_c) over the points with 0 < r - r_c <= window and rho > 0.
+    None when fewer than three points qualify."""
+    r = np.asarray(r, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    sel = (r - r_c > 0) & (r - r_c <= window) & (rho > 0)
+    if np.count_nonzero(sel) < 3:
+        return None
+    x = np.log(r[sel] - r_c)
+    y = np.log(rho[sel])
+    A = np.stack([x, np.ones_like(x)], axis=1)
+    coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+    resid = y - A @ coef
+    return float(coef[0]), float(coef[1]), float(np.mean(resid ** 2)), int(np.count_nonzero(sel))
+
+
+def fit_critical_point(r, rho, rc_grid, window: float = 0.1):
+    """(r_c, beta, mean squared residual, points used) for the trial r_c of
+    rc_grid whose power-law fit is best; trial values must lie below every
+    point used, so the grid should end below the smallest r with rho > 0."""
+    best = None
+    for rc in np.asarray(rc_grid, dtype=np.float64):
+        f = fit_power_law(r, rho, float(rc), window)
+        if f is None:
+            continue
+        if best is None or f[2] < best[2]:
+            best = (float(rc), f[0], f[2], f[3])
+    if best is None:
+        raise ValueError("no trial r_c leaves three points for the fit")
+    return best
+
+
+def stationary_points(counts, L: int, average_last: int, tol: float = 0.05):
+    """Per replica: the mean density over the averaging window, and whether
+    it is stationary (positive, and the means over the window's two halves
+    differ by at most tol times the later one)."""
+    c = np.asarray(counts, dtype=np.float64) / float(L * L)
+    half = average_last // 2
+    early = c[:, c.shape[1] - average_last:c.shape[1] - half].mean(axis=1)
+    late = c[:, c.shape[1] - half:].mean(axis=1)
+    rho = c[:, c.shape[1] - average_last:].mean(axis=1)
+    ok = (late > 0) & (np.abs(early - late) <= tol * late)
+    return rho, ok
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--L", type=int, default=2048)
+    ap.add_argument("--r-min", type=float, default=3.715)
+    ap.add_argument("--r-max", type=float, default=3.80)
+    ap.add_argument("--r-step", type=float, default=0.0025)
+    ap.add_argument("--sweeps", type=int, default=100_000)
+    ap.add_argument("--average-last", type=int, default=0, help="0: the last half of the sweeps")
+    ap.add_argument("--seed", type=int, default=500, help="replica k gets seed + k")
+    ap.add_argument("--window", type=float, default=0.05, help="largest r - r_c in the fit")
+    ap.add_argument("--tol", type=float, default=0.05, help="stationarity tolerance (relative)")
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import observables as ob
+    from . import pgg
+    if not torch.cuda.is_available():
+        raise SystemExit("the scan needs a GPU")
+    torch.cuda.set_device(0)
+    pgg.load()
+    n_r = int(round((args.r_max - args.r_min) / args.r_step)) + 1
+    r_values = tuple(float("%.6f" % (args.r_min + args.r_step * k)) for k in range(n_r))
+    last = args.average_last or args.sweeps // 2
+    cfg = dict(L=args.L, K=wl.K_PAPER, p0=0.5, sweeps=args.sweeps, average_last=last, r_values=r_values,
+               seeds=tuple(args.seed + k for k in range(n_r)))
+    print("scan: %d values of r in [%g, %g], L = %d, %d sweeps, mean over the last %d"
+          % (n_r, args.r_min, args.r_max, args.L, args.sweeps, last), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    r, rho, counts = ob.r_scan(pgg, cfg, block=10_000)
+    dt = time.perf_counter() - t0
+    _, ok = stationary_points(counts, args.L, last, args.tol)
+    fits = {}
+    if np.count_nonzero(ok) >= 3:
+        rc_hi = float(r[ok].min())
+        rc_grid = np.arange(rc_hi - 0.03, rc_hi, 0.0001)
+        for win in sorted({args.window, 0.02, 0.05, 0.1}):
+            try:
+                rc, beta, msr, npts = fit_critical_point(r[ok], rho[ok], rc_grid, win)
+                fits["%g" % win] = {"r_c": rc, "beta": beta, "mean_sq_residual": msr, "points": npts}
+            except ValueError:
+                pass
+    out = {"L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
+           "stationary_density": [float(v) for v in rho], "stationary": [bool(v) for v in ok],
+           "seconds": dt, "replica_site_updates_per_s": n_r * float(args.L) ** 2 * args.sweeps / dt,
+           "fit_by_window": fits, "tol": args.tol}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
