@@ -15,6 +15,8 @@ What each function follows in the paper (M. Perc, 2017):
 * ``sweep``    -- Sec. III elementary step, swept with the 16-colour schedule
                   (oracle A, the bit-exact contract).
 * ``rs_run``   -- Sec. III random-sequential Monte Carlo (oracle B).
+* ``sweep_tiled`` -- Sec. IV double tiling: 4 x 4 domains of four types,
+                  random sequential steps inside each domain (oracle C).
 * ``count``    -- Eq. (4): the cooperator count whose mean over L^2 is rho_C.
 
 Pins (tests/test_oracle_*.py) tie every function to something other than
@@ -77,6 +79,8 @@ def _load():
                                   ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, u64p,
                                   ctypes.c_int, ctypes.c_uint64]
     lib.pgg_ref_sweep.restype = ctypes.c_int
+    lib.pgg_ref_sweep_tiled.argtypes = lib.pgg_ref_sweep.argtypes
+    lib.pgg_ref_sweep_tiled.restype = ctypes.c_int
     lib.pgg_ref_rs_run.argtypes = [u8p, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_uint64, ctypes.c_uint32, u64p]
     lib.pgg_ref_rs_run.restype = ctypes.c_int
@@ -167,6 +171,28 @@ def sweep(s: np.ndarray, r: float, K: float, seed: int, t0: int, n: int,
                                  _p(counts, ctypes.c_uint64), int(order),
                                  int(order_seed) & (2**64 - 1)), "sweep")
     return s, counts[:n]
+
+
+def sweep_tiled(s: np.ndarray, r: float, K: float, seed: int, t0: int, n: int,
+                order: int = 0, order_seed: int = 0):
+    """Oracle C: n Monte Carlo steps of the double tiling (Sec. IV) from
+    absolute sweep index t0; L a multiple of 8.  Returns (new lattice, counts
+    after each step).  ``order`` permutes the domains inside each part (0
+    raster, 1 reversed, 2 random), which must not change the result."""
+    s = _lattice(s).copy()
+    counts = np.zeros(max(int(n), 1), dtype=np.uint64)
+    _check(_load().pgg_ref_sweep_tiled(_p(s, ctypes.c_uint8), s.shape[0], float(r), float(K),
+                                       int(seed) & (2**64 - 1), int(t0), int(n),
+                                       _p(counts, ctypes.c_uint64), int(order),
+                                       int(order_seed) & (2**64 - 1)), "sweep_tiled")
+    return s, counts[:n]
+
+
+def run_tiled(L: int, r: float, K: float, p0: float, seed: int, n: int):
+    """Init + n tiled steps (oracle C): (lattice, N_C(0), counts)."""
+    s, nc0 = init(L, p0, seed)
+    s, counts = sweep_tiled(s, r, K, seed, 0, n)
+    return s, nc0, counts
 
 
 def rs_run(s: np.ndarray, r: float, K: float, seed: int, n_mcs: int):

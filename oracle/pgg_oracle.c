@@ -15,13 +15,18 @@
  * a player is summed over the five groups it belongs to; the player imitates a
  * random nearest neighbour with the Fermi probability of Eq. (3).
  *
- * Two oracles:
+ * Three oracles:
  *   A  pgg_ref_sweep   the deterministic 16-colour sublattice sweep with a
  *                      Philox4x32-10 counter RNG and an integer acceptance
  *                      table.  This is the bit-exact contract.
  *   B  pgg_ref_rs_run  the textbook random-sequential Monte Carlo step of
  *                      Sec. III, payoffs from Eq. (1)-(2) group by group in
  *                      binary64, Eq. (3) in binary64.  Statistical check only.
+ *   C  pgg_ref_sweep_tiled  the paper's own parallel dynamics, the double
+ *                      tiling of Sec. IV (4 x 4 domains of four types, random
+ *                      sequential steps inside each domain), with the same
+ *                      counter RNG and table as A.  The bit-exact contract of
+ *                      the tiled schedule.
  *
  * Conventions the paper leaves open (our reading, fixed here):
  *   - lattice index x = i*L + j, i = row, j = column, both periodic mod L;
@@ -209,14 +214,11 @@ uint64_t pgg_ref_count(const uint8_t* s, uint32_t L)
 static const int DIR_DI[4] = {0, 0, 1, -1}; /* d = 0: E, 1: W, 2: S, 3: N */
 static const int DIR_DJ[4] = {1, -1, 0, 0};
 
-/* Returns +1 if x turned C, -1 if it turned D, 0 if unchanged. */
-static int elementary_step(uint8_t* s, int L, const uint32_t* T, uint64_t seed,
-                           uint32_t t, int k, int i, int j)
+/* The imitation of Sec. III for player x = (i, j), its neighbour in
+ * direction d and the uniform 32-bit word u.  Returns +1 if x turned C, -1 if
+ * it turned D, 0 if unchanged. */
+static int imitate(uint8_t* s, int L, const uint32_t* T, int i, int j, int d, uint32_t u)
 {
-    uint32_t w[4];
-    philox_site(seed, (uint32_t)(i * L + j), t, (uint32_t)k, 0u, w);
-    const int d = (int)(w[0] >> 30);
-    const uint32_t u = w[1];
     const int yi = wrap((int64_t)i + DIR_DI[d], L), yj = wrap((int64_t)j + DIR_DJ[d], L);
     /* x plays in its five groups and earns Pi_x; y likewise (Eq. (1)-(2)). */
     const int sig_x = pgg_ref_sigma(s, L, i, j);
@@ -230,6 +232,15 @@ static int elementary_step(uint8_t* s, int L, const uint32_t* T, uint64_t seed,
         return sy ? +1 : -1;
     }
     return 0;
+}
+
+/* The elementary step of oracle A at site (i, j) of colour k in sweep t. */
+static int elementary_step(uint8_t* s, int L, const uint32_t* T, uint64_t seed,
+                           uint32_t t, int k, int i, int j)
+{
+    uint32_t w[4];
+    philox_site(seed, (uint32_t)(i * L + j), t, (uint32_t)k, 0u, w);
+    return imitate(s, L, T, i, j, (int)(w[0] >> 30), w[1]);
 }
 
 /* xorshift64* for the test hook that permutes the in-colour visiting order
@@ -279,6 +290,80 @@ int pgg_ref_sweep(uint8_t* s, uint32_t L, double r, double K, uint64_t seed,
                 int i = a + 4 * (int)(idx / (L / 4));
                 int j = b + 4 * (int)(idx % (L / 4));
                 elementary_step(s, (int)L, T, seed, t, k, i, j);
+            }
+        }
+        if (counts) counts[q] = pgg_ref_count(s, L);
+    }
+    free(perm);
+    return PGG_REF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Oracle C: the double tiling decomposition of Sec. IV (Fig. 2).  The       */
+/* lattice is cut into 4 x 4 domains (I, J) = rows 4I..4I+3, columns         */
+/* 4J..4J+3; rows of domains alternate the type sequences 1,2,1,2,... (I     */
+/* even) and 3,4,3,4,... (I odd), so domain (I, J) has type                 */
+/* 1 + 2 (I mod 2) + (J mod 2).  A full Monte Carlo step runs four parts,    */
+/* types 1, 2, 3, 4 in turn; in a part every domain of that type performs    */
+/* 16 elementary steps of Sec. III in random sequential order -- x uniform   */
+/* among the domain's 16 players, y uniform among x's four neighbours (which */
+/* may lie outside the domain) -- so each player gets one chance per MCS on  */
+/* average.  Domains of one type neither share a player nor read each       */
+/* other's players (they are 4 sites apart and a step reads at most 3 sites  */
+/* beyond x), so a part's domains are independent.  L must be a multiple of  */
+/* 8 (Sec. IV).                                                             */
+/* Random numbers (our reading; the paper names no generator): step m of    */
+/* part p in sweep t of domain (I, J) takes the Philox block of counter      */
+/* (I * L/4 + J, t, 16 p + m, 2): x is player w0 >> 28 of the domain         */
+/* (row-major, (w0 >> 28) / 4 rows down, (w0 >> 28) mod 4 columns right),    */
+/* d = (w0 >> 26) mod 4 picks y as in oracle A, u = w1.                       */
+/* ------------------------------------------------------------------------ */
+static int tiled_step(uint8_t* s, int L, const uint32_t* T, uint64_t seed, uint32_t t,
+                      int part, int m, int I, int J)
+{
+    uint32_t w[4];
+    philox_site(seed, (uint32_t)(I * (L / 4) + J), t, (uint32_t)(16 * part + m), 2u, w);
+    const int idx = (int)(w[0] >> 28);
+    return imitate(s, L, T, 4 * I + idx / 4, 4 * J + idx % 4, (int)((w[0] >> 26) & 3u), w[1]);
+}
+
+/* n tiled Monte Carlo steps from absolute sweep index t0 (in place);
+ * counts[q] = N_C after sweep t0 + q.  order: 0 raster, 1 reversed raster,
+ * 2 random permutation (order_seed) of the domains inside each part; the
+ * result must not depend on it. */
+int pgg_ref_sweep_tiled(uint8_t* s, uint32_t L, double r, double K, uint64_t seed,
+                        uint64_t t0, uint32_t n, uint64_t* counts, int order,
+                        uint64_t order_seed)
+{
+    if (!valid_L(L) || (L % 8) != 0 || t0 + (uint64_t)n > 4294967296ull || order < 0 || order > 2)
+        return PGG_REF_EINVAL;
+    uint32_t T[153];
+    int rc = pgg_ref_table(r, K, T);
+    if (rc) return rc;
+    const uint32_t half = L / 8;            /* domains of one type per row of domains */
+    const uint32_t per = half * half;       /* domains of one type */
+    uint32_t* perm = NULL;
+    if (order == 2) {
+        perm = (uint32_t*)malloc(sizeof(uint32_t) * per);
+        if (!perm) return PGG_REF_ENOMEM;
+    }
+    uint64_t ost = order_seed | 1ull;
+    for (uint32_t q = 0; q < n; ++q) {
+        const uint32_t t = (uint32_t)(t0 + q);
+        for (int part = 0; part < 4; ++part) {
+            const int pi = part / 2, pj = part % 2;  /* type 1 + part: (I mod 2, J mod 2) */
+            if (order == 2) {
+                for (uint32_t m = 0; m < per; ++m) perm[m] = m;
+                for (uint32_t m = per - 1; m > 0; --m) {
+                    uint32_t z = (uint32_t)(xs64(&ost) % (uint64_t)(m + 1));
+                    uint32_t tmp = perm[m]; perm[m] = perm[z]; perm[z] = tmp;
+                }
+            }
+            for (uint32_t e = 0; e < per; ++e) {
+                uint32_t idx = order == 0 ? e : order == 1 ? per - 1 - e : perm[e];
+                int I = pi + 2 * (int)(idx / half);
+                int J = pj + 2 * (int)(idx % half);
+                for (int m = 0; m < 16; ++m) tiled_step(s, (int)L, T, seed, t, part, m, I, J);
             }
         }
         if (counts) counts[q] = pgg_ref_count(s, L);

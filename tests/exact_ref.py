@@ -67,3 +67,45 @@ def sweep(s, L, r, K, words, t=None):
                 if u < threshold(dpi, K):
                     s[i][j] = s[yi][yj]
     return s
+
+
+def _imitate(s, L, r, K, i, j, d, u):
+    """Sec. III imitation of y by x = (i, j), exact payoffs and threshold."""
+    yi, yj = (i + _DIR[d][0]) % L, (j + _DIR[d][1]) % L
+    if s[i][j] == s[yi][yj]:
+        return
+    dpi = payoff(s, L, r, i, j) - payoff(s, L, r, yi, yj)
+    if u < threshold(dpi, K):
+        s[i][j] = s[yi][yj]
+
+
+def tiled_counters(L, t, seed):
+    """Philox rows [c0, c1, c2, c3, k0, k1] of one double-tiling step
+    (Sec. IV) in execution order: part p = 0..3 (domain type 1 + p, i.e.
+    domain row parity p // 2 and column parity p % 2), its domains in raster
+    order, 16 elementary steps each; counter (domain index, t, 16 p + m, 2)."""
+    n = L // 4
+    rows = []
+    for p in range(4):
+        for I in range(p // 2, n, 2):
+            for J in range(p % 2, n, 2):
+                for m in range(16):
+                    rows.append([I * n + J, t, 16 * p + m, 2, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+    return rows
+
+
+def sweep_tiled(s, L, r, K, words):
+    """One double-tiling Monte Carlo step in place; words in the order of
+    tiled_counters.  The player is word0 >> 28 of the 4 x 4 domain (row-major),
+    the direction (word0 >> 26) & 3, the acceptance word word1."""
+    n = L // 4
+    q = 0
+    for p in range(4):
+        for I in range(p // 2, n, 2):
+            for J in range(p % 2, n, 2):
+                for _ in range(16):
+                    w = words[q]
+                    q += 1
+                    idx = int(w[0]) >> 28
+                    _imitate(s, L, r, K, 4 * I + idx // 4, 4 * J + idx % 4, (int(w[0]) >> 26) & 3, int(w[1]))
+    return s

@@ -7,7 +7,12 @@
   step.  Its stationary density must agree with oracle B's within three
   combined standard errors plus a stated systematic allowance of 0.02 for the
   schedule (measured difference about +0.009 at L = 128, r = 3.98).
-* Both must show the absorbing-state transition reported in Sec. V: below
+* Oracle C (the double tiling of Sec. IV) runs random sequential steps inside
+  each domain; its stationary density must agree with oracle B's within three
+  combined standard errors with no schedule allowance, and sit at the
+  printed rho_C = 0.5 at r = 3.98 (measured at L = 64: 0.499 +- 0.003
+  against 0.504 +- 0.003 for oracle B).
+* All must show the absorbing-state transition reported in Sec. V: below
   r ~ 3.74 cooperators die out, above it they survive.
 """
 from concurrent.futures import ProcessPoolExecutor
@@ -35,6 +40,22 @@ def _rho_a(args):
     s, _ = oracle.init(L, 0.5, seed)
     _, c = oracle.sweep(s, r, 0.5, seed, 0, RELAX + MEASURE)
     return float(c[RELAX:].mean()) / (L * L)
+
+
+def _rho_c(args):
+    import oracle
+    r, seed = args
+    s, _ = oracle.init(L, 0.5, seed)
+    _, c = oracle.sweep_tiled(s, r, 0.5, seed, 0, RELAX + MEASURE)
+    return float(c[RELAX:].mean()) / (L * L)
+
+
+def _final_c(args):
+    import oracle
+    r, seed, n = args
+    s, _ = oracle.init(L, 0.5, seed)
+    _, c = oracle.sweep_tiled(s, r, 0.5, seed, 0, n)
+    return int(c[-1])
 
 
 def _final_a(args):
@@ -76,9 +97,18 @@ def test_sweep_schedule_agrees_with_random_sequential(pool, r):
     assert abs(ma - mb) < 3 * np.hypot(ea, eb) + SCHEDULE_ALLOWANCE, (ma, ea, mb, eb)
 
 
+@pytest.mark.parametrize("r", [3.98, 4.6])
+def test_tiled_schedule_agrees_with_random_sequential(pool, r):
+    mc, ec = _mean_sem(list(pool.map(_rho_c, [(r, s) for s in SEEDS])))
+    mb, eb = _mean_sem(list(pool.map(_rho_b, [(r, s) for s in SEEDS])))
+    assert abs(mc - mb) < 3 * np.hypot(ec, eb), (mc, ec, mb, eb)
+    if r == 3.98:
+        assert abs(mc - 0.5) < max(0.015, 3 * ec), (mc, ec)
+
+
 def test_extinction_below_and_survival_above_threshold(pool):
     n = 1000
-    for fn in (_final_a, _final_b):
+    for fn in (_final_a, _final_b, _final_c):
         low = list(pool.map(fn, [(3.5, s, n) for s in range(1, 5)]))
         high = list(pool.map(fn, [(4.2, s, n) for s in range(1, 5)]))
         assert all(v == 0 for v in low), low
