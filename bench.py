@@ -104,10 +104,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def make_sim(pgg, L, r, seed, kernel, layout, stream, tile=0, group=0):
+    """The lattice of the timed passes; kernel "tiled" is the double-tiling
+    schedule (its own kernel), every other name a kernel of the 16-colour
+    sweep."""
+    if kernel == "tiled":
+        return pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, "auto", stream=stream, schedule="tiled")
+    return pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
+
+
 def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0, group=0):
     """Wall time of `steps` sweeps after `warmup`, and the HIP-event time of
     the same region recorded on the stream the sweep kernels run on."""
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
+    sim = make_sim(pgg, L, r, seed, kernel, layout, stream, tile, group)
     sim.sweep(warmup, want_counts=False)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -126,7 +135,7 @@ def time_sweeps(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, t
 
 def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, tile=0, group=0):
     """Same trajectory with every sweep-kernel launch bracketed by events."""
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
+    sim = make_sim(pgg, L, r, seed, kernel, layout, stream, tile, group)
     sim.sweep(warmup, want_counts=False)
     sim.set_kernel_timing(True)
     sim.sweep(steps, want_counts=False)
@@ -190,7 +199,7 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
 def late_window(pgg, torch, L, r, seed, kernel, layout, t_start, steps, stream, tile=0, group=0):
     """The same lattice later in its decay: sweeps t_start .. t_start+steps-1
     (fewer active sites, so fewer draws per sweep)."""
-    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, seed, layout, kernel, stream=stream, tile=tile, group=group)
+    sim = make_sim(pgg, L, r, seed, kernel, layout, stream, tile, group)
     sim.sweep(t_start, want_counts=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -302,7 +311,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel", default="segment_pair",
                     choices=["segment", "segment_pair", "strip", "rowband_staged", "rowband_compact", "rowband",
-                             "colour"])
+                             "colour", "tiled"],
+                    help="sweep kernel of the 16-colour schedule, or 'tiled': the double-tiling schedule of "
+                         "Sec. IV (a different dynamics)")
     ap.add_argument("--layout", default="auto", choices=["auto", "int8", "bits"],
                     help="lattice storage (auto: int8 for the colour kernel, else bits); the segment kernels "
                          "run an int8 lattice through a bit-packed working copy")
@@ -380,7 +391,7 @@ def main():
     # clock, first workgroup start to last workgroup end).
     avg_ms = region_ms / max(launches, 1)
     sites_per_launch = updates / max(launches, 1)  # the strip kernel: one launch per timed call
-    if args.kernel == "colour":
+    if args.kernel in ("colour", "tiled"):
         drawn = updates
     drawn_per_launch = drawn / max(launches, 1)
     slots = drawn_per_launch * SLOTS_PER_DRAWN_UPDATE + sites_per_launch * SLOTS_PER_SITE_SCAN
@@ -391,7 +402,8 @@ def main():
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": {"segment": "k_ens_segment", "segment_pair": "k_ens_pair", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
                            "rowband_compact": "k_rowband_bits<true>",
-                           "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8"}[args.kernel],
+                           "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8",
+                           "tiled": "k_tiled_part"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,
                 "avg_launch_source": "HIP events around the timed region on the sweep stream / launches",
                 "timing_pass_event_us_per_launch": kms / max(launches, 1) * 1e3,

@@ -127,6 +127,29 @@ typedef enum {
                                for SEGMENT, through a bit-packed working copy */
 } pgg_kernel;
 
+/* The update schedule: which dynamics a Monte Carlo step runs.  Unlike the
+ * kernel, the schedule changes the results (different sites are updated in
+ * a different order with different random numbers). */
+typedef enum {
+    PGG_SCHEDULE_COLOUR16 = 0, /* the 16-colour sublattice sweep: colours
+                                  k = 4 (i mod 4) + (j mod 4) in ascending
+                                  order, every site once per sweep; Philox
+                                  counter (x, t, k, 0) per site            */
+    PGG_SCHEDULE_TILED = 1     /* the double tiling of Sec. IV (Fig. 2): 4 x 4
+                                  domains of four types, type 1 + 2 (I mod 2)
+                                  + (J mod 2) for domain (I, J); a Monte Carlo
+                                  step runs the types in turn, every domain of
+                                  the running type taking 16 random sequential
+                                  steps (x uniform in the domain, y uniform
+                                  among its neighbours).  Step m of part p of
+                                  domain (I, J) in sweep t uses the Philox
+                                  counter (I L/4 + J, t, 16 p + m, 2): x =
+                                  player w0 >> 28 of the domain (row-major),
+                                  direction (w0 >> 26) mod 4, u = w1.  Needs
+                                  L % 8 == 0, the bits layout, kernel AUTO,
+                                  tile 0 and group 0                       */
+} pgg_schedule;
+
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
 typedef struct {
     uint32_t L;      /* lattice side; 4 <= L <= 32768 and L % 4 == 0          */
@@ -146,6 +169,7 @@ typedef struct {
     uint32_t group;  /* SEGMENT: segment waves per workgroup, 2, 4 or 8
                         (0 = 4); other kernels: must be 0.  Results never
                         depend on it.                                         */
+    uint32_t schedule; /* pgg_schedule (0 = the 16-colour sweep)            */
 } pgg_params;
 
 typedef struct pgg_sim pgg_sim; /* opaque handle */
@@ -217,8 +241,8 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable);
 /* Totals since the last pgg_set_kernel_timing: number of timed sweep-kernel
  * launches, their summed event-to-event duration in ms (segment kernel: of
  * the chunks holding them, with the chunks' bookkeeping kernels), and the
- * number of site updates that drew random numbers (0 for the colour kernel,
- * where every update draws).
+ * number of site updates that drew random numbers (0 for the colour kernel
+ * and the tiled schedule, where every update draws).
  * All three pointers are host and must be non-NULL.  Synchronises. */
 pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, uint64_t* drawn);
 
@@ -254,7 +278,8 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
 
 /* Create n_reps replicas and draw their initial states (t = 0).
  *   reps       host array of n_reps parameter sets: 64 <= L <= 32768, L % 4
- *              == 0, layout BITS, kernel AUTO or SEGMENT; copied.
+ *              == 0, layout BITS, kernel AUTO or SEGMENT, schedule
+ *              COLOUR16; copied.
  *   tiles      host array of n_reps work splits as pgg_params.tile of
  *              the segment kernel (0 = automatic), or NULL for all
  *              automatic.
@@ -355,7 +380,7 @@ pgg_status pgg_server_create(size_t hbm_budget, uint32_t max_L, uint32_t max_res
                              void* hip_stream, pgg_server** out);
 
 /* Queue a job: p (host, copied; 64 <= L <= max_L, layout BITS, kernel AUTO
- * or SEGMENT) and n_sweeps >= 1.  A job whose footprint exceeds the whole
+ * or SEGMENT, schedule COLOUR16) and n_sweeps >= 1.  A job whose footprint exceeds the whole
  * budget is PGG_E_INVAL.  job_id (host) receives its id.  Host only. */
 pgg_status pgg_server_submit(pgg_server* s, const pgg_params* p, uint32_t n_sweeps, uint64_t* job_id);
 

@@ -26,6 +26,7 @@ void set_err(const char* fmt, ...) {
 
 constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 constexpr int kGraphChunk = 64;    // sweeps per graph replay (segment kernel)
+constexpr int kKernelTiled = 100;  // internal kernel id of the tiled schedule (not a pgg_kernel value)
 
 }  // namespace
 
@@ -165,6 +166,16 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (!std::isfinite(p->K) || !(p->K > 0.0)) { *why = "K must be finite and > 0"; return false; }
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_INT8 && p->layout != PGG_LAYOUT_BITS) { *why = "unknown layout"; return false; }
+    if (p->schedule == PGG_SCHEDULE_TILED) {
+        if (p->L % 8 != 0) { *why = "the tiled schedule needs L % 8 == 0"; return false; }
+        if (p->layout != PGG_LAYOUT_BITS) { *why = "the tiled schedule needs the bits layout"; return false; }
+        if (p->kernel != PGG_KERNEL_AUTO || p->tile != 0 || p->group != 0) {
+            *why = "the tiled schedule takes kernel AUTO, tile 0 and group 0";
+            return false;
+        }
+        return true;
+    }
+    if (p->schedule != PGG_SCHEDULE_COLOUR16) { *why = "unknown schedule"; return false; }
     const uint32_t tr = p->tile;
     const bool segment = p->kernel == PGG_KERNEL_SEGMENT || (p->kernel == PGG_KERNEL_AUTO && p->L >= 64);
     if (p->group != 0 && !segment) { *why = "group applies to the segment kernel only"; return false; }
@@ -574,7 +585,9 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     }
     s->stride = bits_stride(p->L);
     s->R = p->tile ? (int)p->tile : choose_R(p->L);
-    if (p->kernel != PGG_KERNEL_AUTO)
+    if (p->schedule == PGG_SCHEDULE_TILED)
+        s->kernel = kKernelTiled;
+    else if (p->kernel != PGG_KERNEL_AUTO)
         s->kernel = (int)p->kernel;
     else if (p->L < 64)
         s->kernel = p->layout == PGG_LAYOUT_INT8 ? PGG_KERNEL_COLOUR : PGG_KERNEL_ROWBAND_COMPACT;
@@ -658,7 +671,13 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         for (uint32_t q = 0; s->kernel != PGG_KERNEL_STRIP && q < n; ++q) {
             const uint32_t t = (uint32_t)(s->t + done + q);
             unsigned long long* dq = s->d_delta + (size_t)q * pgg::kSweepWords;
-            if (s->kernel == PGG_KERNEL_COLOUR) {
+            if (s->kernel == kKernelTiled) {
+                for (int part = 0; part < 4; ++part)
+                    PGG_HIP(s, timed_launch(s, [&] {
+                        return pgg::launch_tiled_part((uint32_t*)s->lattice, L, s->stride, part, t, s->p.seed,
+                                                      s->d_table, dq, s->stream);
+                    }));
+            } else if (s->kernel == PGG_KERNEL_COLOUR) {
                 for (int k = 0; k < 16; ++k)
                     PGG_HIP(s, timed_launch(s, [&] {
                         return pgg::launch_colour_phase((uint8_t*)s->lattice, L, k, t, s->p.seed,

@@ -512,6 +512,7 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
         if (p.layout != PGG_LAYOUT_BITS) { eerr("replica %u: ensembles use the bits layout", k); return PGG_E_INVAL; }
         if (p.kernel != PGG_KERNEL_AUTO && p.kernel != PGG_KERNEL_SEGMENT) { eerr("replica %u: ensembles use the segment kernel", k); return PGG_E_INVAL; }
         if (p.group != 0) { eerr("replica %u: group must be 0 (the ensemble's waves_per_group applies)", k); return PGG_E_INVAL; }
+        if (p.schedule != PGG_SCHEDULE_COLOUR16) { eerr("replica %u: ensembles run the 16-colour sweep", k); return PGG_E_INVAL; }
         const uint32_t w = tiles ? tiles[k] : 0;
         if (w != 0 && !pgg::segw_valid((int)p.L, (int)w)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)", k); return PGG_E_INVAL; }
     }

@@ -49,6 +49,11 @@ hipError_t launch_staged_residue(uint32_t* lat, int L, int stride, int R, int a,
                                  uint64_t seed, const uint32_t* T, unsigned long long* delta,
                                  unsigned long long* drawn, hipStream_t st);
 size_t staged_lds_bytes(int L, int R);
+// Double tiling (pgg_tiled.hip): part p (domain type 1 + p) of sweep t, every
+// domain of that type taking its 16 random sequential steps (4 per sweep).
+// L must be a multiple of 8.
+hipError_t launch_tiled_part(uint32_t* lat, int L, int stride, int part, uint32_t t, uint64_t seed,
+                             const uint32_t* T, unsigned long long* delta, hipStream_t st);
 constexpr size_t kMaxDynamicLds = 64 * 1024;
 
 // Persistent strip kernel (pgg_strip.hip).  One task per workgroup: rows

@@ -22,7 +22,9 @@ PGG_OK, PGG_E_INVAL, PGG_E_NOMEM, PGG_E_DEVICE, PGG_E_STATE = 0, -1, -2, -3, -4
 LAYOUT_INT8, LAYOUT_BITS = 0, 1
 KERNEL_AUTO, KERNEL_COLOUR, KERNEL_ROWBAND, KERNEL_ROWBAND_COMPACT, KERNEL_ROWBAND_STAGED = 0, 1, 2, 3, 4
 KERNEL_STRIP, KERNEL_SEGMENT, KERNEL_SEGMENT_PAIR = 5, 6, 7
+SCHEDULE_COLOUR16, SCHEDULE_TILED = 0, 1
 LAYOUTS = {"int8": LAYOUT_INT8, "bits": LAYOUT_BITS}
+SCHEDULES = {"colour16": SCHEDULE_COLOUR16, "tiled": SCHEDULE_TILED}
 KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBAND,
            "rowband_compact": KERNEL_ROWBAND_COMPACT, "rowband_staged": KERNEL_ROWBAND_STAGED,
            "strip": KERNEL_STRIP, "segment": KERNEL_SEGMENT, "segment_pair": KERNEL_SEGMENT_PAIR}
@@ -42,7 +44,8 @@ EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop
 class PggParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("r", ctypes.c_double), ("K", ctypes.c_double),
                 ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
-                ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("group", ctypes.c_uint32)]
+                ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("schedule", ctypes.c_uint32)]
 
 
 class PggServerInfo(ctypes.Structure):
@@ -119,10 +122,12 @@ def _check(status):
         raise PggError(status, load().pgg_last_error().decode())
 
 
-def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto", tile=0, group=0) -> PggParams:
+def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto", tile=0, group=0,
+                schedule="colour16") -> PggParams:
     return PggParams(int(L), float(r), float(K), float(p0), int(seed) & (2**64 - 1),
                      LAYOUTS[layout] if isinstance(layout, str) else int(layout),
-                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(tile), int(group))
+                     KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(tile), int(group),
+                     SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule))
 
 
 def pgg_device_bytes(params: PggParams) -> int:
@@ -217,8 +222,8 @@ class Sim:
     """One lattice on the GPU.  Mirrors the C calls one to one."""
 
     def __init__(self, L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto",
-                 dev_buf=None, stream=None, tile=0, group=0):
-        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile, group)
+                 dev_buf=None, stream=None, tile=0, group=0, schedule="colour16"):
+        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile, group, schedule)
         self.L = int(L)
         self._buf = dev_buf  # keep a caller tensor alive as long as the handle
         self.handle = pgg_init(self.params, dev_buf, stream)

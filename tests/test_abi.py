@@ -35,9 +35,10 @@ def test_every_declared_symbol_is_exported(pgg):
 
 def test_params_struct_layout(pgg):
     # uint32 L; double r, K, p0; uint64 seed; uint32 layout, kernel, tile, group
-    assert ctypes.sizeof(pgg.PggParams) == 56
+    assert ctypes.sizeof(pgg.PggParams) == 64
     assert pgg.PggParams.seed.offset == 32
     assert pgg.PggParams.group.offset == 52
+    assert pgg.PggParams.schedule.offset == 56
 
 
 def test_device_bytes(pgg):
@@ -71,7 +72,10 @@ def test_device_bytes(pgg):
                                 dict(L=512, kernel="segment_pair", group=4),
                                 dict(layout="int8", L=480, kernel="segment_pair"),
                                 dict(layout="int8", kernel="colour", group=2),
-                                dict(L=16384, kernel="segment", tile=8192, group=8)])
+                                dict(L=16384, kernel="segment", tile=8192, group=8),
+                                dict(schedule=2), dict(L=100, schedule="tiled"), dict(L=96, schedule="tiled", layout="int8"),
+                                dict(L=96, schedule="tiled", kernel="segment"), dict(L=96, schedule="tiled", tile=32),
+                                dict(L=96, schedule="tiled", group=4)])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")
     args.update(kw)

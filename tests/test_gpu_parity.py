@@ -472,3 +472,73 @@ def test_decay_driver_matches_oracle(pgg, oracle_lib):
     say("decay driver, L", L, "t_max", n)
     grid, rho = ob.decay(pgg, L, r, seed, n, block=128)
     assert np.array_equal(rho, ob.sample_on_grid(counts, L, grid, nc0))
+
+
+# ---------------------------------------------------------------------------
+# The double tiling of Sec. IV (schedule "tiled") against oracle C.
+
+TILED_CASES = [(8, 3.8, 0.5, 31), (16, 4.4, 0.5, 32), (40, 3.9, 0.5, 33), (64, 3.75, 0.1, 34),
+               (72, 5.0, 1.5, 2**40 + 35), (96, 3.98, 0.5, 36), (128, 3.85, 0.5, 37)]
+
+
+@pytest.mark.parametrize("L,r,K,seed", TILED_CASES, ids=lambda v: str(v))
+def test_tiled_every_sweep_against_oracle(pgg, oracle_lib, L, r, K, seed):
+    """Tiny to mid-size lattices (L % 8 == 0, also not a multiple of 32):
+    lattice and count after every Monte Carlo step, bit for bit."""
+    n = 20
+    say("tiled", L, r, K, seed)
+    s0, nc0 = oracle_lib.init(L, 0.5, seed)
+    with pgg.Sim(L, r, K, 0.5, seed, "bits", schedule="tiled") as sim:
+        assert sim.coop_count() == nc0
+        ref = s0
+        for t in range(n):
+            ref, c = oracle_lib.sweep_tiled(ref, r, K, seed, t, 1)
+            assert int(sim.sweep(1)[0]) == int(c[0]), t
+            assert np.array_equal(sim.read_lattice(), ref), t
+
+
+def test_tiled_long_run_against_oracle(pgg, oracle_lib):
+    """L = 256 through 400 steps near the transition, calls of uneven length."""
+    L, r, seed, n = 256, 3.74, 41, 400
+    s0, _ = oracle_lib.init(L, 0.5, seed)
+    ref, counts = oracle_lib.sweep_tiled(s0, r, 0.5, seed, 0, n)
+    say("tiled long run", L, n)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", schedule="tiled") as sim:
+        got = np.concatenate([sim.sweep(1), sim.sweep(150), sim.sweep(249)])
+        assert np.array_equal(got, counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_tiled_L4096_against_oracle(pgg, oracle_lib):
+    """The benchmark size: two tiled steps of the L = 4096 lattice at r_c."""
+    L, r, seed = 4096, wl.R_CRITICAL, 1
+    s0, nc0 = oracle_lib.init(L, 0.5, seed)
+    ref, counts = oracle_lib.sweep_tiled(s0, r, 0.5, seed, 0, 2)
+    say("tiled L=4096")
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", schedule="tiled") as sim:
+        assert sim.coop_count() == nc0
+        assert np.array_equal(sim.sweep(2), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
+def test_tiled_resume_and_sweep_index_near_2_pow_32(pgg, oracle_lib):
+    L, r, K, seed = 48, 3.9, 0.5, 77
+    lat = wl.random_lattice(L, 0.4, 6)
+    t0 = 2**32 - 5
+    ref, counts = oracle_lib.sweep_tiled(lat, r, K, seed, t0, 5)
+    say("tiled resume near 2^32")
+    with pgg.Sim(L, r, K, 0.5, seed, "bits", schedule="tiled") as sim:
+        sim.write_lattice(lat, t0)
+        got = np.concatenate([sim.sweep(2), sim.sweep(0), sim.sweep(3)])
+        assert np.array_equal(got, counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+        with pytest.raises(pgg.PggError):
+            sim.sweep(1)
+
+
+@pytest.mark.parametrize("value", [0, 1])
+def test_tiled_absorbing_states_stay(pgg, value):
+    say("tiled absorbing", value)
+    with pgg.Sim(64, 3.8, 0.5, float(value), 3, "bits", schedule="tiled") as sim:
+        assert np.all(sim.sweep(10) == value * 64 * 64)
+        assert np.all(sim.read_lattice() == value)
