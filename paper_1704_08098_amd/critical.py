@@ -48,19 +48,20 @@ def fit_power_law(r, rho, r_c: float, window: float = 0.1):
     return float(coef[0]), float(coef[1]), float(np.mean(resid ** 2)), int(np.count_nonzero(sel))
 
 
-def fit_critical_point(r, rho, rc_grid, window: float = 0.1):
+def fit_critical_point(r, rho, rc_grid, window: float = 0.1, min_points: int = 5):
     """(r_c, beta, mean squared residual, points used) for the trial r_c of
-    rc_grid whose power-law fit is best; trial values must lie below every
-    point used, so the grid should end below the smallest r with rho > 0."""
+    rc_grid whose power-law fit over at least min_points points is best;
+    trial values must lie below every point used, so the grid should end
+    below the smallest r with rho > 0."""
     best = None
     for rc in np.asarray(rc_grid, dtype=np.float64):
         f = fit_power_law(r, rho, float(rc), window)
-        if f is None:
+        if f is None or f[3] < min_points:
             continue
         if best is None or f[2] < best[2]:
             best = (float(rc), f[0], f[2], f[3])
     if best is None:
-        raise ValueError("no trial r_c leaves three points for the fit")
+        raise ValueError("no trial r_c leaves min_points points for the fit")
     return best
 
 
@@ -88,6 +89,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=500, help="replica k gets seed + k")
     ap.add_argument("--window", type=float, default=0.05, help="largest r - r_c in the fit")
     ap.add_argument("--tol", type=float, default=0.05, help="stationarity tolerance (relative)")
+    ap.add_argument("--schedule", default="colour16", choices=["colour16", "tiled"],
+                    help="colour16: one batched ensemble; tiled: the double tiling of Sec. IV, one lattice per r "
+                         "on --workers concurrent streams")
+    ap.add_argument("--workers", type=int, default=4)
     args = ap.parse_args(argv)
 
     import torch
@@ -105,20 +110,28 @@ def main(argv=None):
     print("scan: %d values of r in [%g, %g], L = %d, %d sweeps, mean over the last %d"
           % (n_r, args.r_min, args.r_max, args.L, args.sweeps, last), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    r, rho, counts = ob.r_scan(pgg, cfg, block=10_000)
+    if args.schedule == "colour16":
+        r, rho, counts = ob.r_scan(pgg, cfg, block=10_000)
+    else:
+        def progress(r_done, seed_done):
+            print("lattice r = %g (seed %d) done, %.0f s" % (r_done, seed_done, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+
+        r, rho, counts = ob.r_scan_lattices(pgg, cfg, schedule=args.schedule, workers=args.workers,
+                                            progress=progress)
     dt = time.perf_counter() - t0
     _, ok = stationary_points(counts, args.L, last, args.tol)
     fits = {}
     if np.count_nonzero(ok) >= 3:
         rc_hi = float(r[ok].min())
         rc_grid = np.arange(rc_hi - 0.03, rc_hi, 0.0001)
-        for win in sorted({args.window, 0.02, 0.05, 0.1}):
+        for win in sorted({args.window, 0.01, 0.02, 0.03, 0.05, 0.1}):
             try:
                 rc, beta, msr, npts = fit_critical_point(r[ok], rho[ok], rc_grid, win)
                 fits["%g" % win] = {"r_c": rc, "beta": beta, "mean_sq_residual": msr, "points": npts}
             except ValueError:
                 pass
-    out = {"L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
+    out = {"schedule": args.schedule, "L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
            "stationary_density": [float(v) for v in rho], "stationary": [bool(v) for v in ok],
            "seconds": dt, "replica_site_updates_per_s": n_r * float(args.L) ** 2 * args.sweeps / dt,
            "fit_by_window": fits, "tol": args.tol}

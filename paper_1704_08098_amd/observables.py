@@ -78,6 +78,56 @@ def r_scan(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None
     return np.array(cfg["r_values"], dtype=np.float64), rho, counts
 
 
+def r_scan_lattices(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None = None,
+                    schedule: str = "colour16", workers: int = 4, block: int = 10_000, progress=None):
+    """As r_scan, but one lattice per r through pgg_init / pgg_sweep (any
+    schedule, e.g. the double tiling, which the ensemble does not run):
+    `workers` host threads each drive their lattices on a stream of their
+    own, so up to that many lattices advance on the device at once.
+    progress(r, seed), if given, is called as each lattice finishes.
+    Returns (r values, stationary densities, counts)."""
+    import threading
+    import torch
+    n = int(sweeps if sweeps is not None else cfg["sweeps"])
+    last = int(average_last if average_last is not None else min(cfg["average_last"], n))
+    jobs = list(enumerate(zip(cfg["r_values"], cfg["seeds"])))
+    counts = np.zeros((len(jobs), n), dtype=np.uint64)
+    errors = []
+    lock = threading.Lock()
+
+    def worker():
+        stream = torch.cuda.Stream()
+        while True:
+            with lock:
+                if not jobs or errors:
+                    return
+                k, (r, seed) = jobs.pop(0)
+            try:
+                with pgg.Sim(cfg["L"], r, cfg["K"], cfg["p0"], seed, "bits", "auto", stream=stream,
+                             schedule=schedule) as sim:
+                    done = 0
+                    while done < n:
+                        m = min(block, n - done)
+                        counts[k, done:done + m] = sim.sweep(m)
+                        done += m
+                if progress is not None:
+                    progress(r, seed)
+            except Exception as exc:  # reported after the join
+                with lock:
+                    errors.append(exc)
+                return
+
+    threads = [threading.Thread(target=worker) for _ in range(max(1, workers))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    if errors:
+        raise errors[0]
+    rho = np.array([stationary_density(counts[k], cfg["L"], last) for k in range(counts.shape[0])])
+    return np.array(cfg["r_values"], dtype=np.float64), rho, counts
+
+
 def decay(pgg, L: int, r: float, seed: int, t_max: int, per_decade: int = 20, K: float = wl.K_PAPER,
           p0: float = 0.5, stream=None, block: int = 10_000, layout: str = "bits", kernel: str = "auto"):
     """rho_C(t) of one lattice from its i.i.d. start on the log grid of

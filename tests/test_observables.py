@@ -98,3 +98,32 @@ def test_decay_samples_the_log_grid():
     grid, rho = ob.decay(_FakePgg, 10, 3.7, 1, 120, block=50)
     assert np.array_equal(grid, wl.log_time_grid(120)[wl.log_time_grid(120) <= 120])
     assert np.allclose(rho, 3 * grid / 100.0, rtol=0, atol=1e-15)
+
+
+def test_r_scan_lattices_runs_every_replica_once(monkeypatch):
+    """One lattice per r on worker threads: every count row filled from its
+    own lattice, whatever thread ran it."""
+    torch = pytest.importorskip("torch")
+    monkeypatch.setattr(torch.cuda, "Stream", lambda: None)
+    seen = []
+
+    class Sim(_FakeSim):
+        def __init__(self, L, r, K, p0, seed, layout, kernel, stream=None, schedule="colour16"):
+            super().__init__(L, r, K, p0, seed, layout, kernel, stream)
+            seen.append((r, seed, schedule))
+            self.base = seed
+
+        def sweep(self, m):
+            t = np.arange(self.t + 1, self.t + m + 1, dtype=np.uint64)
+            self.t += m
+            return t + np.uint64(1000 * self.base)
+
+    class Fake:
+        pass
+
+    Fake.Sim = Sim
+    cfg = dict(wl.SCAN, L=10, sweeps=30, average_last=10)
+    r, rho, counts = ob.r_scan_lattices(Fake, cfg, schedule="tiled", workers=3, block=7)
+    assert sorted(seen) == sorted((rv, s, "tiled") for rv, s in zip(cfg["r_values"], cfg["seeds"]))
+    for k, s in enumerate(cfg["seeds"]):
+        assert np.array_equal(counts[k], 1000 * s + np.arange(1, 31))
