@@ -212,3 +212,26 @@ def test_r_scan_driver_matches_oracle_stationary_densities(pgg, oracle_lib):
     for k, (lat, ref_counts) in enumerate(refs):
         assert np.array_equal(counts[k], ref_counts), k
         assert rho[k] == ob.stationary_density(ref_counts, cfg["L"], cfg["average_last"]), k
+
+
+def test_r_scan_lattices_tiled_matches_oracle_c(pgg, oracle_lib):
+    """observables.r_scan_lattices (one lattice per r, four worker threads on
+    streams of their own) with the double-tiling schedule: every lattice's
+    counts equal oracle C's, whichever thread and stream ran it."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1704_08098_amd import observables as ob
+    cfg = dict(wl.SCAN, L=64, sweeps=150, average_last=50, r_values=(3.74, 3.76, 3.8, 3.9, 4.2),
+               seeds=(7, 8, 9, 10, 11))
+    args = [(cfg["L"], r, s, cfg["sweeps"]) for r, s in zip(cfg["r_values"], cfg["seeds"])]
+    with ProcessPoolExecutor(max_workers=5) as ex:
+        refs = list(ex.map(_oracle_tiled, args))
+    say("r_scan_lattices tiled, L", cfg["L"])
+    r, rho, counts = ob.r_scan_lattices(pgg, cfg, schedule="tiled", workers=4, block=40)
+    for k, ref_counts in enumerate(refs):
+        assert np.array_equal(counts[k], ref_counts), k
+
+
+def _oracle_tiled(args):
+    import oracle
+    L, r, seed, n = args
+    return oracle.run_tiled(L, r, 0.5, 0.5, seed, n)[2]
