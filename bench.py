@@ -240,6 +240,38 @@ def decay_batch_pass(pgg, torch, warmup, steps, stream):
             "unit": "replica-site updates/s", "ms_per_sweep_of_all": 1e3 * dt / steps}
 
 
+# The paper's own timing of its graphics-card code (Sec. V prose, Fig. 5 workload):
+# 10^6 Monte Carlo steps of the double tiling at L = 4096, r = 3.98, K = 0.5 in
+# "less than an hour and a half" on a GeForce GTX 1080, i.e. at least
+# 4096^2 * 10^6 / 5400 s site updates/s; the serial CPU code took nearly a month.
+PAPER_GPU_UPDATES_PER_S = 4096.0 ** 2 * 1e6 / 5400.0
+PAPER_CPU_UPDATES_PER_S = 4096.0 ** 2 * 1e6 / (30 * 86400.0)
+
+
+def paper_workload_pass(pgg, torch, warmup, steps, stream):
+    """The paper's benchmark workload with the paper's own dynamics: the
+    double tiling at L = 4096, r = 3.98, K = 0.5 from a 50/50 start."""
+    L, r = 4096, 3.98
+    sim = pgg.Sim(L, r, wl.K_PAPER, 0.5, 1, "bits", "auto", stream=stream, schedule="tiled")
+    sim.sweep(warmup, want_counts=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(steps, want_counts=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rho = sim.density()
+    sim.close()
+    value = float(L) * L * steps / dt
+    return {"schedule": "tiled (Sec. IV double tiling)", "L": L, "r": r, "steps": steps,
+            "value": value, "unit": "site updates/s", "ms_per_step": 1e3 * dt / steps, "density_at_end": rho,
+            "paper_gtx1080_updates_per_s": PAPER_GPU_UPDATES_PER_S,
+            "paper_xeon_updates_per_s": PAPER_CPU_UPDATES_PER_S,
+            "ratio_vs_paper_gpu": value / PAPER_GPU_UPDATES_PER_S,
+            "note": "context, not a target: the paper's numbers are derived from its prose (10^6 steps at "
+                    "L = 4096 in under 1.5 h on a GTX 1080, nearly a month on a 2.8 GHz Xeon) and were "
+                    "measured on other hardware"}
+
+
 def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64):
     """Poisson arrivals of simulation jobs through the C job server at 70 %
     of its capacity.  The capacity is measured first: calib_jobs jobs of the
@@ -327,6 +359,8 @@ def main():
     ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
+    ap.add_argument("--no-paper-workload", dest="paper_workload", action="store_false",
+                    help="skip the paper's own workload (double tiling, L = 4096, r = 3.98)")
     ap.add_argument("--no-decay-batch", dest="decay_batch", action="store_false",
                     help="skip the nine L = 4096 decay lattices run as one ensemble")
     ap.add_argument("--scan-sweeps", type=int, default=10_000,
@@ -425,6 +459,11 @@ def main():
         batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream,
                                 not args.no_autotune)
 
+    paper_workload = None
+    if args.paper_workload:
+        log("paper workload: double tiling, L=4096, r=3.98")
+        paper_workload = paper_workload_pass(pgg, torch, args.warmup, args.steps, stream)
+
     decay_batch = None
     if args.decay_batch:
         log("decay batch: 9 lattices of L=%d as one ensemble" % wl.DECAY["L"])
@@ -462,7 +501,7 @@ def main():
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
         "roofline": roofline, "hbm": hbm, "dense": dense, "late": late, "batched": batched, "serving": serving,
-        "scan": scan, "decay_batch": decay_batch,
+        "scan": scan, "decay_batch": decay_batch, "paper_workload": paper_workload,
         "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }
