@@ -68,21 +68,27 @@ k_tiled_part(uint32_t* __restrict__ lat, int L, int stride, int part, uint32_t t
     int my_delta = 0;
     if (on) {
         const uint32_t D = (uint32_t)(I * (L >> 2) + J);
-#pragma unroll 1
+        // The random words do not depend on the lattice: draw all 16 first
+        // (independent Philox blocks, so they overlap), then run the steps,
+        // whose chain is only the LDS stencil and the flip.
+        uint2 rnd[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) rnd[m] = philox4x32_10_w01(D, t, (uint32_t)(16 * part + m), 2u, k0, k1);
+#pragma unroll
         for (int m = 0; m < 16; ++m) {
-            const uint2 rnd = philox4x32_10_w01(D, t, (uint32_t)(16 * part + m), 2u, k0, k1);
-            const int idx = (int)(rnd.x >> 28);
-            const int d = (int)((rnd.x >> 26) & 3u);
+            const int idx = (int)(rnd[m].x >> 28);
+            const int d = (int)((rnd[m].x >> 26) & 3u);
             const int rx = 3 + (idx >> 2), cx = 3 + (idx & 3);  // window position of x
             const int ry = rx + dir_di(d), cy = cx + dir_dj(d);
             const int sx = (int)((w[rx * kTiledThreads] >> cx) & 1u);
             const int sy = (int)((w[ry * kTiledThreads] >> cy) & 1u);
             const int ds = sx - sy;
-            if (ds == 0) continue;  // copying an equal strategy changes nothing
-            const int dsig = tiled_rest(w, rx, cx) - tiled_rest(w, ry, cy) + 5 * ds;
-            if (rnd.y < sT[(dsig + 25) * 3 + ds + 1]) {
-                w[rx * kTiledThreads] ^= 1u << cx;
-                my_delta += sy ? 1 : -1;
+            if (ds != 0) {  // copying an equal strategy changes nothing
+                const int dsig = tiled_rest(w, rx, cx) - tiled_rest(w, ry, cy) + 5 * ds;
+                if (rnd[m].y < sT[(dsig + 25) * 3 + ds + 1]) {
+                    w[rx * kTiledThreads] ^= 1u << cx;
+                    my_delta += sy ? 1 : -1;
+                }
             }
         }
         // write back the domain's changed bits (other lanes write other
