@@ -272,14 +272,14 @@ def paper_workload_pass(pgg, torch, warmup, steps, stream):
                     "measured on other hardware"}
 
 
-def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64):
+def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64, chunk=16):
     """Poisson arrivals of simulation jobs through the C job server at 70 %
     of its capacity.  The capacity is measured first: calib_jobs jobs of the
     same distribution all submitted at once (a closed batch)."""
     from paper_1704_08098_amd import server
 
     def run(jobs):
-        engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, chunk=16, stream=stream)
+        engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, chunk=chunk, stream=stream)
         try:
             rep = server.serve(engine, jobs)
         finally:
@@ -298,7 +298,7 @@ def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64):
     rep = run(wl.serving_trace(n_jobs, rate))
     rep.update({"arrival_rate_per_s": rate, "offered_load": 0.7, "capacity_site_updates_per_s": capacity,
                 "capacity_basis": "%d jobs of the same distribution submitted at once (closed batch)" % calib_jobs,
-                "hbm_budget_MiB": budget_mib, "chunk": 16,
+                "hbm_budget_MiB": budget_mib, "chunk": chunk,
                 "trace": "Poisson arrivals; L log-uniform in [64, 2048] (multiples of 4), r ~ U[3.5, 5.6], "
                          "MCS ~ U{1000..10000}, p0 ~ U[0.1, 0.9], seed 7"})
     return rep
@@ -359,6 +359,7 @@ def main():
     ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
+    ap.add_argument("--serve-chunk", type=int, default=16, help="sweeps per server step")
     ap.add_argument("--no-paper-workload", dest="paper_workload", action="store_false",
                     help="skip the paper's own workload (double tiling, L = 4096, r = 3.98)")
     ap.add_argument("--no-decay-batch", dest="decay_batch", action="store_false",
@@ -478,7 +479,7 @@ def main():
     serving = None
     if args.serve_jobs > 0:
         log("serving pass: capacity batch, then %d jobs" % args.serve_jobs)
-        serving = serving_pass(pgg, args.serve_jobs, stream)
+        serving = serving_pass(pgg, args.serve_jobs, stream, chunk=args.serve_chunk)
 
     scan = None
     if args.scan_sweeps > 0:
