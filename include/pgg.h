@@ -146,8 +146,9 @@ typedef enum {
                                   counter (I L/4 + J, t, 16 p + m, 2): x =
                                   player w0 >> 28 of the domain (row-major),
                                   direction (w0 >> 26) mod 4, u = w1.  Needs
-                                  L % 8 == 0, the bits layout, kernel AUTO,
-                                  tile 0 and group 0                       */
+                                  L % 8 == 0, kernel AUTO, tile 0 and group
+                                  0; on the int8 layout the steps run on a
+                                  bit-packed working copy, as for SEGMENT  */
 } pgg_schedule;
 
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */

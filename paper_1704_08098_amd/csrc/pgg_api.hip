@@ -168,7 +168,6 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (p->layout != PGG_LAYOUT_INT8 && p->layout != PGG_LAYOUT_BITS) { *why = "unknown layout"; return false; }
     if (p->schedule == PGG_SCHEDULE_TILED) {
         if (p->L % 8 != 0) { *why = "the tiled schedule needs L % 8 == 0"; return false; }
-        if (p->layout != PGG_LAYOUT_BITS) { *why = "the tiled schedule needs the bits layout"; return false; }
         if (p->kernel != PGG_KERNEL_AUTO || p->tile != 0 || p->group != 0) {
             *why = "the tiled schedule takes kernel AUTO, tile 0 and group 0";
             return false;
@@ -623,7 +622,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
     pgg_params bits = *p;
     bits.layout = PGG_LAYOUT_BITS;
-    if (st == PGG_OK && segment_path && p->layout == PGG_LAYOUT_INT8) st = alloc((void**)&s->shadow, lattice_bytes(&bits));
+    const bool packed_copy = (segment_path || s->kernel == kKernelTiled) && p->layout == PGG_LAYOUT_INT8;
+    if (st == PGG_OK && packed_copy) st = alloc((void**)&s->shadow, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = alloc((void**)&s->lattice2, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = plan_segment_graph(s);
     if (st != PGG_OK) { release(s); return st; }
@@ -653,6 +653,10 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     if (s->kernel == PGG_KERNEL_SEGMENT || s->kernel == PGG_KERNEL_SEGMENT_PAIR)
         return sweep_segment(s, n_sweeps, coop_counts);
     const int L = (int)s->p.L;
+    // the tiled schedule on the int8 layout sweeps a bit-packed working copy
+    uint32_t* tiled_lat = s->shadow ? s->shadow : (uint32_t*)s->lattice;
+    if (s->kernel == kKernelTiled && s->shadow)
+        PGG_HIP(s, pgg::launch_pack((const uint8_t*)s->lattice, s->shadow, L, s->stride, s->stream));
     uint32_t done = 0;
     while (done < n_sweeps) {
         const uint32_t n = std::min(kChunk, n_sweeps - done);
@@ -674,7 +678,7 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
             if (s->kernel == kKernelTiled) {
                 for (int part = 0; part < 4; ++part)
                     PGG_HIP(s, timed_launch(s, [&] {
-                        return pgg::launch_tiled_part((uint32_t*)s->lattice, L, s->stride, part, t, s->p.seed,
+                        return pgg::launch_tiled_part(tiled_lat, L, s->stride, part, t, s->p.seed,
                                                       s->d_table, dq, s->stream);
                     }));
             } else if (s->kernel == PGG_KERNEL_COLOUR) {
@@ -711,6 +715,8 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         }
         done += n;
     }
+    if (s->kernel == kKernelTiled && s->shadow)
+        PGG_HIP(s, pgg::launch_unpack(s->shadow, (uint8_t*)s->lattice, L, s->stride, s->stream));
     s->t += n_sweeps;
     return PGG_OK;
 }

@@ -73,7 +73,7 @@ def test_device_bytes(pgg):
                                 dict(layout="int8", L=480, kernel="segment_pair"),
                                 dict(layout="int8", kernel="colour", group=2),
                                 dict(L=16384, kernel="segment", tile=8192, group=8),
-                                dict(schedule=2), dict(L=100, schedule="tiled"), dict(L=96, schedule="tiled", layout="int8"),
+                                dict(schedule=2), dict(L=100, schedule="tiled"), dict(L=92, schedule="tiled", layout="int8"),
                                 dict(L=96, schedule="tiled", kernel="segment"), dict(L=96, schedule="tiled", tile=32),
                                 dict(L=96, schedule="tiled", group=4)])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):

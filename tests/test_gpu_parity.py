@@ -542,3 +542,23 @@ def test_tiled_absorbing_states_stay(pgg, value):
     with pgg.Sim(64, 3.8, 0.5, float(value), 3, "bits", schedule="tiled") as sim:
         assert np.all(sim.sweep(10) == value * 64 * 64)
         assert np.all(sim.read_lattice() == value)
+
+
+@pytest.mark.parametrize("L", [8, 64, 136])
+def test_tiled_int8_layout_against_oracle(pgg, oracle_lib, L):
+    """The tiled schedule on the int8 layout (a bit-packed working copy):
+    every step bit for bit, calls of several lengths, a written lattice."""
+    r, seed = 3.9, 60 + L
+    s0, nc0 = oracle_lib.init(L, 0.5, seed)
+    ref, counts = oracle_lib.sweep_tiled(s0, r, 0.5, seed, 0, 12)
+    say("tiled int8", L)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "int8", schedule="tiled") as sim:
+        assert sim.coop_count() == nc0
+        got = np.concatenate([sim.sweep(1), sim.sweep(4), sim.sweep(7)])
+        assert np.array_equal(got, counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+        lat = wl.random_lattice(L, 0.6, 3)
+        ref2, counts2 = oracle_lib.sweep_tiled(lat, r, 0.5, seed, 30, 5)
+        sim.write_lattice(lat, 30)
+        assert np.array_equal(sim.sweep(5), counts2)
+        assert np.array_equal(sim.read_lattice(), ref2)
