@@ -463,6 +463,56 @@ def test_long_trajectory_whole_rows(pgg, oracle_lib):
         assert np.array_equal(sim.read_lattice(), ref)
 
 
+def _golden_decay():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "trajectory_L4096_r3.7443_seed1.txt")
+    params, marks, counts = {}, {}, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, *rest = line.split()
+            if key == "lattice":
+                marks[int(rest[0])] = rest[1]
+            elif key == "count":
+                counts[int(rest[0])] = int(rest[1])
+            else:
+                params[key] = float(rest[0]) if key in ("r", "K", "p0") else int(rest[0])
+    return params, marks, np.array([counts[t] for t in range(len(counts))], dtype=np.uint64)
+
+
+def test_benchmark_workload_against_stored_oracle_trajectory(pgg):
+    """The single-lattice benchmark workload (L = 4096, r = r_c, seed 1) in
+    the kernel and launch configuration the benchmark times (the paired
+    segment kernel, graph replays on a side stream, calls of 20 and then
+    1000 sweeps): N_C after every one of the 1020 sweeps and the lattice
+    after 20, 520 and 1020 sweeps equal the oracle's stored trajectory
+    (tests/golden/make_trajectories.py)."""
+    import hashlib
+    import torch
+    params, marks, counts = _golden_decay()
+    L, r, K, p0, seed = params["L"], params["r"], params["K"], params["p0"], params["seed"]
+    assert (L, r, seed) == (wl.DECAY["L"], wl.R_CRITICAL, 1)
+    stream = torch.cuda.Stream()
+    say("benchmark workload vs stored oracle trajectory, L", L, "sweeps", len(counts) - 1)
+
+    def digest(sim):
+        return hashlib.sha256(sim.read_lattice().tobytes()).hexdigest()
+
+    with pgg.Sim(L, r, K, p0, seed, "bits", "segment_pair", stream=stream) as sim:
+        assert sim.coop_count() == int(counts[0])
+        got = [sim.sweep(20)]
+        assert digest(sim) == marks[20]
+        got += [sim.sweep(500)]
+        assert digest(sim) == marks[520]
+        got += [sim.sweep(500)]
+        assert digest(sim) == marks[1020]
+        got = np.concatenate(got)
+        bad = np.flatnonzero(got != counts[1:])
+        assert bad.size == 0, "first differing sweep %d" % (bad[0] + 1 if bad.size else -1)
+
+
+
 def test_decay_driver_matches_oracle(pgg, oracle_lib):
     """observables.decay (one lattice, counts fetched in blocks, rho_C on the
     log grid) equals the same grid read off the oracle's counts."""
