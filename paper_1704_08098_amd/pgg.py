@@ -288,7 +288,7 @@ def _replica_params(replicas):
     arr = (PggParams * len(replicas))()
     for k, rp in enumerate(replicas):
         arr[k] = make_params(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5),
-                             rp.get("seed", 1), "bits", "auto")
+                             rp.get("seed", 1), "bits", "auto", schedule=rp.get("schedule", "colour16"))
     return arr
 
 

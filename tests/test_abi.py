@@ -114,7 +114,8 @@ def test_engine_has_no_cpu_fallback():
                 assert "pgg_ref_" not in text, f
 
 
-@pytest.mark.parametrize("bad", [dict(L=60), dict(L=130), dict(r=-1.0), dict(K=0.0), dict(p0=2.0)])
+@pytest.mark.parametrize("bad", [dict(L=60), dict(L=130), dict(r=-1.0), dict(K=0.0), dict(p0=2.0),
+                                 dict(schedule="tiled")])
 def test_ensemble_calls_reject_invalid_replicas_before_touching_the_device(pgg, bad):
     reps = [dict(L=128, r=3.8, seed=1), dict(L=256, r=3.7, seed=2)]
     reps[1].update(bad)
