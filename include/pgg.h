@@ -279,8 +279,11 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
 
 /* Create n_reps replicas and draw their initial states (t = 0).
  *   reps       host array of n_reps parameter sets: 64 <= L <= 32768, L % 4
- *              == 0, layout BITS, kernel AUTO or SEGMENT, schedule
- *              COLOUR16; copied.
+ *              == 0, layout BITS, kernel AUTO or SEGMENT, group 0, and one
+ *              schedule for all of them; copied.  With PGG_SCHEDULE_TILED
+ *              (L % 8 == 0) every launch covers one domain type of one step
+ *              of every replica, in place, and tiles and waves_per_group do
+ *              not apply (tiles NULL or all 0).
  *   tiles      host array of n_reps work splits as pgg_params.tile of
  *              the segment kernel (0 = automatic), or NULL for all
  *              automatic.
@@ -318,7 +321,8 @@ void pgg_ensemble_destroy(pgg_ensemble* e);
 /* Autotune the batched launch for a set of replicas: the segment width of
  * each distinct L, the waves per workgroup and the chunk length of a graph
  * replay.  Results never depend on them; only the speed does.
- *   reps, n_reps  as for pgg_ensemble_create.
+ *   reps, n_reps  as for pgg_ensemble_create, schedule COLOUR16 (the tiled
+ *                 schedule has nothing to tune: PGG_E_INVAL).
  *   probe_sweeps  sweeps timed per trial, 1..4096 (after 2 untimed ones).
  *   hip_stream    as for pgg_ensemble_create.
  *   tiles_out     host array of n_reps: the chosen width of each replica

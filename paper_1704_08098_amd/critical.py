@@ -90,8 +90,9 @@ def main(argv=None):
     ap.add_argument("--window", type=float, default=0.05, help="largest r - r_c in the fit")
     ap.add_argument("--tol", type=float, default=0.05, help="stationarity tolerance (relative)")
     ap.add_argument("--schedule", default="colour16", choices=["colour16", "tiled"],
-                    help="colour16: one batched ensemble; tiled: the double tiling of Sec. IV, one lattice per r "
-                         "on --workers concurrent streams")
+                    help="colour16: the 16-colour sweep; tiled: the double tiling of Sec. IV")
+    ap.add_argument("--per-lattice", action="store_true",
+                    help="one lattice per r on --workers concurrent streams instead of one batched ensemble")
     ap.add_argument("--workers", type=int, default=4)
     args = ap.parse_args(argv)
 
@@ -110,8 +111,8 @@ def main(argv=None):
     print("scan: %d values of r in [%g, %g], L = %d, %d sweeps, mean over the last %d"
           % (n_r, args.r_min, args.r_max, args.L, args.sweeps, last), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    if args.schedule == "colour16":
-        r, rho, counts = ob.r_scan(pgg, cfg, block=10_000)
+    if not args.per_lattice:
+        r, rho, counts = ob.r_scan(pgg, cfg, block=10_000, schedule=args.schedule)
     else:
         def progress(r_done, seed_done):
             print("lattice r = %g (seed %d) done, %.0f s" % (r_done, seed_done, time.perf_counter() - t0),
@@ -131,7 +132,7 @@ def main(argv=None):
                 fits["%g" % win] = {"r_c": rc, "beta": beta, "mean_sq_residual": msr, "points": npts}
             except ValueError:
                 pass
-    out = {"schedule": args.schedule, "L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
+    out = {"schedule": args.schedule, "batched": not args.per_lattice, "L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
            "stationary_density": [float(v) for v in rho], "stationary": [bool(v) for v in ok],
            "seconds": dt, "replica_site_updates_per_s": n_r * float(args.L) ** 2 * args.sweeps / dt,
            "fit_by_window": fits, "tol": args.tol}

@@ -258,7 +258,7 @@ k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restric
 // lat2: copy it back (one block per replica).
 __global__ void k_ens_copyback(const EnsRep* __restrict__ reps) {
     const EnsRep& rp = reps[blockIdx.x];
-    if ((rp.n_active & 1) == 0) return;
+    if (rp.tiled || (rp.n_active & 1) == 0) return;  // the tiled schedule updates in place
     const int n = rp.L * rp.stride;
     for (int k = threadIdx.x; k < n; k += blockDim.x) rp.lat[k] = rp.lat2[k];
 }
@@ -429,7 +429,8 @@ struct pgg_ensemble {
     int n = 0;
     int chunk = 32;          // sweeps per graph replay
     int wpg = pgg::kWavesPerGroup;  // waves (segments of one replica) per workgroup
-    int total_waves = 0;
+    int total_waves = 0;     // the tiled schedule: workgroups of a launch
+    bool tiled = false;      // every replica runs the double tiling of Sec. IV
     size_t lds = 0;
     std::vector<pgg::EnsRep> host_reps;
     pgg::EnsRep* d_reps = nullptr;
@@ -474,6 +475,8 @@ void ens_release(pgg_ensemble* e) {
 }
 
 hipError_t enqueue_chunk(pgg_ensemble* e, int len) {
+    if (e->tiled)
+        return pgg::launch_ens_tiled_chunk(e->d_reps, e->n, e->total_waves, len, e->chunk, e->d_counts, e->stream);
     return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts,
                                  e->stream, e->wpg);
 }
@@ -512,7 +515,12 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
         if (p.layout != PGG_LAYOUT_BITS) { eerr("replica %u: ensembles use the bits layout", k); return PGG_E_INVAL; }
         if (p.kernel != PGG_KERNEL_AUTO && p.kernel != PGG_KERNEL_SEGMENT) { eerr("replica %u: ensembles use the segment kernel", k); return PGG_E_INVAL; }
         if (p.group != 0) { eerr("replica %u: group must be 0 (the ensemble's waves_per_group applies)", k); return PGG_E_INVAL; }
-        if (p.schedule != PGG_SCHEDULE_COLOUR16) { eerr("replica %u: ensembles run the 16-colour sweep", k); return PGG_E_INVAL; }
+        if (p.schedule != PGG_SCHEDULE_COLOUR16 && p.schedule != PGG_SCHEDULE_TILED) { eerr("replica %u: unknown schedule", k); return PGG_E_INVAL; }
+        if (p.schedule != reps[0].schedule) { eerr("replica %u: every replica of an ensemble runs the same schedule", k); return PGG_E_INVAL; }
+        if (p.schedule == PGG_SCHEDULE_TILED && (p.L % 8 != 0 || (tiles && tiles[k] != 0))) {
+            eerr("replica %u: the tiled schedule needs L % 8 == 0 and tile 0", k);
+            return PGG_E_INVAL;
+        }
         const uint32_t w = tiles ? tiles[k] : 0;
         if (w != 0 && !pgg::segw_valid((int)p.L, (int)w)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)", k); return PGG_E_INVAL; }
     }
@@ -541,6 +549,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     e->n = (int)n_reps;
     e->chunk = (int)chunk;
     e->wpg = wpg;
+    e->tiled = reps[0].schedule == PGG_SCHEDULE_TILED;
     if (hipGetDevice(&e->device) != hipSuccess) { eerr("no HIP device"); ens_release(e); return PGG_E_DEVICE; }
 
     // Layout: lattices back to back (256-byte aligned), tables, per-replica waves.
@@ -558,13 +567,14 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         rp.k1 = (uint32_t)(p.seed >> 32);
         rp.t0 = 0;
         rp.wave_base = waves;
-        waves += pgg::ens_waves(rp, wpg);
+        rp.tiled = e->tiled ? 1 : 0;
+        waves += e->tiled ? pgg::tiled_blocks(rp.L) : pgg::ens_waves(rp, wpg);
         lat_off[k] = lat_words;
-        lat_words += 2 * (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);  // lat and lat2
-        max_words = std::max(max_words, pgg::ens_wave_words(rp));
+        lat_words += (e->tiled ? 1 : 2) * (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);  // lat (and lat2)
+        if (!e->tiled) max_words = std::max(max_words, pgg::ens_wave_words(rp));
     }
     e->total_waves = waves;
-    e->lds = pgg::ens_lds_bytes(max_words, wpg);
+    e->lds = e->tiled ? 0 : pgg::ens_lds_bytes(max_words, wpg);
     if (e->lds > pgg::kMaxDynamicLds) {
         eerr("the widest replica layout (%d LDS words per wave) does not fit %d waves per workgroup", max_words, wpg);
         ens_release(e);
@@ -589,7 +599,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     for (uint32_t k = 0; k < n_reps; ++k) {
         pgg::EnsRep& rp = e->host_reps[k];
         rp.lat = e->d_lattices + lat_off[k];
-        rp.lat2 = rp.lat + (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);
+        rp.lat2 = e->tiled ? nullptr : rp.lat + (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);
         rp.T = e->d_tables + (size_t)k * 160;
         rp.delta = e->d_delta + (size_t)k * chunk * pgg::kSweepWords;
         rp.nc = e->d_nc + k;
@@ -683,6 +693,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     if (probe_sweeps == 0 || probe_sweeps > 4096) { eerr("probe_sweeps must lie in [1, 4096]"); return PGG_E_INVAL; }
     const pgg_status vs = validate_reps(reps, n_reps, nullptr, 1);
     if (vs != PGG_OK) return vs;
+    if (reps[0].schedule == PGG_SCHEDULE_TILED) { eerr("the tiled schedule has nothing to tune"); return PGG_E_INVAL; }
     std::vector<uint32_t> sizes;
     for (uint32_t k = 0; k < n_reps; ++k)
         if (std::find(sizes.begin(), sizes.end(), reps[k].L) == sizes.end()) sizes.push_back(reps[k].L);

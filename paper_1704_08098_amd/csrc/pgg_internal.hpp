@@ -54,6 +54,8 @@ size_t staged_lds_bytes(int L, int R);
 // L must be a multiple of 8.
 hipError_t launch_tiled_part(uint32_t* lat, int L, int stride, int part, uint32_t t, uint64_t seed,
                              const uint32_t* T, unsigned long long* delta, hipStream_t st);
+// Workgroups of one tiled launch for side L.
+int tiled_blocks(int L);
 constexpr size_t kMaxDynamicLds = 64 * 1024;
 
 // Persistent strip kernel (pgg_strip.hip).  One task per workgroup: rows
@@ -100,6 +102,7 @@ struct EnsRep {
     int L, stride, nw, segw, nseg, wave_base, n_active;
     int rpw;                    // full-row sweep (segw == L): rows per wave; 0 = segments
     uint32_t k0, k1, t0;
+    int tiled;                  // 1: the double-tiling schedule (in place; wave_base counts workgroups)
 };
 
 // Automatic work split for side L: L itself (whole rows per wave) when L is
@@ -139,6 +142,11 @@ constexpr int kSpanWords = 2 * kSpanSlots;
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
                               hipStream_t st, int wpg = kWavesPerGroup, unsigned long long* span = nullptr);
 hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st);
+// One chunk of a tiled ensemble (pgg_tiled.hip): the same bookkeeping as
+// launch_ens_chunk, 4 part launches per sweep over total_blocks workgroups
+// (each replica's tiled_blocks(L), in replica order), in place.
+hipError_t launch_ens_tiled_chunk(EnsRep* d_reps, int n, int total_blocks, int len, int chunk,
+                                  unsigned long long* counts, hipStream_t st);
 // Two residues per launch for one lattice (pgg_ensemble.hip, k_ens_pair):
 // workgroups of kPairBand rows x one segment; d_rep holds the one replica.
 constexpr int kPairBand = 32;

@@ -40,15 +40,16 @@ __device__ __forceinline__ int tiled_rest(const uint32_t* __restrict__ w, int r,
                              w[(r + 2) * kTiledThreads] << sh);
 }
 
-__global__ void __launch_bounds__(kTiledThreads)
-k_tiled_part(uint32_t* __restrict__ lat, int L, int stride, int part, uint32_t t, uint32_t k0, uint32_t k1,
-             const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta) {
-    __shared__ uint32_t sT[kTableSize];
-    __shared__ uint32_t win[10 * kTiledThreads];  // window row o of lane l at win[o * kTiledThreads + l]
-    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = T[k];
+// The 16 random sequential steps of the domain of lane g (0 <= g <
+// (L/8)^2, or on == false for a padding lane) of part `part` in sweep t:
+// fill the lane's window, run the steps, write back the changed bits.  sT:
+// the threshold table in LDS (loaded and synchronised by the caller before
+// this is called; the function synchronises the workgroup once itself).
+// Returns the net change of the cooperator count.
+__device__ __forceinline__ int tiled_domain(uint32_t* __restrict__ lat, int L, int stride, int part, uint32_t t,
+                                            uint32_t k0, uint32_t k1, const uint32_t* __restrict__ sT,
+                                            uint32_t* __restrict__ win, int g, bool on) {
     const int half = L >> 3;  // domains of one type per row of domains
-    const int g = (int)blockIdx.x * kTiledThreads + (int)threadIdx.x;
-    const bool on = g < half * half;
     const int I = (part >> 1) + 2 * (on ? g / half : 0);
     const int J = (part & 1) + 2 * (on ? g % half : 0);
     const int nw = (L + 31) >> 5;
@@ -102,6 +103,10 @@ k_tiled_part(uint32_t* __restrict__ lat, int L, int stride, int part, uint32_t t
             }
         }
     }
+    return my_delta;
+}
+
+__device__ __forceinline__ void add_delta(int my_delta, unsigned long long* __restrict__ delta) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
     if ((threadIdx.x & 63) == 0 && my_delta)
@@ -109,16 +114,70 @@ k_tiled_part(uint32_t* __restrict__ lat, int L, int stride, int part, uint32_t t
                   (unsigned long long)(long long)my_delta);
 }
 
+__global__ void __launch_bounds__(kTiledThreads)
+k_tiled_part(uint32_t* __restrict__ lat, int L, int stride, int part, uint32_t t, uint32_t k0, uint32_t k1,
+             const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta) {
+    __shared__ uint32_t sT[kTableSize];
+    __shared__ uint32_t win[10 * kTiledThreads];  // window row o of lane l at win[o * kTiledThreads + l]
+    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = T[k];
+    const int g = (int)blockIdx.x * kTiledThreads + (int)threadIdx.x;
+    const int my_delta = tiled_domain(lat, L, stride, part, t, k0, k1, sT, win, g, g < (L >> 3) * (L >> 3));
+    add_delta(my_delta, delta);
+}
+
+// Replica whose workgroup range holds workgroup b: the last with wave_base <= b.
+__device__ __forceinline__ int replica_of_block(const EnsRep* __restrict__ reps, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reps[mid].wave_base <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One part of sweep q of a chunk for every replica of a tiled ensemble: the
+// workgroups are dealt out replica by replica (wave_base = first workgroup),
+// and each replica updates in place.
+__global__ void __launch_bounds__(kTiledThreads)
+k_ens_tiled_part(const EnsRep* __restrict__ reps, int n_reps, int part, int q) {
+    __shared__ uint32_t sT[kTableSize];
+    __shared__ uint32_t win[10 * kTiledThreads];
+    const int rep_id = __builtin_amdgcn_readfirstlane(replica_of_block(reps, n_reps, (int)blockIdx.x));
+    const EnsRep& rp = reps[rep_id];
+    for (int k = threadIdx.x; k < kTableSize; k += blockDim.x) sT[k] = rp.T[k];
+    const int L = rp.L;
+    const int g = ((int)blockIdx.x - rp.wave_base) * kTiledThreads + (int)threadIdx.x;
+    const bool on = q < rp.n_active && g < (L >> 3) * (L >> 3);
+    const int my_delta = tiled_domain(rp.lat, L, rp.stride, part, rp.t0 + (uint32_t)q, rp.k0, rp.k1, sT, win, g, on);
+    add_delta(my_delta, rp.delta + (size_t)q * kSweepWords);
+}
+
 }  // namespace
+
+int tiled_blocks(int L) {
+    const int n = (L / 8) * (L / 8);
+    return (n + kTiledThreads - 1) / kTiledThreads;
+}
 
 hipError_t launch_tiled_part(uint32_t* lat, int L, int stride, int part, uint32_t t, uint64_t seed,
                              const uint32_t* T, unsigned long long* delta, hipStream_t st) {
     if (L % 8 != 0 || part < 0 || part > 3) return hipErrorInvalidValue;
-    const int n = (L / 8) * (L / 8);
-    const int blocks = (n + kTiledThreads - 1) / kTiledThreads;
+    const int blocks = tiled_blocks(L);
     hipLaunchKernelGGL(k_tiled_part, dim3(blocks), dim3(kTiledThreads), 0, st, lat, L, stride, part, t,
                        (uint32_t)seed, (uint32_t)(seed >> 32), T, delta);
     return hipGetLastError();
+}
+
+hipError_t launch_ens_tiled_chunk(EnsRep* d_reps, int n, int total_blocks, int len, int chunk,
+                                  unsigned long long* counts, hipStream_t st) {
+    hipError_t err = launch_ens_begin(d_reps, n, len, chunk, true, st);
+    for (int q = 0; err == hipSuccess && q < len; ++q)
+        for (int part = 0; err == hipSuccess && part < 4; ++part) {
+            hipLaunchKernelGGL(k_ens_tiled_part, dim3(total_blocks), dim3(kTiledThreads), 0, st, d_reps, n, part, q);
+            err = hipGetLastError();
+        }
+    if (err != hipSuccess) return err;
+    return launch_ens_end(d_reps, n, chunk, counts, st);
 }
 
 }  // namespace pgg

@@ -58,14 +58,15 @@ def sample_on_grid(counts, L: int, grid, nc0: int | None = None) -> np.ndarray:
 
 
 def r_scan(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None = None,
-           chunk: int = 64, stream=None, block: int = 1000):
+           chunk: int = 64, stream=None, block: int = 1000, schedule: str = "colour16"):
     """Stationary density per r: the scan's replicas (one lattice per r, its
-    own seed) advanced together as one ensemble.  Counts are fetched `block`
-    sweeps at a time.  Returns (r values, stationary densities, counts of
-    shape (replicas, sweeps))."""
+    own seed) advanced together as one ensemble (either schedule).  Counts
+    are fetched `block` sweeps at a time.  Returns (r values, stationary
+    densities, counts of shape (replicas, sweeps))."""
     n = int(sweeps if sweeps is not None else cfg["sweeps"])
     last = int(average_last if average_last is not None else min(cfg["average_last"], n))
-    reps = [dict(L=cfg["L"], r=r, K=cfg["K"], p0=cfg["p0"], seed=s) for r, s in zip(cfg["r_values"], cfg["seeds"])]
+    reps = [dict(L=cfg["L"], r=r, K=cfg["K"], p0=cfg["p0"], seed=s, schedule=schedule)
+            for r, s in zip(cfg["r_values"], cfg["seeds"])]
     parts = []
     with pgg.Ensemble(reps, chunk=chunk, stream=stream) as ens:
         done = 0
@@ -81,7 +82,7 @@ def r_scan(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None
 def r_scan_lattices(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None = None,
                     schedule: str = "colour16", workers: int = 4, block: int = 10_000, progress=None):
     """As r_scan, but one lattice per r through pgg_init / pgg_sweep (any
-    schedule, e.g. the double tiling, which the ensemble does not run):
+    schedule):
     `workers` host threads each drive their lattices on a stream of their
     own, so up to that many lattices advance on the device at once.
     progress(r, seed), if given, is called as each lattice finishes.

@@ -115,7 +115,7 @@ def test_engine_has_no_cpu_fallback():
 
 
 @pytest.mark.parametrize("bad", [dict(L=60), dict(L=130), dict(r=-1.0), dict(K=0.0), dict(p0=2.0),
-                                 dict(schedule="tiled")])
+                                 dict(schedule="tiled"), dict(schedule=5)])
 def test_ensemble_calls_reject_invalid_replicas_before_touching_the_device(pgg, bad):
     reps = [dict(L=128, r=3.8, seed=1), dict(L=256, r=3.7, seed=2)]
     reps[1].update(bad)
@@ -126,6 +126,21 @@ def test_ensemble_calls_reject_invalid_replicas_before_touching_the_device(pgg, 
         pgg.ensemble_autotune(reps)
     assert e.value.status == pgg.PGG_E_INVAL
     assert "replica 1" in pgg.load().pgg_last_error().decode()
+
+
+def test_tiled_ensemble_rules(pgg):
+    # every replica one schedule; L % 8 == 0 for the tiled one; nothing to autotune
+    for reps in ([dict(L=128, r=3.8, seed=1, schedule="tiled"), dict(L=132, r=3.8, seed=2, schedule="tiled")],
+                 [dict(L=128, r=3.8, seed=1, schedule="tiled"), dict(L=128, r=3.8, seed=2)]):
+        with pytest.raises(pgg.PggError) as e:
+            pgg.Ensemble(reps)
+        assert e.value.status == pgg.PGG_E_INVAL and "replica 1" in pgg.load().pgg_last_error().decode()
+    with pytest.raises(pgg.PggError) as e:
+        pgg.ensemble_autotune([dict(L=128, r=3.8, seed=1, schedule="tiled")])
+    assert e.value.status == pgg.PGG_E_INVAL
+    with pytest.raises(pgg.PggError) as e:
+        pgg.Ensemble([dict(L=128, r=3.8, seed=1, schedule="tiled")], tiles=[64])
+    assert e.value.status == pgg.PGG_E_INVAL
 
 
 def test_ensemble_autotune_rejects_bad_arguments(pgg):

@@ -235,3 +235,30 @@ def _oracle_tiled(args):
     import oracle
     L, r, seed, n = args
     return oracle.run_tiled(L, r, 0.5, 0.5, seed, n)[2]
+
+
+def test_tiled_ensemble_equals_oracle_c(pgg, oracle_lib):
+    """Replicas of uneven L (multiples of 8, some not of 32), r and seed with
+    the double-tiling schedule as one ensemble: every replica's counts after
+    each of 30 steps (chunks of 8: graph replays and a short tail) and its
+    final lattice equal oracle C's, and a second call continues them."""
+    from concurrent.futures import ProcessPoolExecutor
+    reps = [dict(L=64, r=3.80, seed=3, schedule="tiled"), dict(L=96, r=4.40, seed=4, schedule="tiled"),
+            dict(L=136, r=3.75, seed=5, schedule="tiled"), dict(L=256, r=3.98, seed=6, schedule="tiled"),
+            dict(L=520, r=3.745, seed=7, schedule="tiled")]
+    n1, n2 = 30, 5
+    with ProcessPoolExecutor(max_workers=5) as ex:
+        refs = list(ex.map(_oracle_tiled_run, [(rp["L"], rp["r"], rp["seed"], n1 + n2) for rp in reps]))
+    say("tiled ensemble of", len(reps))
+    with pgg.Ensemble(reps, chunk=8) as ens:
+        c = np.concatenate([ens.sweep(n1), ens.sweep(n2)], axis=1)
+        for k, (lat, counts) in enumerate(refs):
+            assert np.array_equal(c[k], counts), k
+            assert np.array_equal(ens.read_lattice(k), lat), k
+
+
+def _oracle_tiled_run(args):
+    import oracle
+    L, r, seed, n = args
+    lat, _, counts = oracle.run_tiled(L, r, 0.5, 0.5, seed, n)
+    return lat, counts

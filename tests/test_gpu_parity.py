@@ -612,3 +612,22 @@ def test_tiled_int8_layout_against_oracle(pgg, oracle_lib, L):
         sim.write_lattice(lat, 30)
         assert np.array_equal(sim.sweep(5), counts2)
         assert np.array_equal(sim.read_lattice(), ref2)
+
+
+def test_tiled_maximum_size_count_is_a_recount(pgg):
+    """L = 32768 (the largest accepted; 16.8 M domains per type): two tiled
+    steps in a caller buffer; the running count equals a popcount of the
+    device lattice, and the lattice changed."""
+    import torch
+    L, r, seed = 32768, 3.98, 9
+    params = pgg.make_params(L, r, 0.5, 0.5, seed, "bits", schedule="tiled")
+    buf = torch.empty(pgg.pgg_device_bytes(params), dtype=torch.uint8, device="cuda")
+    say("tiled L=32768")
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", dev_buf=buf, schedule="tiled") as sim:
+        nc0 = sim.coop_count()
+        before = buf.clone()
+        c = sim.sweep(2)
+    torch.cuda.synchronize()
+    pop = int(np.bitwise_count(buf.cpu().numpy()).sum(dtype=np.uint64))
+    assert pop == int(c[-1])
+    assert not torch.equal(before, buf) and int(c[-1]) != nc0
