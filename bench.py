@@ -333,6 +333,34 @@ def cpu_baseline(L, r, seed, n_sweeps):
                       "(16-colour oracle, single thread, %.1f s)" % (n_sweeps, L, r, dt)}
 
 
+def _oracle_replica(args):
+    import oracle
+    L, r, seed, n = args
+    s, _ = oracle.init(L, 0.5, seed)
+    oracle.sweep(s, r, wl.K_PAPER, seed, 0, n)
+    return L * L * n
+
+
+def cpu_ensemble_baseline(n_sweeps=3, max_procs=16):
+    """Ensemble context: the oracle on the host's cores, one replica of the
+    batched ensemble's L = 1024 size per process (a bounded sample), as an
+    aggregate replica-site update rate."""
+    from concurrent.futures import ProcessPoolExecutor
+    import oracle
+    oracle.build(force=False)
+    procs = max(1, min(max_procs, os.cpu_count() or 1))
+    reps = [rp for rp in wl.ensemble_replicas() if rp["L"] == 1024][:procs]
+    args = [(rp["L"], rp["r"], rp["seed"], n_sweeps) for rp in reps]
+    with ProcessPoolExecutor(max_workers=procs) as ex:
+        list(ex.map(_oracle_replica, [(64, 3.8, 1, 1)] * procs))  # start the workers untimed
+        t0 = time.perf_counter()
+        total = sum(ex.map(_oracle_replica, args))
+        dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "replica-site updates/s", "cores": procs, "kind": "oracle",
+            "sample": "%d L=1024 replicas of the batched ensemble, %d sweep(s) each, one process per core "
+                      "(%.1f s)" % (len(args), n_sweeps, dt)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +518,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, %d sweep(s) at L=%d" % (args.cpu_sweeps, L))
         cpu = cpu_baseline(L, r, seed, args.cpu_sweeps)
+        if batched is not None:
+            log("cpu ensemble baseline: oracle on the host cores")
+            batched["cpu_baseline_all_cores"] = cpu_ensemble_baseline()
 
     line = {
         "metric": METRIC, "value": value, "unit": "site updates/s", "n_gpus": 1,
