@@ -112,7 +112,10 @@ def main(argv=None):
           % (n_r, args.r_min, args.r_max, args.L, args.sweeps, last), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     if not args.per_lattice:
-        r, rho, counts = ob.r_scan(pgg, cfg, block=10_000, schedule=args.schedule)
+        def block_done(done):
+            print("%d of %d sweeps, %.0f s" % (done, args.sweeps, time.perf_counter() - t0), file=sys.stderr, flush=True)
+
+        r, rho, counts = ob.r_scan(pgg, cfg, block=10_000, schedule=args.schedule, progress=block_done)
     else:
         def progress(r_done, seed_done):
             print("lattice r = %g (seed %d) done, %.0f s" % (r_done, seed_done, time.perf_counter() - t0),

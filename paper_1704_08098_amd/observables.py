@@ -58,11 +58,12 @@ def sample_on_grid(counts, L: int, grid, nc0: int | None = None) -> np.ndarray:
 
 
 def r_scan(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None = None,
-           chunk: int = 64, stream=None, block: int = 1000, schedule: str = "colour16"):
+           chunk: int = 64, stream=None, block: int = 1000, schedule: str = "colour16", progress=None):
     """Stationary density per r: the scan's replicas (one lattice per r, its
     own seed) advanced together as one ensemble (either schedule).  Counts
-    are fetched `block` sweeps at a time.  Returns (r values, stationary
-    densities, counts of shape (replicas, sweeps))."""
+    are fetched `block` sweeps at a time; progress(sweeps done), if given,
+    is called after each block.  Returns (r values, stationary densities,
+    counts of shape (replicas, sweeps))."""
     n = int(sweeps if sweeps is not None else cfg["sweeps"])
     last = int(average_last if average_last is not None else min(cfg["average_last"], n))
     reps = [dict(L=cfg["L"], r=r, K=cfg["K"], p0=cfg["p0"], seed=s, schedule=schedule)
@@ -74,6 +75,8 @@ def r_scan(pgg, cfg=wl.SCAN, sweeps: int | None = None, average_last: int | None
             m = min(block, n - done)
             parts.append(ens.sweep(m))
             done += m
+            if progress is not None:
+                progress(done)
     counts = np.concatenate(parts, axis=1)
     rho = np.array([stationary_density(counts[k], cfg["L"], last) for k in range(len(reps))])
     return np.array(cfg["r_values"], dtype=np.float64), rho, counts
