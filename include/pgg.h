@@ -37,7 +37,11 @@
  *   - A HIP error returns PGG_E_DEVICE and poisons the handle: every later
  *     call on it except pgg_destroy returns PGG_E_STATE.
  *   - A handle is not thread-safe; distinct handles may be used from distinct
- *     threads.  Work is ordered on the handle's HIP stream.
+ *     threads at once.  Work is ordered on the handle's HIP stream.  Graphs
+ *     are captured in thread-local mode on a non-blocking stream (the
+ *     handle's own, or the caller's); a caller stream given to an ensemble or
+ *     server that captures graphs should be non-blocking, or another thread's
+ *     work on the null stream may fail the capture.
  *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
  *     pointers are HIP device memory on the current device.
  */
@@ -71,7 +75,8 @@ typedef enum {
 typedef enum {
     PGG_KERNEL_AUTO = 0,    /* SEGMENT_PAIR when its workgroups all fit the
                                device at once with one or two per CU (L = 4096
-                               on 256 CUs) and group is 0, else SEGMENT for
+                               on 256 CUs) and group is 0; RESIDENT for L = 64,
+                               96 and 128 with group 0; else SEGMENT for
                                L >= 64; below L = 64, COLOUR (int8) or
                                ROWBAND_COMPACT (bits)                            */
     PGG_KERNEL_COLOUR = 1,  /* int8 only: one launch per colour class, global
@@ -124,7 +129,20 @@ typedef enum {
                                runs residue a + 1 on its rows.  tile: segment
                                width, a multiple of 32 up to L - 64 (0 =
                                automatic); group must be 0.  int8 layout: as
-                               for SEGMENT, through a bit-packed working copy */
+                               for SEGMENT, through a bit-packed working copy */,
+    PGG_KERNEL_RESIDENT = 8 /* L a multiple of 32, 64 <= L <= 256: one
+                               workgroup of 16 waves keeps the whole lattice in
+                               LDS (with 3 periodic halo rows above and below)
+                               and runs every sweep of a pgg_sweep call chunk
+                               (up to 4096 sweeps) in one launch: per row
+                               residue the waves update its rows with the
+                               whole-row update of SEGMENT, then a workgroup
+                               barrier and a halo refresh.  One CU does the
+                               work, so lattices on other streams can run
+                               beside it.  tile and group must be 0.  int8
+                               layout: through a bit-packed working copy, as
+                               for the tiled schedule.  Timing mode times
+                               one launch per chunk                             */
 } pgg_kernel;
 
 /* The update schedule: which dynamics a Monte Carlo step runs.  Unlike the

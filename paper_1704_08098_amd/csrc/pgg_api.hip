@@ -27,6 +27,10 @@ void set_err(const char* fmt, ...) {
 constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 constexpr int kGraphChunk = 64;    // sweeps per graph replay (segment kernel)
 constexpr int kKernelTiled = 100;  // internal kernel id of the tiled schedule (not a pgg_kernel value)
+// Largest L for which AUTO takes the resident kernel: a sweep costs it about
+// 29 us at L = 64 and 128 against 35 us for the whole-row segment kernel's
+// four launches, but 43 us at L = 256.
+constexpr uint32_t kResidentAutoMaxL = 128;
 
 }  // namespace
 
@@ -46,7 +50,7 @@ struct pgg_sim {
     void* lattice = nullptr;
     bool owns_lattice = false;
     uint32_t* lattice2 = nullptr;  // segment kernel: odd sweeps of a call land here
-    uint32_t* shadow = nullptr;    // int8 layout on the segment kernels: bit-packed working lattice
+    uint32_t* shadow = nullptr;    // int8 layout on the segment, resident and tiled paths: bit-packed working lattice
     // Segment kernel: run as a one-replica ensemble.  d_rep[0] serves the
     // captured chunks (one graph per chunk length), d_rep[1] the eager
     // launches of timing mode (it also counts draws); sweep indices live in
@@ -219,6 +223,10 @@ bool params_valid(const pgg_params* p, const char** why) {
             }
             break;
         }
+        case PGG_KERNEL_RESIDENT:
+            if (!pgg::resident_fits((int)p->L)) { *why = "the resident kernel needs L a multiple of 32 in [64, 256]"; return false; }
+            if (tr != 0 || p->group != 0) { *why = "the resident kernel takes tile 0 and group 0"; return false; }
+            break;
         case PGG_KERNEL_STRIP:
             if (p->layout != PGG_LAYOUT_BITS) { *why = "the strip kernel needs the bits layout"; return false; }
             if (tr != 0 && (tr < 4 || tr > p->L)) { *why = "strip tile must lie in [4, L]"; return false; }
@@ -387,8 +395,9 @@ pgg_status plan_strips(pgg_sim* s, uint32_t tile) {
         set_err("hipMalloc failed: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
     }
-    e = hipMemcpy(s->d_tasks, tasks.data(), S * sizeof(pgg::StripTask), hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(s->d_tasks, tasks.data(), S * sizeof(pgg::StripTask), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = pgg::launch_fill_u32(s->d_abort, 1, 0u, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) { set_err("strip plan upload failed: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
     return PGG_OK;
 }
@@ -403,7 +412,8 @@ pgg_status plan_segment_graph(pgg_sim* s) {
     hipError_t e = hipMalloc((void**)&s->d_rep, 2 * sizeof(pgg::EnsRep));
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_gdelta, (size_t)kGraphChunk * pgg::kSweepWords * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_gcounts, (size_t)kGraphChunk * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipStreamCreate(&s->capture_stream);
+    // non-blocking: a legacy-stream call of another thread never depends on a capture in progress
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         set_err("segment graph buffers: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
@@ -424,7 +434,8 @@ pgg_status plan_segment_graph(pgg_sim* s) {
         s->launches_per_sweep = 4;
     }
     const pgg::EnsRep both[2] = {rp, rp};
-    e = hipMemcpy(s->d_rep, both, sizeof(both), hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(s->d_rep, both, sizeof(both), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) { set_err("segment graph descriptor: %s", hipGetErrorString(e)); return PGG_E_DEVICE; }
     return PGG_OK;
 }
@@ -536,7 +547,8 @@ pgg_status sweep_segment(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
 pgg_status check_abort(pgg_sim* s) {
     if (!s->d_abort) return PGG_OK;
     uint32_t v = 0;
-    hipError_t e = hipMemcpy(&v, s->d_abort, sizeof(v), hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpyAsync(&v, s->d_abort, sizeof(v), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return device_fail(s, e, "abort flag read");
     if (v) {
         set_err("a persistent strip launch aborted: a workgroup waited too long for its neighbours");
@@ -590,6 +602,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
         s->kernel = (int)p->kernel;
     else if (p->L < 64)
         s->kernel = p->layout == PGG_LAYOUT_INT8 ? PGG_KERNEL_COLOUR : PGG_KERNEL_ROWBAND_COMPACT;
+    else if (p->L <= kResidentAutoMaxL && pgg::resident_fits((int)p->L) && p->group == 0)
+        s->kernel = PGG_KERNEL_RESIDENT;
     else
         s->kernel = pair_fits(p, s->device) ? PGG_KERNEL_SEGMENT_PAIR : PGG_KERNEL_SEGMENT;
     s->wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
@@ -622,7 +636,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
     pgg_params bits = *p;
     bits.layout = PGG_LAYOUT_BITS;
-    const bool packed_copy = (segment_path || s->kernel == kKernelTiled) && p->layout == PGG_LAYOUT_INT8;
+    const bool packed_copy =
+        (segment_path || s->kernel == kKernelTiled || s->kernel == PGG_KERNEL_RESIDENT) && p->layout == PGG_LAYOUT_INT8;
     if (st == PGG_OK && packed_copy) st = alloc((void**)&s->shadow, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = alloc((void**)&s->lattice2, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = plan_segment_graph(s);
@@ -653,9 +668,10 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     if (s->kernel == PGG_KERNEL_SEGMENT || s->kernel == PGG_KERNEL_SEGMENT_PAIR)
         return sweep_segment(s, n_sweeps, coop_counts);
     const int L = (int)s->p.L;
-    // the tiled schedule on the int8 layout sweeps a bit-packed working copy
+    // the tiled schedule and the resident kernel sweep a bit-packed working
+    // copy of an int8 lattice
     uint32_t* tiled_lat = s->shadow ? s->shadow : (uint32_t*)s->lattice;
-    if (s->kernel == kKernelTiled && s->shadow)
+    if (s->shadow)
         PGG_HIP(s, pgg::launch_pack((const uint8_t*)s->lattice, s->shadow, L, s->stride, s->stream));
     uint32_t done = 0;
     while (done < n_sweeps) {
@@ -672,7 +688,15 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
                                          s->strip_G, s->strip_lds, s->stream);
             }));
         }
-        for (uint32_t q = 0; s->kernel != PGG_KERNEL_STRIP && q < n; ++q) {
+        if (s->kernel == PGG_KERNEL_RESIDENT) {
+            const uint32_t t0 = (uint32_t)(s->t + done);
+            PGG_HIP(s, timed_launch(s, [&] {
+                return pgg::launch_resident(tiled_lat, L, s->stride, t0, (int)n, s->p.seed, s->d_table, s->d_delta,
+                                            s->timing ? s->d_drawn : nullptr, s->stream);
+            }));
+        }
+        const bool per_sweep = s->kernel != PGG_KERNEL_STRIP && s->kernel != PGG_KERNEL_RESIDENT;
+        for (uint32_t q = 0; per_sweep && q < n; ++q) {
             const uint32_t t = (uint32_t)(s->t + done + q);
             unsigned long long* dq = s->d_delta + (size_t)q * pgg::kSweepWords;
             if (s->kernel == kKernelTiled) {
@@ -715,7 +739,7 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         }
         done += n;
     }
-    if (s->kernel == kKernelTiled && s->shadow)
+    if (s->shadow)
         PGG_HIP(s, pgg::launch_unpack(s->shadow, (uint8_t*)s->lattice, L, s->stride, s->stream));
     s->t += n_sweeps;
     return PGG_OK;

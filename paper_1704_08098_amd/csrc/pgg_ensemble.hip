@@ -543,7 +543,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     if (!e) { eerr("host allocation failed"); return PGG_E_NOMEM; }
     e->stream = (hipStream_t)hip_stream;
     if (!e->stream) {
-        if (hipStreamCreate(&e->stream) != hipSuccess) { eerr("stream creation failed"); delete e; return PGG_E_DEVICE; }
+        if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) { eerr("stream creation failed"); delete e; return PGG_E_DEVICE; }
         e->own_stream = true;
     }
     e->n = (int)n_reps;
@@ -608,8 +608,11 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     for (uint32_t k = 0; k < n_reps; ++k) { rK[2 * k] = reps[k].r; rK[2 * k + 1] = reps[k].K; }
     double* d_rK = nullptr;
     hipError_t err = hipMalloc((void**)&d_rK, rK.size() * sizeof(double));
-    if (err == hipSuccess) err = hipMemcpy(e->d_reps, e->host_reps.data(), n_reps * sizeof(pgg::EnsRep), hipMemcpyHostToDevice);
-    if (err == hipSuccess) err = hipMemcpy(d_rK, rK.data(), rK.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->d_reps, e->host_reps.data(), n_reps * sizeof(pgg::EnsRep), hipMemcpyHostToDevice,
+                             e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(d_rK, rK.data(), rK.size() * sizeof(double), hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess) {
         hipLaunchKernelGGL(pgg::k_ens_tables, dim3(n_reps), dim3(192), 0, e->stream, e->d_reps, d_rK);
         err = hipGetLastError();

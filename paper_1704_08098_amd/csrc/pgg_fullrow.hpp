@@ -58,16 +58,17 @@ __device__ __forceinline__ void fullrow_fill(const uint32_t* __restrict__ cur, c
 }
 
 // The four classes on the nrows (<= R) owned rows, then the rows written to
-// next.  Adds the net change of the cooperator count to my_delta (every
-// lane) and the number of draws to my_drawn (per lane; the caller sums over
-// the wave).
+// next (next == nullptr: no write-back, the rows stay in LDS).  Adds the net
+// change of the cooperator count to my_delta (every lane) and the number of
+// draws to my_drawn (per lane; the caller sums over the wave).  list: the
+// class list (R L / 4 + 8 words), or nullptr for the words after the window.
 __device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, int stride, int a, int i0, int R,
                                             int nrows, uint32_t t, uint32_t k0, uint32_t k1,
                                             const uint32_t* __restrict__ sT, uint32_t* __restrict__ win,
-                                            int& my_delta, int& my_drawn) {
+                                            int& my_delta, int& my_drawn, uint32_t* __restrict__ list_in = nullptr) {
     const int lane = threadIdx.x & 63;
     const int nw = L >> 5, ldw = nw + 2;
-    uint32_t* list = win + (4 * R + 3) * ldw;
+    uint32_t* list = list_in ? list_in : win + (4 * R + 3) * ldw;
     uint32_t* row0 = win + 3 * ldw + 1;  // word 0 of owned row 0; owned row r starts 4 ldw later per r
     const int nwords = nrows * nw;
     const uint32_t k_first = (uint32_t)(4 * a);
@@ -142,6 +143,7 @@ __device__ __forceinline__ void fullrow_run(uint32_t* __restrict__ next, int L, 
         __builtin_amdgcn_wave_barrier();
     }
     // Write back the owned rows.
+    if (!next) return;
     for (int q = lane; q < nwords; q += 64) {
         const int r = q / nw, w = q - r * nw;
         next[(size_t)(i0 + 4 * r) * stride + w] = row0[4 * r * ldw + w];

@@ -222,7 +222,7 @@ pgg_status pgg_server_create(size_t hbm_budget, uint32_t max_L, uint32_t max_res
     s->stream = (hipStream_t)hip_stream;
     hipError_t e = hipSuccess;
     if (!s->stream) {
-        e = hipStreamCreate(&s->stream);
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
         s->own_stream = (e == hipSuccess);
     }
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_arena, s->budget);

@@ -21,13 +21,14 @@ LIB_PATH = os.path.join(_PKG, "libpgg.so")
 PGG_OK, PGG_E_INVAL, PGG_E_NOMEM, PGG_E_DEVICE, PGG_E_STATE = 0, -1, -2, -3, -4
 LAYOUT_INT8, LAYOUT_BITS = 0, 1
 KERNEL_AUTO, KERNEL_COLOUR, KERNEL_ROWBAND, KERNEL_ROWBAND_COMPACT, KERNEL_ROWBAND_STAGED = 0, 1, 2, 3, 4
-KERNEL_STRIP, KERNEL_SEGMENT, KERNEL_SEGMENT_PAIR = 5, 6, 7
+KERNEL_STRIP, KERNEL_SEGMENT, KERNEL_SEGMENT_PAIR, KERNEL_RESIDENT = 5, 6, 7, 8
 SCHEDULE_COLOUR16, SCHEDULE_TILED = 0, 1
 LAYOUTS = {"int8": LAYOUT_INT8, "bits": LAYOUT_BITS}
 SCHEDULES = {"colour16": SCHEDULE_COLOUR16, "tiled": SCHEDULE_TILED}
 KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBAND,
            "rowband_compact": KERNEL_ROWBAND_COMPACT, "rowband_staged": KERNEL_ROWBAND_STAGED,
-           "strip": KERNEL_STRIP, "segment": KERNEL_SEGMENT, "segment_pair": KERNEL_SEGMENT_PAIR}
+           "strip": KERNEL_STRIP, "segment": KERNEL_SEGMENT, "segment_pair": KERNEL_SEGMENT_PAIR,
+           "resident": KERNEL_RESIDENT}
 
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",

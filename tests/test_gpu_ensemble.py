@@ -231,6 +231,30 @@ def test_r_scan_lattices_tiled_matches_oracle_c(pgg, oracle_lib):
         assert np.array_equal(counts[k], ref_counts), k
 
 
+def test_r_scan_lattices_colour16_threads_match_oracle(pgg, oracle_lib):
+    """observables.r_scan_lattices with the 16-colour sweep: eight host threads
+    create, capture (segment-kernel graphs) and sweep lattices at once, each
+    on a stream of its own; every lattice's counts equal the oracle's."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1704_08098_amd import observables as ob
+    cfg = dict(wl.SCAN, L=160, sweeps=300, average_last=100,
+               r_values=(3.70, 3.72, 3.74, 3.76, 3.78, 3.80, 3.9, 4.1, 4.4, 5.0),
+               seeds=(21, 22, 23, 24, 25, 26, 27, 28, 29, 30))
+    args = [(cfg["L"], r, s, cfg["sweeps"]) for r, s in zip(cfg["r_values"], cfg["seeds"])]
+    with ProcessPoolExecutor(max_workers=5) as ex:
+        refs = list(ex.map(_oracle_colour16, args))
+    say("r_scan_lattices colour16, 8 threads, L", cfg["L"])
+    r, rho, counts = ob.r_scan_lattices(pgg, cfg, schedule="colour16", workers=8, block=40)
+    for k, ref_counts in enumerate(refs):
+        assert np.array_equal(counts[k], ref_counts), k
+
+
+def _oracle_colour16(args):
+    import oracle
+    L, r, seed, n = args
+    return oracle.run(L, r, 0.5, 0.5, seed, n)[2]
+
+
 def _oracle_tiled(args):
     import oracle
     L, r, seed, n = args

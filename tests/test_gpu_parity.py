@@ -450,14 +450,16 @@ def test_segment_pair_against_oracle(pgg, oracle_lib, L, tile):
         assert launches == 6 and sim.kernel_span()[0] == 6
 
 
-def test_long_trajectory_whole_rows(pgg, oracle_lib):
-    """L = 128 (whole rows, 8 per wave) through 3000 sweeps near the
-    transition: the count after every sweep and the final lattice equal the
-    oracle's (the domains coarsen, so late sweeps exercise sparse activity)."""
+@pytest.mark.parametrize("kernel", ["segment", "resident", "auto"])
+def test_long_trajectory_whole_rows(pgg, oracle_lib, kernel):
+    """L = 128 (segment: whole rows, 8 per wave; resident: the lattice in one
+    workgroup's LDS) through 3000 sweeps near the transition: the count after
+    every sweep and the final lattice equal the oracle's (the domains coarsen,
+    so late sweeps exercise sparse activity)."""
     L, r, seed, n = 128, 3.9, 4242, 3000
     ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
-    say("long trajectory L=128", n)
-    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", "auto") as sim:
+    say("long trajectory L=128", kernel, n)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", kernel) as sim:
         got = np.concatenate([sim.sweep(1000), sim.sweep(1), sim.sweep(1999)])
         assert np.array_equal(got, counts)
         assert np.array_equal(sim.read_lattice(), ref)
