@@ -370,8 +370,8 @@ def main():
     ap.add_argument("--r", type=float, default=wl.R_CRITICAL)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel", default="segment_pair",
-                    choices=["segment", "segment_pair", "strip", "rowband_staged", "rowband_compact", "rowband",
-                             "colour", "tiled"],
+                    choices=["segment", "segment_pair", "resident", "strip", "rowband_staged", "rowband_compact",
+                             "rowband", "colour", "tiled"],
                     help="sweep kernel of the 16-colour schedule, or 'tiled': the double-tiling schedule of "
                          "Sec. IV (a different dynamics)")
     ap.add_argument("--layout", default="auto", choices=["auto", "int8", "bits"],
@@ -466,7 +466,7 @@ def main():
                 "kernel": {"segment": "k_ens_segment", "segment_pair": "k_ens_pair", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
                            "rowband_compact": "k_rowband_bits<true>",
                            "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8",
-                           "tiled": "k_tiled_part"}[args.kernel],
+                           "tiled": "k_tiled_part", "resident": "k_resident"}[args.kernel],
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,
                 "avg_launch_source": "HIP events around the timed region on the sweep stream / launches",
                 "timing_pass_event_us_per_launch": kms / max(launches, 1) * 1e3,
@@ -475,8 +475,8 @@ def main():
                 "slots_per_drawn_update": SLOTS_PER_DRAWN_UPDATE,
                 "slots_per_site_scan": SLOTS_PER_SITE_SCAN}
     kernel_rate = sites_per_launch / (avg_ms * 1e-3)
-    # the segment kernels sweep a bit-packed lattice whatever the layout
-    hbm_bytes = BYTES_PER_UPDATE["bits" if args.kernel in ("segment", "segment_pair") else layout]
+    # the segment and resident kernels sweep a bit-packed lattice whatever the layout
+    hbm_bytes = BYTES_PER_UPDATE["bits" if args.kernel in ("segment", "segment_pair", "resident") else layout]
     hbm = {"bytes_per_update": hbm_bytes, "achieved_GBs": value * hbm_bytes / 1e9,
            "peak_GBs": HBM_PEAK_GBS, "frac": value * hbm_bytes / 1e9 / HBM_PEAK_GBS,
            "frac_int8_equivalent": value * 2.0 / 1e9 / HBM_PEAK_GBS,

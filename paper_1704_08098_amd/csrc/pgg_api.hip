@@ -27,9 +27,10 @@ void set_err(const char* fmt, ...) {
 constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 constexpr int kGraphChunk = 64;    // sweeps per graph replay (segment kernel)
 constexpr int kKernelTiled = 100;  // internal kernel id of the tiled schedule (not a pgg_kernel value)
-// Largest L for which AUTO takes the resident kernel: a sweep costs it about
-// 29 us at L = 64 and 128 against 35 us for the whole-row segment kernel's
-// four launches, but 43 us at L = 256.
+// Largest L for which AUTO takes the resident kernel: a sweep costs it 27-29 us
+// at L = 64 and 128 against 31-35 us for the whole-row segment kernel's four
+// launches; at L = 256 it is 32-43 us against 33-35 us, depending on how many
+// sites are active.
 constexpr uint32_t kResidentAutoMaxL = 128;
 
 }  // namespace
