@@ -131,7 +131,8 @@ typedef enum {
                                automatic); group must be 0.  int8 layout: as
                                for SEGMENT, through a bit-packed working copy */,
     PGG_KERNEL_RESIDENT = 8 /* L a multiple of 32, 64 <= L <= 256: one
-                               workgroup of 16 waves keeps the whole lattice in
+                               workgroup of `group` waves (4, 8 or 16; 0 =
+                               automatic) keeps the whole lattice in
                                LDS (with 3 periodic halo rows above and below)
                                and runs every sweep of a pgg_sweep call chunk
                                (up to 4096 sweeps) in one launch: per row
@@ -139,7 +140,7 @@ typedef enum {
                                whole-row update of SEGMENT, then a workgroup
                                barrier and a halo refresh.  One CU does the
                                work, so lattices on other streams can run
-                               beside it.  tile and group must be 0.  int8
+                               beside it.  tile must be 0.  int8
                                layout: through a bit-packed working copy, as
                                for the tiled schedule.  Timing mode times
                                one launch per chunk                             */

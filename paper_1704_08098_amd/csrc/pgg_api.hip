@@ -27,10 +27,10 @@ void set_err(const char* fmt, ...) {
 constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 constexpr int kGraphChunk = 64;    // sweeps per graph replay (segment kernel)
 constexpr int kKernelTiled = 100;  // internal kernel id of the tiled schedule (not a pgg_kernel value)
-// Largest L for which AUTO takes the resident kernel: a sweep costs it 27-29 us
-// at L = 64 and 128 against 31-35 us for the whole-row segment kernel's four
-// launches; at L = 256 it is 32-43 us against 33-35 us, depending on how many
-// sites are active.
+// Largest L for which AUTO takes the resident kernel: a sweep costs it 16-17 us
+// at L = 64 and 19-22 us at L = 128 against 31-35 us for the whole-row segment
+// kernel's four launches; at L = 256 it is 30-45 us against 33-36 us,
+// depending on how many sites are active.
 constexpr uint32_t kResidentAutoMaxL = 128;
 
 }  // namespace
@@ -182,7 +182,10 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (p->schedule != PGG_SCHEDULE_COLOUR16) { *why = "unknown schedule"; return false; }
     const uint32_t tr = p->tile;
     const bool segment = p->kernel == PGG_KERNEL_SEGMENT || (p->kernel == PGG_KERNEL_AUTO && p->L >= 64);
-    if (p->group != 0 && !segment) { *why = "group applies to the segment kernel only"; return false; }
+    if (p->group != 0 && !segment && p->kernel != PGG_KERNEL_RESIDENT) {
+        *why = "group applies to the segment and resident kernels only";
+        return false;
+    }
     switch (p->kernel) {
         case PGG_KERNEL_AUTO:
             if (tr != 0) { *why = "tile needs an explicit kernel"; return false; }
@@ -226,7 +229,11 @@ bool params_valid(const pgg_params* p, const char** why) {
         }
         case PGG_KERNEL_RESIDENT:
             if (!pgg::resident_fits((int)p->L)) { *why = "the resident kernel needs L a multiple of 32 in [64, 256]"; return false; }
-            if (tr != 0 || p->group != 0) { *why = "the resident kernel takes tile 0 and group 0"; return false; }
+            if (tr != 0) { *why = "the resident kernel takes tile 0"; return false; }
+            if (p->group != 0 && !pgg::resident_waves_valid((int)p->group)) {
+                *why = "the resident kernel's group (waves) must be 0, 4, 8 or 16";
+                return false;
+            }
             break;
         case PGG_KERNEL_STRIP:
             if (p->layout != PGG_LAYOUT_BITS) { *why = "the strip kernel needs the bits layout"; return false; }
@@ -691,9 +698,10 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         }
         if (s->kernel == PGG_KERNEL_RESIDENT) {
             const uint32_t t0 = (uint32_t)(s->t + done);
+            const int W = s->p.group ? (int)s->p.group : pgg::resident_auto_waves(L);
             PGG_HIP(s, timed_launch(s, [&] {
-                return pgg::launch_resident(tiled_lat, L, s->stride, t0, (int)n, s->p.seed, s->d_table, s->d_delta,
-                                            s->timing ? s->d_drawn : nullptr, s->stream);
+                return pgg::launch_resident(tiled_lat, L, s->stride, W, t0, (int)n, s->p.seed, s->d_table,
+                                            s->d_delta, s->timing ? s->d_drawn : nullptr, s->stream);
             }));
         }
         const bool per_sweep = s->kernel != PGG_KERNEL_STRIP && s->kernel != PGG_KERNEL_RESIDENT;

@@ -56,13 +56,15 @@ hipError_t launch_tiled_part(uint32_t* lat, int L, int stride, int part, uint32_
                              const uint32_t* T, unsigned long long* delta, hipStream_t st);
 // Workgroups of one tiled launch for side L.
 int tiled_blocks(int L);
-// Resident sweep (pgg_resident.hip): one workgroup holds the lattice in LDS
-// and runs n sweeps from sweep index t0; delta[q] (kSweepWords each) receives
-// sweep t0 + q.  L a multiple of 32, 64 <= L <= 256.
+// Resident sweep (pgg_resident.hip): one workgroup of W waves (4, 8 or 16)
+// holds the lattice in LDS and runs n sweeps from sweep index t0; delta[q]
+// (kSweepWords each) receives sweep t0 + q.  L a multiple of 32, 64 <= L <= 256.
 bool resident_fits(int L);
-size_t resident_lds_bytes(int L);
-hipError_t launch_resident(uint32_t* lat, int L, int stride, uint32_t t0, int n, uint64_t seed, const uint32_t* T,
-                           unsigned long long* delta, unsigned long long* drawn, hipStream_t st);
+bool resident_waves_valid(int W);
+int resident_auto_waves(int L);
+size_t resident_lds_bytes(int L, int W);
+hipError_t launch_resident(uint32_t* lat, int L, int stride, int W, uint32_t t0, int n, uint64_t seed,
+                           const uint32_t* T, unsigned long long* delta, unsigned long long* drawn, hipStream_t st);
 constexpr size_t kMaxDynamicLds = 64 * 1024;
 
 // Persistent strip kernel (pgg_strip.hip).  One task per workgroup: rows

@@ -7,13 +7,16 @@
 // in LDS with three halo rows above and below (copies of the rows across the
 // periodic wrap) and one pad word on each side of every row (the word
 // across the wrap), so every stencil reads plain LDS offsets.  Per residue a
-// the 16 waves split the L/4 rows of residue a and run the whole-row update
+// the W waves (4, 8 or 16) split the L/4 rows of residue a and run the whole-row update
 // of pgg_fullrow.hpp on them (classes 4a..4a+3, lists, flips in place --
 // rows of one residue never read each other); a workgroup barrier, the halo
 // rows refreshed from the rows they copy, another barrier, the next residue.
 // After the last sweep the rows are written back.  For L a multiple of 32,
-// 64 <= L <= 256 (the lattice and 16 wave lists fit the LDS); one CU does the
+// 64 <= L <= 256 (the lattice and the wave lists fit the LDS); one CU does the
 // work, so other lattices on other streams can use the rest of the device.
+// Few waves with many rows each beat many sparse ones: a wave's class pass
+// issues about the same instructions whether 8 or 64 of its lanes hold sites,
+// and the CU's VALU issue is what bounds the sweep.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,12 +29,11 @@ namespace pgg {
 
 namespace {
 
-constexpr int kResidentWaves = 16;
+__host__ __device__ inline int resident_rows_per_wave(int L, int W) { return (L / 4 + W - 1) / W; }
+__host__ __device__ inline int resident_list_words(int L, int W) { return resident_rows_per_wave(L, W) * (L / 4) + 8; }
 
-__host__ __device__ inline int resident_rows_per_wave(int L) { return (L / 4 + kResidentWaves - 1) / kResidentWaves; }
-__host__ __device__ inline int resident_list_words(int L) { return resident_rows_per_wave(L) * (L / 4) + 8; }
-
-__global__ void __launch_bounds__(64 * kResidentWaves)
+template <int W>
+__global__ void __launch_bounds__(64 * W)
 k_resident(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n, uint32_t k0, uint32_t k1,
            const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta,
            unsigned long long* __restrict__ drawn) {
@@ -40,10 +42,10 @@ k_resident(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n, ui
     const int nw = L >> 5, ldw = nw + 2;
     // buffer row o holds lattice row o - 3 (periodic): pad word, nw words, pad word
     uint32_t* buf = smem + kSegTableWords;
-    const int R = resident_rows_per_wave(L);
+    const int R = resident_rows_per_wave(L, W);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    uint32_t* list = buf + (L + 6) * ldw + wid * resident_list_words(L);
+    uint32_t* list = buf + (L + 6) * ldw + wid * resident_list_words(L, W);
     seg_load_table(sT, T);
     for (int q = threadIdx.x; q < (L + 6) * ldw; q += blockDim.x) {
         const int o = q / ldw;
@@ -97,18 +99,27 @@ k_resident(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n, ui
 }  // namespace
 
 bool resident_fits(int L) { return L % 32 == 0 && L >= 64 && L <= 256; }
+bool resident_waves_valid(int W) { return W == 4 || W == 8 || W == 16; }
+int resident_auto_waves(int L) { return L <= 96 ? 4 : 8; }  // 4 to 8 rows of a residue per wave
 
-size_t resident_lds_bytes(int L) {
+size_t resident_lds_bytes(int L, int W) {
     const int ldw = L / 32 + 2;
-    return ((size_t)kSegTableWords + (size_t)(L + 6) * ldw + (size_t)kResidentWaves * resident_list_words(L)) *
+    return ((size_t)kSegTableWords + (size_t)(L + 6) * ldw + (size_t)W * resident_list_words(L, W)) *
            sizeof(uint32_t);
 }
 
-hipError_t launch_resident(uint32_t* lat, int L, int stride, uint32_t t0, int n, uint64_t seed, const uint32_t* T,
-                           unsigned long long* delta, unsigned long long* drawn, hipStream_t st) {
-    if (!resident_fits(L) || n < 1 || stride < L / 32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_resident, dim3(1), dim3(64 * kResidentWaves), resident_lds_bytes(L), st, lat, L, stride,
-                       t0, n, (uint32_t)seed, (uint32_t)(seed >> 32), T, delta, drawn);
+hipError_t launch_resident(uint32_t* lat, int L, int stride, int W, uint32_t t0, int n, uint64_t seed,
+                           const uint32_t* T, unsigned long long* delta, unsigned long long* drawn, hipStream_t st) {
+    if (!resident_fits(L) || !resident_waves_valid(W) || n < 1 || stride < L / 32) return hipErrorInvalidValue;
+    const size_t lds = resident_lds_bytes(L, W);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (W == 4)
+        hipLaunchKernelGGL(k_resident<4>, dim3(1), dim3(256), lds, st, lat, L, stride, t0, n, k0, k1, T, delta, drawn);
+    else if (W == 8)
+        hipLaunchKernelGGL(k_resident<8>, dim3(1), dim3(512), lds, st, lat, L, stride, t0, n, k0, k1, T, delta, drawn);
+    else
+        hipLaunchKernelGGL(k_resident<16>, dim3(1), dim3(1024), lds, st, lat, L, stride, t0, n, k0, k1, T, delta,
+                           drawn);
     return hipGetLastError();
 }
 

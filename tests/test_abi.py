@@ -78,7 +78,7 @@ def test_device_bytes(pgg):
                                 dict(L=96, schedule="tiled", group=4),
                                 dict(L=32, kernel="resident"), dict(L=288, kernel="resident"),
                                 dict(L=100, kernel="resident"), dict(L=240, kernel="resident"),
-                                dict(L=128, kernel="resident", tile=32), dict(L=128, kernel="resident", group=4),
+                                dict(L=128, kernel="resident", tile=32), dict(L=128, kernel="resident", group=2), dict(L=128, kernel="resident", group=32),
                                 dict(L=128, schedule="tiled", kernel="resident")])
 def test_init_rejects_invalid_parameters_before_touching_the_device(pgg, kw):
     args = dict(L=100, r=3.8, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto")

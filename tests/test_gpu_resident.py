@@ -46,6 +46,20 @@ def test_every_sweep_against_oracle(pgg, oracle_lib, layout, L, r, K, seed):
             assert np.array_equal(sim.read_lattice(), ref), t
 
 
+@pytest.mark.parametrize("group", [4, 8, 16])
+@pytest.mark.parametrize("L", [64, 160, 256])
+def test_wave_counts(pgg, oracle_lib, L, group):
+    """Every workgroup shape (4, 8 or 16 waves, so 1 to 16 rows of a residue
+    per wave) gives the oracle's lattice and count after every sweep."""
+    r, K, seed, n = 3.76, 0.5, 31, 40
+    say("resident waves", group, "L", L)
+    s0, _ = oracle_lib.init(L, 0.5, seed)
+    ref, counts = oracle_lib.sweep(s0, r, K, seed, 0, n)
+    with pgg.Sim(L, r, K, 0.5, seed, "bits", "resident", group=group) as sim:
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
 @pytest.mark.parametrize("layout", ["bits", "int8"])
 @pytest.mark.parametrize("L", [64, 256])
 def test_one_launch_many_sweeps(pgg, oracle_lib, layout, L):
