@@ -187,25 +187,28 @@ def test_write_lattice_rejects_bad_bytes(pgg):
         assert e.value.status == pgg.PGG_E_INVAL
 
 
-def test_caller_buffer_and_stream(pgg, oracle_lib):
+@pytest.mark.parametrize("L,kernel", [(100, "auto"), (96, "auto"), (160, "resident")])
+def test_caller_buffer_and_stream(pgg, oracle_lib, L, kernel):
     import torch
-    L, r, seed, n = 100, 3.8, 4, 40
+    r, seed, n = 3.8, 4, 40
     ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
-    params = pgg.make_params(L, r, 0.5, 0.5, seed, "bits")
+    params = pgg.make_params(L, r, 0.5, 0.5, seed, "bits", kernel)
     buf = torch.zeros(pgg.pgg_device_bytes(params), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.Stream()
-    say("caller buffer + stream")
-    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", dev_buf=buf, stream=stream) as sim:
+    say("caller buffer + stream", L, kernel)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", kernel, dev_buf=buf, stream=stream) as sim:
         assert np.array_equal(sim.sweep(n), counts)
         assert np.array_equal(sim.read_lattice(), ref)
-    # the buffer is the caller's and still holds the lattice (rows of 16 bytes)
+    # the buffer is the caller's and still holds the lattice (rows of 2 ceil(L / 64) words)
     torch.cuda.synchronize()
-    host = buf.cpu().numpy().reshape(L, 16)
+    row_bytes = 8 * ((L + 63) // 64)
+    host = buf.cpu().numpy().reshape(L, row_bytes)
     bits = np.unpackbits(host, axis=1, bitorder="little")[:, :L]
     assert np.array_equal(bits, ref)
 
 
-@pytest.mark.parametrize("kernel,L", [("auto", 100), ("segment", 260), ("segment_pair", 512)])
+@pytest.mark.parametrize("kernel,L", [("auto", 100), ("segment", 260), ("segment_pair", 512), ("auto", 128),
+                                      ("resident", 224)])
 def test_int8_caller_buffer_on_segment_kernels(pgg, oracle_lib, kernel, L):
     """int8 layout on the segment kernels (a bit-packed working copy inside the
     library): the caller's byte buffer holds the oracle's lattice after every
