@@ -247,6 +247,16 @@ pgg_status pgg_write_lattice(pgg_sim* s, const uint8_t* host_LxL, uint64_t t);
  * device uses to host_T (host, 153 entries).  Synchronises the stream. */
 pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T);
 
+/* The Fermi thresholds of Eq. (3) for (r, K), as every handle, ensemble
+ * replica and served job of the library uses them: T[(dSigma + 25) * 3 +
+ * ds + 1] = min(2^32 - 1, floor(W 2^32 + 1/2)) with W = 1 / (1 + exp(((r
+ * dSigma)/5 - 5 ds)/K)), dSigma in [-25, 25], ds in {-1, 0, 1}, evaluated
+ * on the host in binary64 in exactly this operation order with the C
+ * library's exp (Sec. III; with c = 1 and G = 5, Pi_x - Pi_y = (r/5) dSigma
+ * - 5 ds).  host_T: host, 153 entries.  r finite and >= 0, K finite and >
+ * 0, else PGG_E_INVAL.  Host only: no device, no handle. */
+pgg_status pgg_fermi_table(double r, double K, uint32_t* host_T);
+
 /* Diagnostics for measurement.  With enable != 0, later pgg_sweep calls on
  * this handle time their sweep-kernel launches with HIP events on the
  * handle's stream and count the site updates that drew random numbers.
@@ -333,6 +343,10 @@ pgg_status pgg_ensemble_sweep_index(const pgg_ensemble* e, uint64_t* t);
 /* Lattice of replica rep into host_LxL (L*L bytes, row-major 0/1).
  * Synchronises. */
 pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* host_LxL);
+
+/* The 153 Fermi thresholds replica rep uses on the device (the layout of
+ * pgg_fermi_table) into host_T.  Synchronises. */
+pgg_status pgg_ensemble_threshold_table(pgg_ensemble* e, uint32_t rep, uint32_t* host_T);
 
 /* Release every buffer, graph and owned stream.  NULL is a no-op. */
 void pgg_ensemble_destroy(pgg_ensemble* e);

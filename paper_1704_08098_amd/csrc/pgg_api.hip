@@ -73,6 +73,7 @@ struct pgg_sim {
     int R = 1;       // rows per workgroup (row-band kernels)
     int segw = 0;    // columns per segment (segment kernel)
     uint32_t* d_table = nullptr;
+    uint32_t h_table[pgg::kTableSize];  // host copy, the source of the upload
     unsigned long long* d_nc = nullptr;
     unsigned long long* d_delta = nullptr;
     unsigned long long* d_counts = nullptr;
@@ -651,7 +652,8 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     if (st == PGG_OK && segment_path) st = plan_segment_graph(s);
     if (st != PGG_OK) { release(s); return st; }
 
-    hipError_t e = pgg::launch_build_table(p->r, p->K, s->d_table, s->stream);
+    pgg::fermi_table(p->r, p->K, s->h_table);
+    hipError_t e = pgg::upload_table(s->h_table, s->d_table, s->stream);
     if (e == hipSuccess)
         e = pgg::launch_init((int)p->layout, s->lattice, (int)p->L, s->stride, p->p0, p->seed, s->d_nc,
                              s->stream);
@@ -836,6 +838,14 @@ pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T) {
     PGG_HIP(s, hipMemcpyAsync(host_T, s->d_table, pgg::kTableSize * sizeof(uint32_t),
                               hipMemcpyDeviceToHost, s->stream));
     PGG_HIP(s, hipStreamSynchronize(s->stream));
+    return PGG_OK;
+}
+
+pgg_status pgg_fermi_table(double r, double K, uint32_t* host_T) {
+    if (!host_T) { set_err("host_T is NULL"); return PGG_E_INVAL; }
+    if (!std::isfinite(r) || r < 0.0) { set_err("r must be finite and >= 0"); return PGG_E_INVAL; }
+    if (!std::isfinite(K) || !(K > 0.0)) { set_err("K must be finite and > 0"); return PGG_E_INVAL; }
+    pgg::fermi_table(r, K, host_T);
     return PGG_OK;
 }
 

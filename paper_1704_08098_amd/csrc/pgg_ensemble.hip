@@ -204,21 +204,6 @@ k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __
     }
 }
 
-// Fermi tables, one block per replica (same arithmetic as k_build_table).
-__global__ void k_ens_tables(const EnsRep* __restrict__ reps, const double* __restrict__ rK) {
-#pragma clang fp contract(off)
-    const EnsRep& rp = reps[blockIdx.x];
-    const double r = rK[2 * blockIdx.x], K = rK[2 * blockIdx.x + 1];
-    const int idx = threadIdx.x;
-    if (idx >= kTableSize) return;
-    const int dsig = idx / 3 - 25;
-    const int ds = idx % 3 - 1;
-    const double dpi = (r * (double)dsig) / 5.0 - 5.0 * (double)ds;
-    const double w = 1.0 / (1.0 + exp(dpi / K));
-    const double scaled = floor(w * 4294967296.0 + 0.5);
-    ((uint32_t*)rp.T)[idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)scaled;
-}
-
 // Per replica: counts[rep][q] = nc[rep] + prefix over q of the sweep deltas
 // (q < n_active), then nc[rep] advances.  One block per replica.
 __global__ void __launch_bounds__(256)
@@ -604,26 +589,20 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         rp.delta = e->d_delta + (size_t)k * chunk * pgg::kSweepWords;
         rp.nc = e->d_nc + k;
     }
-    std::vector<double> rK(2 * n_reps);
-    for (uint32_t k = 0; k < n_reps; ++k) { rK[2 * k] = reps[k].r; rK[2 * k + 1] = reps[k].K; }
-    double* d_rK = nullptr;
-    hipError_t err = hipMalloc((void**)&d_rK, rK.size() * sizeof(double));
+    // Fermi tables built on the host, 160 words apart like the device tables
+    std::vector<uint32_t> tables((size_t)n_reps * 160, 0u);
+    for (uint32_t k = 0; k < n_reps; ++k) pgg::fermi_table(reps[k].r, reps[k].K, tables.data() + (size_t)k * 160);
+    hipError_t err = hipMemcpyAsync(e->d_reps, e->host_reps.data(), n_reps * sizeof(pgg::EnsRep),
+                                    hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess)
-        err = hipMemcpyAsync(e->d_reps, e->host_reps.data(), n_reps * sizeof(pgg::EnsRep), hipMemcpyHostToDevice,
+        err = hipMemcpyAsync(e->d_tables, tables.data(), tables.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                              e->stream);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(d_rK, rK.data(), rK.size() * sizeof(double), hipMemcpyHostToDevice, e->stream);
-    if (err == hipSuccess) {
-        hipLaunchKernelGGL(pgg::k_ens_tables, dim3(n_reps), dim3(192), 0, e->stream, e->d_reps, d_rK);
-        err = hipGetLastError();
-    }
     if (err == hipSuccess) err = pgg::launch_fill_u64(e->d_nc, n_reps, 0ull, e->stream);
     for (uint32_t k = 0; k < n_reps && err == hipSuccess; ++k) {
         const pgg::EnsRep& rp = e->host_reps[k];
         err = pgg::launch_init(PGG_LAYOUT_BITS, rp.lat, rp.L, rp.stride, reps[k].p0, reps[k].seed, e->d_nc + k, e->stream);
     }
-    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
-    if (d_rK) (void)hipFree(d_rK);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);  // also keeps `tables` alive until the copy
     if (err != hipSuccess) {
         eerr("ensemble initialisation failed: %s", hipGetErrorString(err));
         ens_release(e);
@@ -685,6 +664,17 @@ pgg_status pgg_ensemble_read_lattice(pgg_ensemble* e, uint32_t rep, uint8_t* hos
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
     (void)hipFree(tmp);
     if (err != hipSuccess) return efail(e, err, "ensemble read_lattice");
+    return PGG_OK;
+}
+
+pgg_status pgg_ensemble_threshold_table(pgg_ensemble* e, uint32_t rep, uint32_t* host_T) {
+    if (!e || !host_T) { eerr("NULL argument"); return PGG_E_INVAL; }
+    if (rep >= (uint32_t)e->n) { eerr("replica %u out of range", rep); return PGG_E_INVAL; }
+    if (e->poisoned) { eerr("ensemble poisoned by an earlier device error"); return PGG_E_STATE; }
+    hipError_t err = hipMemcpyAsync(host_T, e->host_reps[rep].T, pgg::kTableSize * sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) return efail(e, err, "ensemble threshold_table");
     return PGG_OK;
 }
 

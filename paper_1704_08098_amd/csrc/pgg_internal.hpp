@@ -20,7 +20,11 @@ __device__ __forceinline__ unsigned long long* slot_of(unsigned long long* base,
     return base + (id & (kSlots - 1)) * kSlotStride;
 }
 
-hipError_t launch_build_table(double r, double K, uint32_t* T, hipStream_t st);
+// The kTableSize Fermi thresholds T[(dSigma + 25) * 3 + ds + 1] of (r, K),
+// computed on the host (binary64), and their upload to a device table.  The
+// host array must stay valid until the copy has completed on st.
+void fermi_table(double r, double K, uint32_t* host_T);
+hipError_t upload_table(const uint32_t* host_T, uint32_t* T, hipStream_t st);
 hipError_t launch_init(int layout, void* lat, int L, int stride, double p0, uint64_t seed,
                        unsigned long long* nc, hipStream_t st);
 hipError_t launch_count(int layout, const void* lat, int L, int stride, unsigned long long* nc,

@@ -1,12 +1,14 @@
 // Kernels of the spatial public goods game engine (gfx950).
 //
-//   k_build_table      Fermi thresholds of Eq. (3) as 32-bit integers.
+//   fermi_table        Fermi thresholds of Eq. (3) as 32-bit integers (host).
 //   k_init_int8/bits   i.i.d. initial strategies (Sec. III) + N_C(0).
 //   k_colour_int8      one colour class of the sweep on the int8 layout.
 //   k_rowband_bits     the four colour classes of one row residue on the
 //                      bit-packed layout, rows staged in LDS.
 //   k_count_*, k_pack, k_unpack, k_fill_u64, k_scan_counts: bookkeeping.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <stdint.h>
 
 #include "pgg_device.hpp"
@@ -15,21 +17,24 @@
 namespace pgg {
 
 // ---------------------------------------------------------------------------
-// Fermi acceptance table, Sec. III Eq. (3).  With c = 1, G = 5 the payoff
-// difference is Pi_x - Pi_y = (r/5) dSigma - 5 ds, so the Fermi probability is
-// a function of (dSigma, ds) only; T = min(2^32 - 1, floor(W 2^32 + 1/2)).
-// binary64, fixed operation order, no contraction.
+// Fermi acceptance table, Sec. III Eq. (3), built once on the host.  With
+// c = 1, G = 5 the payoff difference is Pi_x - Pi_y = (r/5) dSigma - 5 ds, so
+// the Fermi probability is a function of (dSigma, ds) only;
+// T = min(2^32 - 1, floor(W 2^32 + 1/2)).  binary64 with the host's libm exp,
+// a fixed operation order and no contraction, so that every table of the
+// library (single lattices, ensembles, served jobs) is the same function of
+// (r, K) and never depends on a device math library.
 // ---------------------------------------------------------------------------
-__global__ void k_build_table(double r, double K, uint32_t* __restrict__ T) {
+void fermi_table(double r, double K, uint32_t* T) {
 #pragma clang fp contract(off)
-    const int idx = threadIdx.x;
-    if (idx >= kTableSize) return;
-    const int dsig = idx / 3 - 25;
-    const int ds = idx % 3 - 1;
-    const double dpi = (r * (double)dsig) / 5.0 - 5.0 * (double)ds;
-    const double w = 1.0 / (1.0 + exp(dpi / K));
-    const double scaled = floor(w * 4294967296.0 + 0.5);
-    T[idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)scaled;
+    for (int idx = 0; idx < kTableSize; ++idx) {
+        const int dsig = idx / 3 - 25;  // Sigma_x - Sigma_y
+        const int ds = idx % 3 - 1;     // s_x - s_y
+        const double dpi = (r * (double)dsig) / 5.0 - 5.0 * (double)ds;
+        const double w = 1.0 / (1.0 + std::exp(dpi / K));
+        const double scaled = std::floor(w * 4294967296.0 + 0.5);
+        T[idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)scaled;
+    }
 }
 
 // Threshold on a 32-bit word for "cooperate" in the initial state.
@@ -384,9 +389,8 @@ static int grid_for(int64_t n, int block, int cap = 65536) {
     return (int)g;
 }
 
-hipError_t launch_build_table(double r, double K, uint32_t* T, hipStream_t st) {
-    hipLaunchKernelGGL(k_build_table, dim3(1), dim3(192), 0, st, r, K, T);
-    return hipGetLastError();
+hipError_t upload_table(const uint32_t* host_T, uint32_t* T, hipStream_t st) {
+    return hipMemcpyAsync(T, host_T, kTableSize * sizeof(uint32_t), hipMemcpyHostToDevice, st);
 }
 
 hipError_t launch_init(int layout, void* lat, int L, int stride, double p0, uint64_t seed,

@@ -83,6 +83,7 @@ struct Job {
     int state = kQueued;
     size_t off = 0, bytes = 0;  // arena placement
     pgg::EnsRep rep{};
+    uint32_t table[pgg::kTableSize];  // host-built Fermi table, the source of the upload (stable map node)
     std::vector<uint64_t> counts;
     std::vector<uint8_t> lattice;
 };
@@ -181,7 +182,8 @@ hipError_t admit(pgg_server* s, uint64_t id, Job& j) {
     rp.k1 = (uint32_t)(j.p.seed >> 32);
     rp.t0 = 0;
     s->resident.push_back(id);
-    hipError_t e = pgg::launch_build_table(j.p.r, j.p.K, (uint32_t*)rp.T, s->stream);
+    pgg::fermi_table(j.p.r, j.p.K, j.table);
+    hipError_t e = pgg::upload_table(j.table, (uint32_t*)rp.T, s->stream);
     if (e == hipSuccess) e = pgg::launch_init(PGG_LAYOUT_BITS, rp.lat, rp.L, rp.stride, j.p.p0, j.p.seed, rp.nc, s->stream);
     return e;
 }

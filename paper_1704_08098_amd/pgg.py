@@ -32,11 +32,11 @@ KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBA
 
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
-           "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table",
+           "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table", "pgg_fermi_table",
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_kernel_span", "pgg_set_strip_wait", "pgg_destroy",
            "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
            "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy",
-           "pgg_ensemble_autotune",
+           "pgg_ensemble_autotune", "pgg_ensemble_threshold_table",
            "pgg_server_job_bytes", "pgg_server_create", "pgg_server_submit", "pgg_server_step",
            "pgg_server_completed", "pgg_server_job_state", "pgg_server_job_result", "pgg_server_stats",
            "pgg_server_destroy")
@@ -84,6 +84,7 @@ def load():
         "pgg_read_lattice": (ctypes.c_int, [vp, u8p]),
         "pgg_write_lattice": (ctypes.c_int, [vp, u8p, ctypes.c_uint64]),
         "pgg_threshold_table": (ctypes.c_int, [vp, u32p]),
+        "pgg_fermi_table": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, u32p]),
         "pgg_set_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "pgg_kernel_timing": (ctypes.c_int, [vp, u64p, P(ctypes.c_double), u64p]),
         "pgg_kernel_span": (ctypes.c_int, [vp, u64p, P(ctypes.c_double)]),
@@ -97,6 +98,7 @@ def load():
         "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_read_lattice": (ctypes.c_int, [vp, ctypes.c_uint32, u8p]),
         "pgg_ensemble_destroy": (None, [vp]),
+        "pgg_ensemble_threshold_table": (ctypes.c_int, [vp, ctypes.c_uint32, u32p]),
         "pgg_ensemble_autotune": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, vp, u32p, u32p,
                                                  u32p, P(ctypes.c_double)]),
         "pgg_server_job_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
@@ -196,6 +198,14 @@ def pgg_write_lattice(handle, lattice: np.ndarray, t: int) -> None:
 def pgg_threshold_table(handle) -> np.ndarray:
     out = np.zeros(153, dtype=np.uint32)
     _check(load().pgg_threshold_table(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return out.reshape(51, 3)
+
+
+def pgg_fermi_table(r: float, K: float) -> np.ndarray:
+    """The Fermi thresholds the library uses for (r, K), built on the host:
+    T[dSigma + 25, ds + 1], shape (51, 3) (host only, no device)."""
+    out = np.zeros(153, dtype=np.uint32)
+    _check(load().pgg_fermi_table(float(r), float(K), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
     return out.reshape(51, 3)
 
 
@@ -360,6 +370,13 @@ class Ensemble:
         _check(load().pgg_ensemble_read_lattice(self.handle, int(k),
                                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
         return out
+
+    def threshold_table(self, k):
+        """The Fermi thresholds replica k uses on the device, shape (51, 3)."""
+        out = np.zeros(153, dtype=np.uint32)
+        _check(load().pgg_ensemble_threshold_table(self.handle, int(k),
+                                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+        return out.reshape(51, 3)
 
     def close(self):
         if self.handle:

@@ -5,7 +5,7 @@ of the Sec. III elementary step with the Eq. (3) Fermi rule; oracle C: the
 double tiling of Sec. IV; counts as in Eq. (4)); nothing else is called.  Run
 from the repository root:
 
-    python tests/golden/make_trajectories.py [--jobs 6] [--only decay|scan|tiled]
+    python tests/golden/make_trajectories.py [--jobs 6] [--only decay|scan|tiled|ensemble|serving]
 
 Outputs (beside this script):
 
@@ -19,6 +19,16 @@ Outputs (beside this script):
 * tiled_L4096_r3.98_seed1.txt -- the paper's benchmark workload with the
   double tiling of Sec. IV (oracle C): L = 4096, r = 3.98, K = 0.5, p0 = 0.5,
   seed 1 through 1020 steps, in the format of the first file.
+* ensemble256_5000.txt -- 32 sampled replicas of the 256-replica batched
+  ensemble (8 of each L in {128, 256, 512, 1024}: replicas 0, 8, ..., 56 of
+  each size's block of 64) through all 5000 sweeps: per replica N_C at 1000,
+  2500 and 5000 sweeps, the SHA-256 of N_C(1..5000) and of the lattice after
+  5000 sweeps.  About 2.5 hours of one core, spread over --jobs processes.
+* serving_jobs.txt -- 20 jobs of the serving trace (master seed 7: every
+  fifth of its first 100 jobs; L from 88 to 1496, up to 9888 sweeps, r in
+  [3.5, 5.6], p0 in [0.1, 0.9]) run alone from their own initial state: per
+  job N_C(0), N_C after its last sweep, the SHA-256 of N_C(1..n) and of the
+  final lattice.  About four hours of one core, spread over --jobs processes.
 
 Lattice digests are over the L*L bytes (0 or 1, row-major); count digests
 over the counts as little-endian uint64.
@@ -46,6 +56,13 @@ TILED_FILE = os.path.join(HERE, "tiled_L4096_r3.98_seed1.txt")
 SCAN_FILE = os.path.join(HERE, "rscan_L1024_1000.txt")
 DECAY_MARKS = (20, 520, 1020)
 SCAN_SWEEPS = 1000
+ENSEMBLE_FILE = os.path.join(HERE, "ensemble256_5000.txt")
+ENSEMBLE_SWEEPS = 5000
+ENSEMBLE_MARKS = (1000, 2500, 5000)
+ENSEMBLE_SAMPLE = tuple(64 * b + 8 * m for b in range(4) for m in range(8))  # 8 replicas of each L
+SERVING_FILE = os.path.join(HERE, "serving_jobs.txt")
+SERVING_TRACE_JOBS = 100
+SERVING_SAMPLE = tuple(range(0, SERVING_TRACE_JOBS, 5))
 
 
 def digest_lattice(s: np.ndarray) -> str:
@@ -126,11 +143,111 @@ def scan_replicas(jobs: int):
     print("wrote", SCAN_FILE, flush=True)
 
 
+def _marked_run(args):
+    """Init + n sweeps of oracle A with N_C recorded at the marks."""
+    key, L, r, K, p0, seed, n, marks = args
+    s, nc0 = oracle.init(L, p0, seed)
+    counts = []
+    t = 0
+    for m in sorted(set(marks) | {n}):
+        s, c = oracle.sweep(s, r, K, seed, t, m - t)
+        counts.extend(int(v) for v in c)
+        t = m
+    counts = np.asarray(counts, dtype=np.uint64)
+    return key, nc0, counts, digest_counts(counts), digest_lattice(s)
+
+
+CACHE_DIR = None  # --cache: finished runs are kept there and not repeated
+
+
+def _cached_run(args):
+    """_marked_run, reusing (and saving) a finished run under CACHE_DIR."""
+    if CACHE_DIR is None:
+        return _marked_run(args)
+    key = args[0]
+    path = os.path.join(CACHE_DIR, "run_%s.npz" % hashlib.sha256(repr(args).encode()).hexdigest()[:24])
+    if os.path.exists(path):
+        z = np.load(path)
+        return key, int(z["nc0"]), z["counts"], str(z["dc"]), str(z["dl"])
+    res = _marked_run(args)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, nc0=res[1], counts=res[2], dc=res[3], dl=res[4])
+    os.replace(tmp, path)
+    return res
+
+
+def _run_pool(tasks, jobs, label):
+    """Run _marked_run over tasks (largest first), yielding results as they end."""
+    tasks = sorted(tasks, key=lambda a: -(a[1] ** 2 * a[6]))
+    t0 = time.time()
+    with ProcessPoolExecutor(max_workers=jobs) as ex:
+        for k, res in enumerate(ex.map(_cached_run, tasks)):
+            print("%s: %d of %d done, %.0f s" % (label, k + 1, len(tasks), time.time() - t0), flush=True)
+            yield res
+
+
+def ensemble_replicas_digests(jobs: int):
+    reps = wl.ensemble_replicas(sweeps=ENSEMBLE_SWEEPS)
+    tasks = [(k, reps[k]["L"], reps[k]["r"], reps[k]["K"], reps[k]["p0"], reps[k]["seed"], ENSEMBLE_SWEEPS,
+              ENSEMBLE_MARKS) for k in ENSEMBLE_SAMPLE]
+    rows = {}
+    for key, nc0, counts, dc, dl in _run_pool(tasks, jobs, "ensemble"):
+        rp = reps[key]
+        marks = " ".join("%d" % counts[m - 1] for m in ENSEMBLE_MARKS)
+        rows[key] = "%d %d %r %d %d %s %s %s" % (key, rp["L"], rp["r"], rp["seed"], nc0, marks, dc, dl)
+    lines = [
+        "# Oracle runs of sampled replicas of the batched ensemble (256 replicas, 64 of each",
+        "# L in {128, 256, 512, 1024}, r ~ U[3.6, 3.9], K = 0.5, p0 = 0.5, master seed 2017)",
+        "# through %d sweeps of the 16-colour sweep (Sec. III elementary step, Eq. (3)" % ENSEMBLE_SWEEPS,
+        "# Fermi rule, Eq. (4) count), each run alone from its own initial state.  Written by",
+        "# tests/golden/make_trajectories.py, which calls only the oracle.",
+        "# columns: replica L r seed N_C(0) N_C(%s) sha256(N_C(1..%d) as little-endian" % (
+            ") N_C(".join(str(m) for m in ENSEMBLE_MARKS), ENSEMBLE_SWEEPS),
+        "#          uint64) sha256(lattice after %d sweeps: L*L bytes 0/1, row-major)" % ENSEMBLE_SWEEPS,
+        "sweeps %d" % ENSEMBLE_SWEEPS,
+    ]
+    lines += [rows[k] for k in sorted(rows)]
+    with open(ENSEMBLE_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", ENSEMBLE_FILE, flush=True)
+
+
+def serving_job_digests(jobs: int):
+    trace = wl.serving_trace(SERVING_TRACE_JOBS, 1.0)
+    tasks = [(q, trace[q]["L"], trace[q]["r"], trace[q]["K"], trace[q]["p0"], trace[q]["seed"],
+              trace[q]["sweeps"], ()) for q in SERVING_SAMPLE]
+    rows = {}
+    for key, nc0, counts, dc, dl in _run_pool(tasks, jobs, "serving"):
+        j = trace[key]
+        rows[key] = "%d %d %r %r %d %d %d %d %s %s" % (key, j["L"], j["r"], j["p0"], j["seed"], j["sweeps"], nc0,
+                                                    counts[-1], dc, dl)
+    lines = [
+        "# Oracle runs of sampled jobs of the serving trace (wl.serving_trace, master seed 7:",
+        "# L log-uniform in [64, 2048], r ~ U[3.5, 5.6], sweeps ~ U{1000..10000}, p0 ~ U[0.1, 0.9],",
+        "# K = 0.5), each run alone from its own initial state with the 16-colour sweep",
+        "# (Sec. III elementary step, Eq. (3) Fermi rule, Eq. (4) count).  Written by",
+        "# tests/golden/make_trajectories.py, which calls only the oracle.",
+        "# columns: job L r p0 seed sweeps N_C(0) N_C(sweeps) sha256(N_C(1..sweeps) as",
+        "#          little-endian uint64) sha256(final lattice: L*L bytes 0/1, row-major)",
+        "trace_jobs %d" % SERVING_TRACE_JOBS,
+    ]
+    lines += [rows[k] for k in sorted(rows)]
+    with open(SERVING_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", SERVING_FILE, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--jobs", type=int, default=6)
-    ap.add_argument("--only", choices=["decay", "scan", "tiled"], default=None)
+    ap.add_argument("--only", choices=["decay", "scan", "tiled", "ensemble", "serving"], default=None)
+    ap.add_argument("--cache", default=None, help="directory that keeps finished ensemble/serving runs, so "
+                    "that an interrupted run resumes")
     args = ap.parse_args()
+    global CACHE_DIR
+    if args.cache:
+        os.makedirs(args.cache, exist_ok=True)
+        CACHE_DIR = os.path.abspath(args.cache)
     oracle.build(force=False)
     if args.only in (None, "scan"):
         scan_replicas(args.jobs)
@@ -138,6 +255,10 @@ def main():
         decay_trajectory()
     if args.only in (None, "tiled"):
         decay_trajectory(tiled=True)
+    if args.only in (None, "ensemble"):
+        ensemble_replicas_digests(args.jobs)
+    if args.only in (None, "serving"):
+        serving_job_digests(args.jobs)
 
 
 if __name__ == "__main__":

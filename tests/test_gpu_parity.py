@@ -96,6 +96,29 @@ def test_threshold_tables_match_oracle(pgg, oracle_lib):
                 assert np.array_equal(sim.threshold_table(), oracle_lib.table(r, K)), (r, K)
 
 
+def test_device_tables_are_the_host_tables(pgg, oracle_lib):
+    """The table each handle and ensemble replica holds on the device is the
+    host-built one (pgg_fermi_table), which equals the oracle's: random (r, K)
+    for single lattices, every replica of the 256-replica ensemble, and the r
+    of every job of the serving trace (as replicas of an ensemble)."""
+    rng = np.random.default_rng(355)
+    for r, K in zip(rng.uniform(0.0, 8.0, 40), np.exp(rng.uniform(np.log(0.02), np.log(10.0), 40))):
+        say("table r", r, "K", K)
+        with pgg.Sim(64, r, K, 0.5, 1, "bits") as sim:
+            T = sim.threshold_table()
+        assert np.array_equal(T, oracle_lib.table(r, K)) and np.array_equal(T, pgg.pgg_fermi_table(r, K)), (r, K)
+    reps = wl.ensemble_replicas()
+    say("tables of the", len(reps), "ensemble replicas")
+    with pgg.Ensemble(reps, chunk=8) as ens:
+        for k, rp in enumerate(reps):
+            assert np.array_equal(ens.threshold_table(k), oracle_lib.table(rp["r"], rp["K"])), k
+    jobs = wl.serving_trace(300, 1.0)
+    say("tables of the", len(jobs), "serving-trace jobs")
+    with pgg.Ensemble([dict(L=64, r=j["r"], K=j["K"], p0=j["p0"], seed=j["seed"]) for j in jobs], chunk=8) as ens:
+        for k, j in enumerate(jobs):
+            assert np.array_equal(ens.threshold_table(k), oracle_lib.table(j["r"], j["K"])), k
+
+
 @pytest.mark.parametrize("layout", ["int8", "bits"])
 def test_initial_states_match_oracle(pgg, oracle_lib, layout):
     for L in (4, 8, 12, 36, 100, 132, 1024):

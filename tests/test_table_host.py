@@ -1,0 +1,60 @@
+"""The library's Fermi table (Sec. III, Eq. (3)), built on the host, against
+the oracle's for every r of the workloads and thousands of random (r, K).
+
+pgg_fermi_table is a host-only call (no device, no handle), so this runs on
+the CPU; the GPU tests check that the device holds exactly this table.
+"""
+import numpy as np
+import pytest
+
+from paper_1704_08098_amd import workloads as wl
+
+
+@pytest.fixture(scope="module")
+def pgg():
+    import os
+    from paper_1704_08098_amd import pgg as mod
+    if not os.path.exists(mod.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    mod.load()
+    return mod
+
+
+def _workload_r_values():
+    rs = {wl.SMALL["r"], 3.98, 3.8, wl.R_CRITICAL}
+    rs.update(wl.SCAN["r_values"])
+    rs.update(wl.DECAY["r_values"])
+    rs.update(rp["r"] for rp in wl.ensemble_replicas())
+    rs.update(j["r"] for j in wl.serving_trace(1000, 1.0))
+    rs.update(j["r"] for j in wl.serving_trace(64, 1.0, master_seed=11))
+    return sorted(rs)
+
+
+def test_table_matches_oracle_on_every_workload_r(pgg, oracle_lib):
+    rs = _workload_r_values()
+    assert len(rs) > 1300
+    for r in rs:
+        assert np.array_equal(pgg.pgg_fermi_table(r, wl.K_PAPER), oracle_lib.table(r, wl.K_PAPER)), r
+
+
+def test_table_matches_oracle_on_random_r_and_K(pgg, oracle_lib):
+    rng = np.random.default_rng(1704)
+    r = rng.uniform(0.0, 10.0, 3000)
+    K = np.exp(rng.uniform(np.log(0.01), np.log(20.0), 3000))
+    for rv, Kv in zip(r, K):
+        assert np.array_equal(pgg.pgg_fermi_table(rv, Kv), oracle_lib.table(rv, Kv)), (rv, Kv)
+
+
+@pytest.mark.parametrize("r,K", [(0.0, 0.5), (5.0, 0.5), (3.8, 1e-6), (3.8, 1e6), (1e-300, 0.5), (1e6, 0.5)])
+def test_table_edge_values(pgg, oracle_lib, r, K):
+    T = pgg.pgg_fermi_table(r, K)
+    assert np.array_equal(T, oracle_lib.table(r, K))
+    assert T[25, 1] == 2 ** 31  # dSigma = 0, ds = 0: W = 1/2 exactly
+
+
+@pytest.mark.parametrize("r,K", [(float("nan"), 0.5), (-1.0, 0.5), (float("inf"), 0.5), (3.8, 0.0),
+                                 (3.8, -0.5), (3.8, float("nan"))])
+def test_table_rejects_invalid(pgg, r, K):
+    with pytest.raises(pgg.PggError):
+        pgg.pgg_fermi_table(r, K)
