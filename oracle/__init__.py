@@ -18,6 +18,11 @@ What each function follows in the paper (M. Perc, 2017):
 * ``sweep_tiled`` -- Sec. IV double tiling: 4 x 4 domains of four types,
                   random sequential steps inside each domain (oracle C).
 * ``count``    -- Eq. (4): the cooperator count whose mean over L^2 is rho_C.
+* ``pd_payoff``, ``pd_ncoop``, ``pd_table``, ``pd_class``, ``pd_sweep`` --
+                  the pairwise prisoner's dilemma that Sec. VI names as the
+                  next game for the same scheme (oracle D): four pairwise
+                  games per player (R = 1, T = b, S = P = 0, our reading),
+                  the Eq. (3) imitation, an 8-colour schedule.
 
 Pins (tests/test_oracle_*.py) tie every function to something other than
 itself: hand-worked payoffs, an 18-site brute force, exact rounding with
@@ -84,6 +89,16 @@ def _load():
     lib.pgg_ref_rs_run.argtypes = [u8p, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_uint64, ctypes.c_uint32, u64p]
     lib.pgg_ref_rs_run.restype = ctypes.c_int
+    lib.pgg_ref_pd_payoff.argtypes = [u8p, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    lib.pgg_ref_pd_payoff.restype = ctypes.c_double
+    lib.pgg_ref_pd_ncoop.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.pgg_ref_pd_ncoop.restype = ctypes.c_int
+    lib.pgg_ref_pd_table.argtypes = [ctypes.c_double, ctypes.c_double, u32p]
+    lib.pgg_ref_pd_table.restype = ctypes.c_int
+    lib.pgg_ref_pd_class.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.pgg_ref_pd_class.restype = ctypes.c_int
+    lib.pgg_ref_pd_sweep.argtypes = lib.pgg_ref_sweep.argtypes
+    lib.pgg_ref_pd_sweep.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -209,4 +224,51 @@ def run(L: int, r: float, K: float, p0: float, seed: int, n: int):
     """Init + n sweeps of oracle A: (lattice after n sweeps, N_C(0), counts)."""
     s, nc0 = init(L, p0, seed)
     s, counts = sweep(s, r, K, seed, 0, n)
+    return s, nc0, counts
+
+
+def pd_payoff(s: np.ndarray, b: float, i: int, j: int) -> float:
+    """Oracle D: payoff of (i, j) from its four pairwise games, binary64."""
+    s = _lattice(s)
+    return _load().pgg_ref_pd_payoff(_p(s, ctypes.c_uint8), s.shape[0], float(b), int(i), int(j))
+
+
+def pd_ncoop(s: np.ndarray, i: int, j: int) -> int:
+    """Oracle D: cooperators among the four nearest neighbours of (i, j)."""
+    s = _lattice(s)
+    return _load().pgg_ref_pd_ncoop(_p(s, ctypes.c_uint8), s.shape[0], int(i), int(j))
+
+
+def pd_table(b: float, K: float) -> np.ndarray:
+    """Oracle D: Fermi thresholds T[dir, n_x, n_y] (shape 2 x 5 x 5, uint32);
+    dir 0: x cooperates and y defects, dir 1: x defects and y cooperates."""
+    t = np.zeros(50, dtype=np.uint32)
+    _check(_load().pgg_ref_pd_table(float(b), float(K), _p(t, ctypes.c_uint32)), "pd_table")
+    return t.reshape(2, 5, 5)
+
+
+def pd_class(i: int, j: int) -> int:
+    """Oracle D: class of (i, j) in the 8-colour schedule."""
+    return int(_load().pgg_ref_pd_class(int(i), int(j)))
+
+
+def pd_sweep(s: np.ndarray, b: float, K: float, seed: int, t0: int, n: int,
+             order: int = 0, order_seed: int = 0):
+    """Oracle D: n 8-colour sweeps of the pairwise prisoner's dilemma from
+    absolute sweep index t0.  Returns (new lattice, counts after each sweep);
+    ``order`` permutes the sites inside each class and must not change the
+    result."""
+    s = _lattice(s).copy()
+    counts = np.zeros(max(int(n), 1), dtype=np.uint64)
+    _check(_load().pgg_ref_pd_sweep(_p(s, ctypes.c_uint8), s.shape[0], float(b), float(K),
+                                    int(seed) & (2**64 - 1), int(t0), int(n),
+                                    _p(counts, ctypes.c_uint64), int(order),
+                                    int(order_seed) & (2**64 - 1)), "pd_sweep")
+    return s, counts[:n]
+
+
+def pd_run(L: int, b: float, K: float, p0: float, seed: int, n: int):
+    """Init (as for oracle A) + n sweeps of oracle D: (lattice, N_C(0), counts)."""
+    s, nc0 = init(L, p0, seed)
+    s, counts = pd_sweep(s, b, K, seed, 0, n)
     return s, nc0, counts

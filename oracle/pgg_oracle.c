@@ -27,6 +27,9 @@
  *                      sequential steps inside each domain), with the same
  *                      counter RNG and table as A.  The bit-exact contract of
  *                      the tiled schedule.
+ *   D  pgg_ref_pd_sweep  the pairwise prisoner's dilemma Sec. VI names as the
+ *                      next game for the scheme: four pairwise games per
+ *                      player, the same imitation, an 8-colour schedule.
  *
  * Conventions the paper leaves open (our reading, fixed here):
  *   - lattice index x = i*L + j, i = row, j = column, both periodic mod L;
@@ -440,5 +443,138 @@ int pgg_ref_rs_run(uint8_t* s, uint32_t L, double r, double K, uint64_t seed,
         }
         if (counts) counts[mcs] = pgg_ref_count(s, L);
     }
+    return PGG_REF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Oracle D: the pairwise prisoner's dilemma that Sec. VI names as the next  */
+/* game for the same scheme: the game is played pairwise with each of the    */
+/* four nearest neighbours instead of in groups, so an elementary step reads */
+/* one line less in every direction (radius 2 around x instead of 3).        */
+/* The paper gives no payoffs; our reading is the weak prisoner's dilemma    */
+/* with temptation b: a cooperator meeting a cooperator earns R = 1, a       */
+/* defector meeting a cooperator earns T = b, everything else earns 0        */
+/* (S = P = 0).  A player's payoff is the sum of its four games, and the     */
+/* imitation is the elementary step of Sec. III with the Fermi rule Eq. (3). */
+/*                                                                          */
+/* Schedule (our reading): with a radius-2 read set, sites 4 apart (L1) may  */
+/* update together, and with L a multiple of 4 the densest such colouring    */
+/* has 8 classes: the cosets of the sublattice spanned by (2, 2) and (4, 0). */
+/* Site (i, j) has class k = 4 (i mod 2) + ((j - 2 h) mod 4) with h =         */
+/* (i div 2) mod 2; a sweep runs k = 0..7 in ascending order, every site     */
+/* once.  Random numbers: the Philox block of counter (x, t, k, 0), d = w0    */
+/* >> 30 as in oracle A, u = w1; the initial state as in oracle A.           */
+/* ------------------------------------------------------------------------ */
+
+/* Payoff of the player at (i, j) literally from the four pairwise games,
+ * binary64 (R = 1, T = b, S = P = 0). */
+double pgg_ref_pd_payoff(const uint8_t* s, int L, double b, int i, int j)
+{
+    const double R = 1.0, Tm = b, S = 0.0, P = 0.0;
+    const int sx = at(s, L, i, j);
+    double total = 0.0;
+    for (int d = 0; d < 4; ++d) {
+        const int sy = at(s, L, (int64_t)i + DIR_DI[d], (int64_t)j + DIR_DJ[d]);
+        total += sx ? (sy ? R : S) : (sy ? Tm : P);
+    }
+    return total;
+}
+
+/* Cooperators among the four nearest neighbours of (i, j), indexed modulo L
+ * on every access.  With R = 1, T = b and S = P = 0 a cooperator earns
+ * exactly this number n and a defector b n: the integer form the table uses. */
+int pgg_ref_pd_ncoop(const uint8_t* s, int L, int i, int j)
+{
+    int n = 0;
+    for (int d = 0; d < 4; ++d) n += at(s, L, (int64_t)i + DIR_DI[d], (int64_t)j + DIR_DJ[d]);
+    return n;
+}
+
+/* T[(dir * 5 + n_x) * 5 + n_y]: dir 0 = x cooperates and y defects (Pi_x =
+ * n_x, Pi_y = b n_y), dir 1 = x defects and y cooperates (Pi_x = b n_x, Pi_y =
+ * n_y); W = 1 / (1 + exp((Pi_x - Pi_y) / K)) (Eq. (3)), stored as
+ * min(2^32 - 1, floor(W * 2^32 + 1/2)).  The binary64 operation order is part
+ * of the contract. */
+int pgg_ref_pd_table(double b, double K, uint32_t* T)
+{
+    if (!(isfinite(b) && b >= 0.0 && isfinite(K) && K > 0.0)) return PGG_REF_EINVAL;
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int nx = 0; nx <= 4; ++nx) {
+            for (int ny = 0; ny <= 4; ++ny) {
+                const double pix = dir == 0 ? 1.0 * (double)nx : b * (double)nx;
+                const double piy = dir == 0 ? b * (double)ny : 1.0 * (double)ny;
+                const double w = 1.0 / (1.0 + exp((pix - piy) / K));
+                const double scaled = floor(w * 4294967296.0 + 0.5);
+                T[(dir * 5 + nx) * 5 + ny] = scaled >= 4294967295.0 ? 4294967295u : (uint32_t)scaled;
+            }
+        }
+    }
+    return PGG_REF_OK;
+}
+
+/* Class of site (i, j) in the 8-colour schedule. */
+int pgg_ref_pd_class(int i, int j)
+{
+    const int h = (i / 2) % 2;
+    return 4 * (i % 2) + (((j - 2 * h) % 4) + 4) % 4;
+}
+
+/* One elementary step of the pairwise game at (i, j) of class k, sweep t. */
+static int pd_step(uint8_t* s, int L, const uint32_t* T, uint64_t seed, uint32_t t, int k, int i, int j)
+{
+    uint32_t w[4];
+    philox_site(seed, (uint32_t)(i * L + j), t, (uint32_t)k, 0u, w);
+    const int d = (int)(w[0] >> 30);
+    const int yi = wrap((int64_t)i + DIR_DI[d], L), yj = wrap((int64_t)j + DIR_DJ[d], L);
+    const int sx = s[(size_t)i * L + j], sy = s[(size_t)yi * L + yj];
+    if (sx == sy) return 0;
+    const int nx = pgg_ref_pd_ncoop(s, L, i, j), ny = pgg_ref_pd_ncoop(s, L, yi, yj);
+    const int dir = sx ? 0 : 1;
+    if (w[1] < T[(dir * 5 + nx) * 5 + ny]) {
+        s[(size_t)i * L + j] = (uint8_t)sy;
+        return sy ? +1 : -1;
+    }
+    return 0;
+}
+
+/* n sweeps of the 8-colour schedule from absolute sweep index t0 (in
+ * place); counts[q] = N_C after sweep t0 + q.  order as for oracle A. */
+int pgg_ref_pd_sweep(uint8_t* s, uint32_t L, double b, double K, uint64_t seed,
+                     uint64_t t0, uint32_t n, uint64_t* counts, int order, uint64_t order_seed)
+{
+    if (!valid_L(L) || t0 + (uint64_t)n > 4294967296ull || order < 0 || order > 2)
+        return PGG_REF_EINVAL;
+    uint32_t T[50];
+    int rc = pgg_ref_pd_table(b, K, T);
+    if (rc) return rc;
+    /* the sites of one class, listed once */
+    const uint32_t per = L * L / 8;
+    uint32_t* cls = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)L * L);
+    uint32_t* perm = (uint32_t*)malloc(sizeof(uint32_t) * per);
+    if (!cls || !perm) { free(cls); free(perm); return PGG_REF_ENOMEM; }
+    uint64_t ost = order_seed | 1ull;
+    for (uint32_t q = 0; q < n; ++q) {
+        const uint32_t t = (uint32_t)(t0 + q);
+        for (int k = 0; k < 8; ++k) {
+            uint32_t m = 0;
+            for (uint32_t i = 0; i < L; ++i)
+                for (uint32_t j = 0; j < L; ++j)
+                    if (pgg_ref_pd_class((int)i, (int)j) == k) cls[m++] = i * L + j;
+            for (uint32_t e = 0; e < per; ++e) perm[e] = order == 1 ? per - 1 - e : e;
+            if (order == 2) {
+                for (uint32_t e = per - 1; e > 0; --e) {
+                    uint32_t z = (uint32_t)(xs64(&ost) % (uint64_t)(e + 1));
+                    uint32_t tmp = perm[e]; perm[e] = perm[z]; perm[z] = tmp;
+                }
+            }
+            for (uint32_t e = 0; e < per; ++e) {
+                const uint32_t x = cls[perm[e]];
+                pd_step(s, (int)L, T, seed, t, k, (int)(x / L), (int)(x % L));
+            }
+        }
+        if (counts) counts[q] = pgg_ref_count(s, L);
+    }
+    free(cls);
+    free(perm);
     return PGG_REF_OK;
 }

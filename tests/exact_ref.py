@@ -109,3 +109,63 @@ def sweep_tiled(s, L, r, K, words):
                     idx = int(w[0]) >> 28
                     _imitate(s, L, r, K, 4 * I + idx // 4, 4 * J + idx % 4, (int(w[0]) >> 26) & 3, int(w[1]))
     return s
+
+
+# ---------------------------------------------------------------------------
+# The pairwise prisoner's dilemma (the game Sec. VI names for the same
+# scheme; reading: R = 1, T = b, S = P = 0, four games per player).
+# ---------------------------------------------------------------------------
+def pd_payoff(s, L, b, i, j):
+    """Sum of the four pairwise games of (i, j); exact."""
+    b = Fraction(b)
+    sx = s[i % L][j % L]
+    total = Fraction(0)
+    for di, dj in _DIR:
+        sy = s[(i + di) % L][(j + dj) % L]
+        total += (1 if sy else 0) if sx else (b if sy else 0)
+    return total
+
+
+def pd_sites(L, k):
+    """The sites of class k of the 8-colour schedule, written out from its
+    definition: the coset of the sublattice spanned by (2, 2) and (4, 0)
+    that holds (k // 4, k % 4) -- i.e. (i, j) with i = k // 4 (mod 2) and
+    j - (k % 4) = 2 ((i - k // 4) / 2) (mod 4)."""
+    a, q = divmod(k, 4)
+    out = []
+    for i in range(L):
+        if (i - a) % 2:
+            continue
+        m = (i - a) // 2
+        for j in range(L):
+            if (j - q - 2 * m) % 4 == 0:
+                out.append((i, j))
+    return out
+
+
+def pd_counters(L, t, seed):
+    """Philox rows [c0, c1, c2, c3, k0, k1] of one 8-colour sweep in the
+    order pd_sweep visits the sites."""
+    rows = []
+    for k in range(8):
+        for i, j in pd_sites(L, k):
+            rows.append([i * L + j, t, k, 0, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+    return rows
+
+
+def pd_sweep(s, L, b, K, words):
+    """One 8-colour sweep of the pairwise game in place; words in the order
+    of pd_counters."""
+    q = 0
+    for k in range(8):
+        for i, j in pd_sites(L, k):
+            w = words[q]
+            q += 1
+            d = int(w[0]) >> 30
+            yi, yj = (i + _DIR[d][0]) % L, (j + _DIR[d][1]) % L
+            if s[i][j] == s[yi][yj]:
+                continue
+            dpi = pd_payoff(s, L, b, i, j) - pd_payoff(s, L, b, yi, yj)
+            if int(w[1]) < threshold(dpi, K):
+                s[i][j] = s[yi][yj]
+    return s
