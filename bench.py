@@ -8,10 +8,12 @@ sweeps, then K timed sweeps (t = W .. W+K-1), inputs resident in HBM.
 
 Prints one JSON line:
   value       whole-job site updates/s (L^2 * K / wall time of the K sweeps)
-  roofline    the dominant kernel (the segment sweep) against the VALU roof,
-              from its event-timed average launch duration
-  hbm         the same rate against the HBM roof at the algorithmic bytes of
-              the state (read + write once per sweep)
+  roofline    the dominant kernel (the paired segment sweep) against the HBM
+              roof at the algorithmic bytes of the state (read + write once
+              per sweep), from its event-timed average launch duration, with
+              its measured traffic and its counter-measured VALU use
+  windows     the early (timed) window and the late one (t = 10^4), each with
+              the fraction of updates that draw random numbers
   dense       the data-independent rate with every site drawing its random
               numbers (no skipping of no-op updates)
   late        the same lattice later in its decay (sweeps 10^4 .. 10^4+K-1)
@@ -43,24 +45,13 @@ METRIC = "site updates/s at L=4096 (% HBM roofline); batched replica updates/s v
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T full-rate lane-ops/s
 
-# Algorithmic VALU cost of one elementary step that draws its random numbers,
-# in full-rate 32-bit lane-op slots:
-#   Philox4x32-10: 19 products 32x32->64 (two per round, the last round
-#   needs one); a v_mad_u64_u32 issues at about 1.3 slots on gfx950
-#   (throughput micro-kernel) -> 25; the two 3-input XORs per round -> 19
-#   (first-round key words are uniform); payoff difference: 2 x (5 masked
-#   popcounts + 3 adds), row windows and the neighbour select -> 30; table
-#   index, compare, flip -> 6.
-PHILOX_PRODUCTS = 19
-SLOTS_PER_PRODUCT = 1.3
-SLOTS_PER_DRAWN_UPDATE = round(PHILOX_PRODUCTS * SLOTS_PER_PRODUCT) + 19 + 30 + 6
-# Every site also pays the bit-parallel activity test (8 sites per 32-bit
-# word: 4 XOR, 3 OR, 1 AND, 2 window extractions) -> ~2 slots per site.
-SLOTS_PER_SITE_SCAN = 2
-# HBM traffic of the segment kernels per launch, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (separate passes) scaled by what the same counters read for a
-# plain 256 MiB device copy.  The summary records a hash of the kernel's
-# sources and the launch configuration; a changed kernel reads as null.
+# VALU issue of the dominant kernel is read from committed SQ counter
+# summaries (rocprofv3 --pmc), like the traffic: per dispatch, the VALU
+# instructions issued and the lane-cycles they kept busy; the summary records
+# the hash of the kernel's sources, and a changed kernel reads as null.
+COUNTER_PROFILES = {"segment_pair": os.path.join(ROOT, "profiles", "k_ens_pair_L4096_sq_counters.txt")}
+N_SIMDS = 256 * 4
+GPU_CLOCK_HZ = 2.4e9
 TRAFFIC_PROFILES = {"segment": os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt"),
                     "segment_pair": os.path.join(ROOT, "profiles", "k_ens_pair_L4096_traffic.txt")}
 KERNEL_SOURCES = ("paper_1704_08098_amd/csrc/pgg_segment.hpp", "paper_1704_08098_amd/csrc/pgg_fullrow.hpp",
@@ -93,6 +84,51 @@ def measured_traffic(kernel, L, tile, group):
         return float(kv["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _summary_fields(path):
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if "|" in line:
+                k, v = line.split("|", 1)
+            elif ":" in line:
+                k, v = line.split(":", 1)
+            else:
+                continue
+            kv[k.strip()] = v.strip()
+    return kv
+
+
+def measured_valu(kernel, L, tile, group, launch_us):
+    """VALU use of one launch from the committed SQ counter summary: the
+    fraction of the SIMDs' issue cycles that issued VALU instructions and the
+    fraction of all VALU lanes kept busy, over the launch duration given
+    (the live HIP-event average).  None when the summary is missing or was
+    taken with other kernel sources or another launch configuration."""
+    path = COUNTER_PROFILES.get(kernel)
+    if path is None or not os.path.exists(path):
+        return None
+    kv = _summary_fields(path)
+    try:
+        if (kv["source_hash"] != kernel_source_hash() or int(kv["L"]) != L or int(kv["tile"]) != tile
+                or int(kv["group"]) != group):
+            return None
+        insts = float(kv["SQ_INSTS_VALU"])
+        lane_cycles = float(kv["SQ_THREAD_CYCLES_VALU"])
+    except (KeyError, ValueError):
+        return None
+    cycles = launch_us * 1e-6 * GPU_CLOCK_HZ
+    return {"source": os.path.relpath(path, ROOT), "valu_insts_per_launch": insts,
+            "active_lanes_per_inst": lane_cycles / insts,
+            "issue_frac": insts * 4.0 / (N_SIMDS * cycles),
+            "lane_frac": lane_cycles / (N_SIMDS * 16.0 * cycles),
+            "definition": "issue_frac = SQ_INSTS_VALU x 4 cycles (wave64 on a 16-lane SIMD) / (1024 SIMDs x "
+                          "launch cycles at 2.4 GHz); lane_frac = SQ_THREAD_CYCLES_VALU / (1024 SIMDs x 16 "
+                          "lanes x launch cycles): the kernel's share of the chip's full-rate VALU lane-ops"}
 
 
 # Algorithmic HBM bytes per site update: the state is read and written once
@@ -169,13 +205,16 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     nc = ens.coop_counts()
-    ens.close()
     by_size = {}
     for k, rp in enumerate(reps):
         by_size.setdefault(rp["L"], []).append(k)
+    # The plain baseline times a sample of each size alone and checks that
+    # each ends exactly where its replica in the batched run ended: the same
+    # cooperator count and the same lattice.
     t_plain = 0.0
+    checked, mismatched = 0, []
     for L, ks in sorted(by_size.items()):
-        sample = ks[:plain_per_size]
+        sample = ks[::max(1, len(ks) // plain_per_size)][:plain_per_size]
         ts = []
         for k in sample:
             rp = reps[k]
@@ -186,38 +225,50 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
             sim.sweep(sweeps - 2, want_counts=False)
             torch.cuda.synchronize()
             ts.append((time.perf_counter() - t0) * sweeps / (sweeps - 2))
+            same = sim.coop_count() == int(nc[k]) and bool((sim.read_lattice() == ens.read_lattice(k)).all())
+            checked += 1
+            if not same:
+                mismatched.append(k)
             sim.close()
         t_plain += sum(ts) / len(ts) * len(ks)
+    ens.close()
+    identical = not mismatched
     return {"metric": "replica-site updates/s", "value": total / t_batched, "plain_value": total / t_plain,
-            "ratio_vs_plain": t_plain / t_batched, "replicas": len(reps), "sweeps": sweeps,
+            "ratio_vs_plain": t_plain / t_batched if identical else None,
+            "identical_to_plain": identical, "plain_checked": checked, "plain_mismatched": mismatched, "replicas": len(reps), "sweeps": sweeps,
             "sizes": sorted(by_size), "chunk": chunk, "autotuned": tuned, "batched_s": t_batched, "plain_s_estimated": t_plain,
             "plain": "each replica alone (pgg_init/pgg_sweep, automatic kernel), %d per size timed, "
-                     "scaled to the %d replicas of each size" % (plain_per_size, len(reps) // len(by_size)),
+                     "scaled to the %d replicas of each size; each sampled replica's final count and lattice "
+                     "compared with its batched run" % (plain_per_size, len(reps) // len(by_size)),
             "mean_final_density": float(sum(int(v) / reps[k]["L"] ** 2 for k, v in enumerate(nc)) / len(reps))}
 
 
 def late_window(pgg, torch, L, r, seed, kernel, layout, t_start, steps, stream, tile=0, group=0):
     """The same lattice later in its decay: sweeps t_start .. t_start+steps-1
-    (fewer active sites, so fewer draws per sweep)."""
+    timed; then the same sweeps again from the lattice saved at t_start, in
+    timing mode, for the fraction of updates that draw random numbers and
+    the launches' own spans."""
     sim = make_sim(pgg, L, r, seed, kernel, layout, stream, tile, group)
     sim.sweep(t_start, want_counts=False)
+    start = sim.read_lattice()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.sweep(steps, want_counts=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rho = sim.density()
-    # then 100 sweeps in timing mode: the fraction of updates that draw, and launch spans
-    n_diag = 100
+    sim.write_lattice(start, t_start)
     sim.set_kernel_timing(True)
-    sim.sweep(n_diag, want_counts=False)
+    sim.sweep(steps, want_counts=False)
     launches, _, drawn = sim.kernel_timing()
     span_n, span_us = sim.kernel_span()
+    same = sim.density() == rho
     sim.close()
     return {"t_start": t_start, "steps": steps, "value": float(L) * L * steps / dt, "unit": "site updates/s",
             "ms_per_step": 1e3 * dt / steps, "density_at_end": rho,
-            "drawn_fraction_next_100": drawn / (float(L) * L * n_diag),
-            "kernel_span_us_next_100": span_us / span_n if span_n else None}
+            "drawn_fraction": drawn / (float(L) * L * steps),
+            "kernel_span_us": span_us / span_n if span_n else None,
+            "replay_matches": bool(same)}
 
 
 def decay_batch_pass(pgg, torch, warmup, steps, stream):
@@ -321,16 +372,47 @@ def scan_pass(pgg, torch, sweeps, stream):
             "note": "one batched ensemble; wall time includes the per-block count copies"}
 
 
-def cpu_baseline(L, r, seed, n_sweeps):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L, r, seed, n_sweeps, repeats=3):
+    """The oracle, single-threaded: the median of `repeats` runs of n_sweeps
+    sweeps of the benchmark lattice from its initial state (the headline
+    workload's own rate), and of the small configuration in full (L = 100,
+    r = 3.8, 1000 sweeps, seed 1)."""
     import oracle
     oracle.build(force=False)
     s, _ = oracle.init(L, 0.5, seed)
-    t0 = time.perf_counter()
-    oracle.sweep(s, r, wl.K_PAPER, seed, 0, n_sweeps)
-    dt = time.perf_counter() - t0
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.sweep(s, r, wl.K_PAPER, seed, 0, n_sweeps)
+        ts.append(time.perf_counter() - t0)
+    dt = sorted(ts)[len(ts) // 2]
+    small = wl.SMALL
+    ts_small = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.run(small["L"], small["r"], small["K"], small["p0"], small["seeds"][0], small["sweeps"])
+        ts_small.append(time.perf_counter() - t0)
+    dts = sorted(ts_small)[len(ts_small) // 2]
     return {"value": L * L * n_sweeps / dt, "unit": "site updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d sweep(s) of the L=%d, r=%g lattice from its i.i.d. 50/50 start "
-                      "(16-colour oracle, single thread, %.1f s)" % (n_sweeps, L, r, dt)}
+            "cpu_model": cpu_model(), "host_cores": os.cpu_count(),
+            "sample": "median of %d runs of %d sweep(s) of the L=%d, r=%g lattice from its i.i.d. 50/50 start "
+                      "(16-colour oracle, single thread, %.1f s each)" % (repeats, n_sweeps, L, r, dt),
+            "runs_s": ts,
+            "small_config": {"value": small["L"] ** 2 * small["sweeps"] / dts, "unit": "site updates/s",
+                             "workload": "L=%d, r=%g, %d sweeps, seed %d, init included (in full)" % (
+                                 small["L"], small["r"], small["sweeps"], small["seeds"][0]),
+                             "median_s": dts, "runs_s": ts_small}}
 
 
 def _oracle_replica(args):
@@ -456,31 +538,35 @@ def main():
     sites_per_launch = updates / max(launches, 1)  # the strip kernel: one launch per timed call
     if args.kernel in ("colour", "tiled"):
         drawn = updates
-    drawn_per_launch = drawn / max(launches, 1)
-    slots = drawn_per_launch * SLOTS_PER_DRAWN_UPDATE + sites_per_launch * SLOTS_PER_SITE_SCAN
-    achieved_tops = slots / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved_tops / VALU_PEAK_TOPS,
-                "traffic": measured_traffic(args.kernel, L, args.tile, args.group),
+    # the segment and resident kernels sweep a bit-packed lattice whatever the layout
+    hbm_bytes = BYTES_PER_UPDATE["bits" if args.kernel in ("segment", "segment_pair", "resident") else layout]
+    alg_bytes_per_launch = hbm_bytes * sites_per_launch
+    achieved_gbs = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernel_name = {"segment": "k_ens_segment", "segment_pair": "k_ens_pair", "strip": "k_strip",
+                   "rowband_staged": "k_rowband_staged", "rowband_compact": "k_rowband_bits<true>",
+                   "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8", "tiled": "k_tiled_part",
+                   "resident": "k_resident"}[args.kernel]
+    traffic = measured_traffic(args.kernel, L, args.tile, args.group)
+    roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": {"segment": "k_ens_segment", "segment_pair": "k_ens_pair", "strip": "k_strip", "rowband_staged": "k_rowband_staged",
-                           "rowband_compact": "k_rowband_bits<true>",
-                           "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8",
-                           "tiled": "k_tiled_part", "resident": "k_resident"}[args.kernel],
+                "traffic_over_algorithmic": traffic / alg_bytes_per_launch if traffic else None,
+                "kernel": kernel_name,
+                "algorithmic_bytes_per_launch": alg_bytes_per_launch,
+                "bytes_per_update": hbm_bytes,
+                "sites_per_launch": sites_per_launch,
                 "avg_launch_us": avg_ms * 1e3, "launches": launches,
                 "avg_launch_source": "HIP events around the timed region on the sweep stream / launches",
                 "timing_pass_event_us_per_launch": kms / max(launches, 1) * 1e3,
                 "kernel_span_us": span_us,
                 "drawn_fraction": drawn / updates,
-                "slots_per_drawn_update": SLOTS_PER_DRAWN_UPDATE,
-                "slots_per_site_scan": SLOTS_PER_SITE_SCAN}
-    kernel_rate = sites_per_launch / (avg_ms * 1e-3)
-    # the segment and resident kernels sweep a bit-packed lattice whatever the layout
-    hbm_bytes = BYTES_PER_UPDATE["bits" if args.kernel in ("segment", "segment_pair", "resident") else layout]
-    hbm = {"bytes_per_update": hbm_bytes, "achieved_GBs": value * hbm_bytes / 1e9,
-           "peak_GBs": HBM_PEAK_GBS, "frac": value * hbm_bytes / 1e9 / HBM_PEAK_GBS,
-           "frac_int8_equivalent": value * 2.0 / 1e9 / HBM_PEAK_GBS,
-           "kernel_only_updates_per_s": kernel_rate}
+                "frac_int8_equivalent": achieved_gbs * 2.0 / hbm_bytes / HBM_PEAK_GBS,
+                "valu": measured_valu(args.kernel, L, args.tile, args.group, avg_ms * 1e3),
+                "note": "the state is read and written once per sweep (2 bits per site update on the bit-packed "
+                        "lattice); the path is bound by integer VALU issue (one Philox4x32-10 per drawn update), "
+                        "not by HBM -- 'valu' gives the counter-measured share of the VALU lanes"}
+    windows = {"early": {"sweeps": "%d..%d" % (args.warmup, args.warmup + args.steps - 1), "value": value,
+                         "ms_per_step": 1e3 * dt / args.steps, "drawn_fraction": drawn / updates}}
 
     batched = None
     if args.ensemble_sweeps > 0:
@@ -503,6 +589,9 @@ def main():
         log("late window: sweeps %d..%d" % (args.late_start, args.late_start + args.steps - 1))
         late = late_window(pgg, torch, L, r, seed, args.kernel, layout, args.late_start, args.steps, stream,
                            args.tile, args.group)
+        windows["late"] = {"sweeps": "%d..%d" % (args.late_start, args.late_start + args.steps - 1),
+                           "value": late["value"], "ms_per_step": late["ms_per_step"],
+                           "drawn_fraction": late["drawn_fraction"]}
 
     serving = None
     if args.serve_jobs > 0:
@@ -532,7 +621,7 @@ def main():
                                                                  args.warmup + args.steps - 1),
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
-        "roofline": roofline, "hbm": hbm, "dense": dense, "late": late, "batched": batched, "serving": serving,
+        "roofline": roofline, "windows": windows, "dense": dense, "late": late, "batched": batched, "serving": serving,
         "scan": scan, "decay_batch": decay_batch, "paper_workload": paper_workload,
         "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),

@@ -170,6 +170,35 @@ typedef enum {
                                   bit-packed working copy, as for SEGMENT  */
 } pgg_schedule;
 
+/* The game the players play.  Unlike the kernel, the game changes the
+ * results. */
+typedef enum {
+    PGG_GAME_PUBLIC_GOODS = 0, /* the spatial public goods game of Sec. III
+                                  (G = 5, c = 1, multiplication factor r)  */
+    PGG_GAME_PAIRWISE_PD = 1   /* the pairwise prisoner's dilemma Sec. VI
+                                  names as the next game for the scheme: each
+                                  player plays its four nearest neighbours
+                                  (the weak dilemma, our reading: R = 1 for C
+                                  meeting C, T = b for D meeting C, S = P =
+                                  0, with b = pgg_params.r) and imitates a
+                                  random neighbour with the Fermi rule of
+                                  Eq. (3).  An elementary step reads the
+                                  radius-2 diamond around x, and a sweep runs
+                                  8 colour classes -- the cosets of the
+                                  sublattice spanned by (2, 2) and (4, 0):
+                                  class k = 4 (i mod 2) + ((j - 2 h) mod 4),
+                                  h = (i div 2) mod 2, k = 0..7 in order --
+                                  with the Philox counter (x, t, k, 0), d =
+                                  w0 >> 30, u = w1, and a copy iff s_x != s_y
+                                  and u < T[(dir 5 + n_x) 5 + n_y] (dir 0: x
+                                  is C, dir 1: x is D; n = cooperating
+                                  neighbours; see pgg_pd_table).  Initial
+                                  state as for the public goods game.  Needs
+                                  schedule 0, kernel AUTO, tile 0, group 0;
+                                  single handles only (not ensembles or the
+                                  server)                                  */
+} pgg_game;
+
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
 typedef struct {
     uint32_t L;      /* lattice side; 4 <= L <= 32768 and L % 4 == 0          */
@@ -190,6 +219,7 @@ typedef struct {
                         (0 = 4); other kernels: must be 0.  Results never
                         depend on it.                                         */
     uint32_t schedule; /* pgg_schedule (0 = the 16-colour sweep)            */
+    uint32_t game;     /* pgg_game (0 = the public goods game)              */
 } pgg_params;
 
 typedef struct pgg_sim pgg_sim; /* opaque handle */
@@ -244,7 +274,8 @@ pgg_status pgg_read_lattice(pgg_sim* s, uint8_t* host_LxL);
 pgg_status pgg_write_lattice(pgg_sim* s, const uint8_t* host_LxL, uint64_t t);
 
 /* Copy the 153 Fermi thresholds T[(dSigma + 25) * 3 + ds + 1] that the
- * device uses to host_T (host, 153 entries).  Synchronises the stream. */
+ * device uses to host_T (host, 153 entries; for the pairwise game the 50 of
+ * pgg_pd_table, then zeros).  Synchronises the stream. */
 pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T);
 
 /* The Fermi thresholds of Eq. (3) for (r, K), as every handle, ensemble
@@ -256,6 +287,18 @@ pgg_status pgg_threshold_table(pgg_sim* s, uint32_t* host_T);
  * - 5 ds).  host_T: host, 153 entries.  r finite and >= 0, K finite and >
  * 0, else PGG_E_INVAL.  Host only: no device, no handle. */
 pgg_status pgg_fermi_table(double r, double K, uint32_t* host_T);
+
+/* The 50 thresholds of the pairwise prisoner's dilemma (PGG_GAME_PAIRWISE_PD)
+ * for temptation b and noise K, as the library uses them: T[(dir * 5 + n_x)
+ * * 5 + n_y] = min(2^32 - 1, floor(W 2^32 + 1/2)), W = 1 / (1 + exp((Pi_x -
+ * Pi_y) / K)), with Pi_x = n_x and Pi_y = b n_y for dir 0 (x cooperates, y
+ * defects) and Pi_x = b n_x, Pi_y = n_y for dir 1 (x defects, y
+ * cooperates); n_x, n_y in 0..4 count the cooperating neighbours; binary64
+ * on the host in this operation order with the C library's exp.  host_T:
+ * host, 50 entries.  b finite and >= 0, K finite and > 0, else
+ * PGG_E_INVAL.  Host only.  pgg_threshold_table of a pairwise-game handle
+ * returns these 50 entries followed by zeros. */
+pgg_status pgg_pd_table(double b, double K, uint32_t* host_T);
 
 /* Diagnostics for measurement.  With enable != 0, later pgg_sweep calls on
  * this handle time their sweep-kernel launches with HIP events on the
@@ -272,7 +315,8 @@ pgg_status pgg_set_kernel_timing(pgg_sim* s, int enable);
  * launches, their summed event-to-event duration in ms (segment kernel: of
  * the chunks holding them, with the chunks' bookkeeping kernels), and the
  * number of site updates that drew random numbers (0 for the colour kernel
- * and the tiled schedule, where every update draws).
+ * and the tiled schedule, where every update draws, and for the pairwise
+ * game, which does not count them).
  * All three pointers are host and must be non-NULL.  Synchronises. */
 pgg_status pgg_kernel_timing(pgg_sim* s, uint64_t* launches, double* total_ms, uint64_t* drawn);
 

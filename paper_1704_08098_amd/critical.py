@@ -94,6 +94,10 @@ def main(argv=None):
     ap.add_argument("--per-lattice", action="store_true",
                     help="one lattice per r on --workers concurrent streams instead of one batched ensemble")
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--replicas-per-r", type=int, default=1,
+                    help="independent lattices (seeds) per r; with more than one the output adds, per r, the "
+                         "mean stationary density over them and the fraction that reached the absorbing state "
+                         "(the finite-size check of Sec. V's inset at small L)")
     args = ap.parse_args(argv)
 
     import torch
@@ -104,7 +108,10 @@ def main(argv=None):
     torch.cuda.set_device(0)
     pgg.load()
     n_r = int(round((args.r_max - args.r_min) / args.r_step)) + 1
-    r_values = tuple(float("%.6f" % (args.r_min + args.r_step * k)) for k in range(n_r))
+    per_r = max(1, args.replicas_per_r)
+    r_distinct = tuple(float("%.6f" % (args.r_min + args.r_step * k)) for k in range(n_r))
+    r_values = tuple(r for r in r_distinct for _ in range(per_r))
+    n_r = len(r_values)
     last = args.average_last or args.sweeps // 2
     cfg = dict(L=args.L, K=wl.K_PAPER, p0=0.5, sweeps=args.sweeps, average_last=last, r_values=r_values,
                seeds=tuple(args.seed + k for k in range(n_r)))
@@ -135,7 +142,16 @@ def main(argv=None):
                 fits["%g" % win] = {"r_c": rc, "beta": beta, "mean_sq_residual": msr, "points": npts}
             except ValueError:
                 pass
-    out = {"schedule": args.schedule, "batched": not args.per_lattice, "L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
+    by_r = None
+    if per_r > 1:
+        by_r = []
+        for q, rv in enumerate(r_distinct):
+            ks = list(range(q * per_r, (q + 1) * per_r))
+            final = counts[ks, -1]
+            by_r.append({"r": rv, "mean_stationary_density": float(np.mean(rho[ks])),
+                         "std_stationary_density": float(np.std(rho[ks])),
+                         "absorbed_fraction": float(np.mean(final == 0)), "replicas": per_r})
+    out = {"schedule": args.schedule, "replicas_per_r": per_r, "by_r": by_r, "batched": not args.per_lattice, "L": args.L, "sweeps": args.sweeps, "average_last": last, "r": [float(v) for v in r],
            "stationary_density": [float(v) for v in rho], "stationary": [bool(v) for v in ok],
            "seconds": dt, "replica_site_updates_per_s": n_r * float(args.L) ** 2 * args.sweeps / dt,
            "fit_by_window": fits, "tol": args.tol}

@@ -27,6 +27,7 @@ void set_err(const char* fmt, ...) {
 constexpr uint32_t kChunk = 4096;  // sweeps per count-history chunk
 constexpr int kGraphChunk = 64;    // sweeps per graph replay (segment kernel)
 constexpr int kKernelTiled = 100;  // internal kernel id of the tiled schedule (not a pgg_kernel value)
+constexpr int kKernelPd = 101;     // internal kernel id of the pairwise game (8-colour schedule)
 // Largest L for which AUTO takes the resident kernel: a sweep costs it 16-17 us
 // at L = 64 and 19-22 us at L = 128 against 31-35 us for the whole-row segment
 // kernel's four launches; at L = 256 it is 30-45 us against 33-36 us,
@@ -75,8 +76,12 @@ struct pgg_sim {
     uint32_t* d_table = nullptr;
     uint32_t h_table[pgg::kTableSize];  // host copy, the source of the upload
     unsigned long long* d_nc = nullptr;
+    // Per-sweep counters and count history of the non-segment paths, sized
+    // for the longest chunk of sweeps a call has needed so far (at most
+    // kChunk sweeps of kSweepWords words); the segment paths use d_gdelta.
     unsigned long long* d_delta = nullptr;
     unsigned long long* d_counts = nullptr;
+    uint32_t delta_sweeps = 0;
     uint64_t t = 0;
     bool poisoned = false;
     // Diagnostics (pgg_set_kernel_timing): a pair of HIP events around every
@@ -161,6 +166,24 @@ bool pair_fits(const pgg_params* p, int device) {
     return blocks >= cus && blocks <= 2L * cus && pgg::pair_lds_bytes(segw) <= pgg::kMaxDynamicLds;
 }
 
+}  // namespace
+
+namespace pgg {
+// The automatic single-lattice plan of the segment paths for a bit-packed
+// lattice of side L >= 64 (kernel AUTO, group 0): the paired kernel or the
+// single-residue one, and the segment width.
+void auto_segment_plan(uint32_t L, int device, bool* pair, int* segw) {
+    pgg_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.L = L;
+    p.layout = PGG_LAYOUT_BITS;
+    *pair = pair_fits(&p, device);
+    *segw = *pair ? choose_pair_segw(L) : choose_segw(L, kWavesPerGroup);
+}
+}  // namespace pgg
+
+namespace {
+
 bool strip_fits(uint32_t L, uint32_t H) {
     return pgg::strip_lds_bytes((int)L, (int)H, 1) <= pgg::kMaxDynamicLds;
 }
@@ -172,6 +195,14 @@ bool params_valid(const pgg_params* p, const char** why) {
     if (!std::isfinite(p->K) || !(p->K > 0.0)) { *why = "K must be finite and > 0"; return false; }
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_INT8 && p->layout != PGG_LAYOUT_BITS) { *why = "unknown layout"; return false; }
+    if (p->game != PGG_GAME_PUBLIC_GOODS && p->game != PGG_GAME_PAIRWISE_PD) { *why = "unknown game"; return false; }
+    if (p->game == PGG_GAME_PAIRWISE_PD) {
+        if (p->schedule != PGG_SCHEDULE_COLOUR16 || p->kernel != PGG_KERNEL_AUTO || p->tile != 0 || p->group != 0) {
+            *why = "the pairwise game takes schedule 0 (its own 8-colour sweep), kernel AUTO, tile 0 and group 0";
+            return false;
+        }
+        return true;
+    }
     if (p->schedule == PGG_SCHEDULE_TILED) {
         if (p->L % 8 != 0) { *why = "the tiled schedule needs L % 8 == 0"; return false; }
         if (p->kernel != PGG_KERNEL_AUTO || p->tile != 0 || p->group != 0) {
@@ -605,7 +636,9 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     }
     s->stride = bits_stride(p->L);
     s->R = p->tile ? (int)p->tile : choose_R(p->L);
-    if (p->schedule == PGG_SCHEDULE_TILED)
+    if (p->game == PGG_GAME_PAIRWISE_PD)
+        s->kernel = kKernelPd;
+    else if (p->schedule == PGG_SCHEDULE_TILED)
         s->kernel = kKernelTiled;
     else if (p->kernel != PGG_KERNEL_AUTO)
         s->kernel = (int)p->kernel;
@@ -640,19 +673,23 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     }
     if (st == PGG_OK) st = alloc((void**)&s->d_table, pgg::kTableSize * sizeof(uint32_t));
     if (st == PGG_OK) st = alloc((void**)&s->d_nc, sizeof(unsigned long long));
-    if (st == PGG_OK) st = alloc((void**)&s->d_delta, (size_t)kChunk * pgg::kSweepWords * sizeof(unsigned long long));
-    if (st == PGG_OK) st = alloc((void**)&s->d_counts, kChunk * sizeof(unsigned long long));
     if (st == PGG_OK && s->kernel == PGG_KERNEL_STRIP) st = plan_strips(s, p->tile);
     pgg_params bits = *p;
     bits.layout = PGG_LAYOUT_BITS;
     const bool packed_copy =
-        (segment_path || s->kernel == kKernelTiled || s->kernel == PGG_KERNEL_RESIDENT) && p->layout == PGG_LAYOUT_INT8;
+        (segment_path || s->kernel == kKernelTiled || s->kernel == kKernelPd || s->kernel == PGG_KERNEL_RESIDENT) &&
+        p->layout == PGG_LAYOUT_INT8;
     if (st == PGG_OK && packed_copy) st = alloc((void**)&s->shadow, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = alloc((void**)&s->lattice2, lattice_bytes(&bits));
     if (st == PGG_OK && segment_path) st = plan_segment_graph(s);
     if (st != PGG_OK) { release(s); return st; }
 
-    pgg::fermi_table(p->r, p->K, s->h_table);
+    if (s->kernel == kKernelPd) {
+        std::memset(s->h_table, 0, sizeof(s->h_table));
+        pgg::pd_table(p->r, p->K, s->h_table);
+    } else {
+        pgg::fermi_table(p->r, p->K, s->h_table);
+    }
     hipError_t e = pgg::upload_table(s->h_table, s->d_table, s->stream);
     if (e == hipSuccess)
         e = pgg::launch_init((int)p->layout, s->lattice, (int)p->L, s->stride, p->p0, p->seed, s->d_nc,
@@ -666,6 +703,32 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     *out = s;
     return PGG_OK;
 }
+
+namespace {
+// Make d_delta / d_counts hold n sweeps (n <= kChunk).  Work already queued
+// on the stream may still use the old buffers, so the stream is drained
+// before they are freed.
+pgg_status grow_delta(pgg_sim* s, uint32_t n) {
+    if (n <= s->delta_sweeps) return PGG_OK;
+    if (s->d_delta || s->d_counts) {
+        const hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return device_fail(s, e, "hipStreamSynchronize");
+        if (s->d_delta) (void)hipFree(s->d_delta);
+        if (s->d_counts) (void)hipFree(s->d_counts);
+        s->d_delta = nullptr;
+        s->d_counts = nullptr;
+        s->delta_sweeps = 0;
+    }
+    hipError_t e = hipMalloc((void**)&s->d_delta, (size_t)n * pgg::kSweepWords * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_counts, (size_t)n * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        set_err("hipMalloc of the per-sweep counters (%u sweeps) failed: %s", n, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PGG_E_NOMEM : PGG_E_DEVICE;
+    }
+    s->delta_sweeps = n;
+    return PGG_OK;
+}
+}  // namespace
 
 pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     PGG_LIVE(s);
@@ -683,6 +746,10 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
     uint32_t* tiled_lat = s->shadow ? s->shadow : (uint32_t*)s->lattice;
     if (s->shadow)
         PGG_HIP(s, pgg::launch_pack((const uint8_t*)s->lattice, s->shadow, L, s->stride, s->stream));
+    {
+        const pgg_status gs = grow_delta(s, std::min(kChunk, n_sweeps));
+        if (gs != PGG_OK) return gs;
+    }
     uint32_t done = 0;
     while (done < n_sweeps) {
         const uint32_t n = std::min(kChunk, n_sweeps - done);
@@ -710,7 +777,13 @@ pgg_status pgg_sweep(pgg_sim* s, uint32_t n_sweeps, uint64_t* coop_counts) {
         for (uint32_t q = 0; per_sweep && q < n; ++q) {
             const uint32_t t = (uint32_t)(s->t + done + q);
             unsigned long long* dq = s->d_delta + (size_t)q * pgg::kSweepWords;
-            if (s->kernel == kKernelTiled) {
+            if (s->kernel == kKernelPd) {
+                for (int k = 0; k < 8; ++k)
+                    PGG_HIP(s, timed_launch(s, [&] {
+                        return pgg::launch_pd_class(tiled_lat, L, s->stride, k, t, s->p.seed, s->d_table, dq,
+                                                    s->stream);
+                    }));
+            } else if (s->kernel == kKernelTiled) {
                 for (int part = 0; part < 4; ++part)
                     PGG_HIP(s, timed_launch(s, [&] {
                         return pgg::launch_tiled_part(tiled_lat, L, s->stride, part, t, s->p.seed,
@@ -846,6 +919,14 @@ pgg_status pgg_fermi_table(double r, double K, uint32_t* host_T) {
     if (!std::isfinite(r) || r < 0.0) { set_err("r must be finite and >= 0"); return PGG_E_INVAL; }
     if (!std::isfinite(K) || !(K > 0.0)) { set_err("K must be finite and > 0"); return PGG_E_INVAL; }
     pgg::fermi_table(r, K, host_T);
+    return PGG_OK;
+}
+
+pgg_status pgg_pd_table(double b, double K, uint32_t* host_T) {
+    if (!host_T) { set_err("host_T is NULL"); return PGG_E_INVAL; }
+    if (!std::isfinite(b) || b < 0.0) { set_err("b must be finite and >= 0"); return PGG_E_INVAL; }
+    if (!std::isfinite(K) || !(K > 0.0)) { set_err("K must be finite and > 0"); return PGG_E_INVAL; }
+    pgg::pd_table(b, K, host_T);
     return PGG_OK;
 }
 

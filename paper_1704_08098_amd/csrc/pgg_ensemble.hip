@@ -410,6 +410,10 @@ hipError_t launch_pair_chunk(EnsRep* d_rep, int blocks, size_t lds, int len, int
 struct pgg_ensemble {
     hipStream_t stream = nullptr;
     bool own_stream = false;  // graphs cannot capture the null stream
+    // Graphs are captured on a private non-blocking stream (a capture on a
+    // blocking stream is invalidated by another thread's null-stream work)
+    // and launched on `stream`.
+    hipStream_t capture_stream = nullptr;
     int device = 0;
     int n = 0;
     int chunk = 32;          // sweeps per graph replay
@@ -455,25 +459,29 @@ void ens_release(pgg_ensemble* e) {
     if (e->d_delta) (void)hipFree(e->d_delta);
     if (e->d_counts) (void)hipFree(e->d_counts);
     if (e->d_nc) (void)hipFree(e->d_nc);
+    if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
 
-hipError_t enqueue_chunk(pgg_ensemble* e, int len) {
+hipError_t enqueue_chunk(pgg_ensemble* e, int len, hipStream_t st) {
     if (e->tiled)
-        return pgg::launch_ens_tiled_chunk(e->d_reps, e->n, e->total_waves, len, e->chunk, e->d_counts, e->stream);
-    return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts,
-                                 e->stream, e->wpg);
+        return pgg::launch_ens_tiled_chunk(e->d_reps, e->n, e->total_waves, len, e->chunk, e->d_counts, st);
+    return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts, st,
+                                 e->wpg);
 }
 
 hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
     auto it = e->graphs.find(len);
     if (it != e->graphs.end()) { *out = it->second; return hipSuccess; }
     hipGraph_t g = nullptr;
-    hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal);
+    hipError_t err = hipSuccess;
+    if (!e->capture_stream) err = hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking);
     if (err != hipSuccess) return err;
-    hipError_t enq = enqueue_chunk(e, len);
-    err = hipStreamEndCapture(e->stream, &g);
+    err = hipStreamBeginCapture(e->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return err;
+    hipError_t enq = enqueue_chunk(e, len, e->capture_stream);
+    err = hipStreamEndCapture(e->capture_stream, &g);
     if (enq != hipSuccess) { if (g) (void)hipGraphDestroy(g); return enq; }
     if (err != hipSuccess) return err;
     hipGraphExec_t ex = nullptr;
@@ -500,6 +508,7 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
         if (p.layout != PGG_LAYOUT_BITS) { eerr("replica %u: ensembles use the bits layout", k); return PGG_E_INVAL; }
         if (p.kernel != PGG_KERNEL_AUTO && p.kernel != PGG_KERNEL_SEGMENT) { eerr("replica %u: ensembles use the segment kernel", k); return PGG_E_INVAL; }
         if (p.group != 0) { eerr("replica %u: group must be 0 (the ensemble's waves_per_group applies)", k); return PGG_E_INVAL; }
+        if (p.game != PGG_GAME_PUBLIC_GOODS) { eerr("replica %u: ensembles run the public goods game", k); return PGG_E_INVAL; }
         if (p.schedule != PGG_SCHEDULE_COLOUR16 && p.schedule != PGG_SCHEDULE_TILED) { eerr("replica %u: unknown schedule", k); return PGG_E_INVAL; }
         if (p.schedule != reps[0].schedule) { eerr("replica %u: every replica of an ensemble runs the same schedule", k); return PGG_E_INVAL; }
         if (p.schedule == PGG_SCHEDULE_TILED && (p.L % 8 != 0 || (tiles && tiles[k] != 0))) {

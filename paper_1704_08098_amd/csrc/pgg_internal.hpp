@@ -60,6 +60,14 @@ hipError_t launch_tiled_part(uint32_t* lat, int L, int stride, int part, uint32_
                              const uint32_t* T, unsigned long long* delta, hipStream_t st);
 // Workgroups of one tiled launch for side L.
 int tiled_blocks(int L);
+// The pairwise prisoner's dilemma (pgg_pd.hip): the 50 thresholds
+// T[(dir * 5 + n_x) * 5 + n_y] for temptation b and noise K (host, binary64),
+// and one class k (0..7) of sweep t of the 8-colour schedule on the bits
+// layout, in place.
+constexpr int kPdTableSize = 50;
+void pd_table(double b, double K, uint32_t* host_T);
+hipError_t launch_pd_class(uint32_t* lat, int L, int stride, int k, uint32_t t, uint64_t seed, const uint32_t* T,
+                           unsigned long long* delta, hipStream_t st);
 // Resident sweep (pgg_resident.hip): one workgroup of W waves (4, 8 or 16)
 // holds the lattice in LDS and runs n sweeps from sweep index t0; delta[q]
 // (kSweepWords each) receives sweep t0 + q.  L a multiple of 32, 64 <= L <= 256.
@@ -168,6 +176,11 @@ int pair_blocks(const EnsRep& rp);
 // One chunk of len sweeps, 2 launches per sweep (residues 0-1, then 2-3).
 hipError_t launch_pair_chunk(EnsRep* d_rep, int blocks, size_t lds, int len, int chunk, unsigned long long* counts,
                              hipStream_t st, unsigned long long* span);
+
+// The automatic single-lattice plan of the segment paths (pgg_api.hip): for a
+// bit-packed lattice of side L >= 64 with kernel AUTO and group 0, whether
+// the paired kernel runs, and the segment width.
+void auto_segment_plan(uint32_t L, int device, bool* pair, int* segw);
 
 // Set n_launches span records (kSpanWords words each) to (~0, 0) pairs.
 hipError_t launch_span_reset(unsigned long long* span, int n_launches, hipStream_t st);

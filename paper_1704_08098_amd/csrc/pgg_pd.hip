@@ -1,0 +1,139 @@
+// The pairwise prisoner's dilemma that Sec. VI names as the next game for the
+// same scheme: each player plays the four nearest neighbours pairwise (weak
+// dilemma: R = 1 for C meeting C, T = b for D meeting C, S = P = 0) and
+// imitates a random neighbour with the Fermi probability of Eq. (3).  A
+// player with n cooperating neighbours earns n as a cooperator and b n as a
+// defector, so the acceptance threshold is a function of (s_x, n_x, n_y): 50
+// entries built once on the host.
+//
+// An elementary step of x reads the radius-2 diamond around it (one line
+// less than the public goods game).  The sweep runs 8 colour classes, the
+// cosets of the sublattice spanned by (2, 2) and (4, 0): class k = 4 (i mod 2)
+// + ((j - 2 h) mod 4), h = (i div 2) mod 2, in ascending order.  Same-class
+// sites are at least 4 apart, so a class updates in parallel.
+//
+// One launch per class: a thread owns one 32-column word of one row of the
+// class's row parity.  It reads 64-bit windows (columns 32 w - 16 .. 32 w +
+// 47) of the five rows i-2 .. i+2, finds the class sites of its word with a
+// differing neighbour (the others cannot change and draw nothing), and for
+// each of them draws the Philox block of counter (x, t, k, 0) and applies
+// the rule.  Every bit a thread reads outside its word's class sites is a
+// site of another class, unchanged during the launch, so the order in which
+// threads run never matters; each thread writes only its own word.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <stdint.h>
+
+#include "pgg_device.hpp"
+#include "pgg_internal.hpp"
+#include "pgg_segment.hpp"
+
+namespace pgg {
+
+constexpr int kPdThreads = 256;
+
+// The thresholds of the pairwise game for temptation b and noise K:
+// T[(dir * 5 + n_x) * 5 + n_y], dir 0 = x cooperates and copies a defector
+// (Pi_x = n_x, Pi_y = b n_y), dir 1 = x defects and copies a cooperator
+// (Pi_x = b n_x, Pi_y = n_y); W = 1 / (1 + exp((Pi_x - Pi_y) / K)) and
+// T = min(2^32 - 1, floor(W 2^32 + 1/2)).  binary64, host libm exp, fixed
+// operation order.
+void pd_table(double b, double K, uint32_t* T) {
+#pragma clang fp contract(off)
+    for (int idx = 0; idx < kPdTableSize; ++idx) {
+        const int dir = idx / 25, nx = (idx / 5) % 5, ny = idx % 5;
+        const double pix = dir == 0 ? 1.0 * (double)nx : b * (double)nx;
+        const double piy = dir == 0 ? b * (double)ny : 1.0 * (double)ny;
+        const double w = 1.0 / (1.0 + std::exp((pix - piy) / K));
+        const double scaled = std::floor(w * 4294967296.0 + 0.5);
+        T[idx] = scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)scaled;
+    }
+}
+
+__device__ __forceinline__ uint32_t bit64(uint64_t v, int p) { return (uint32_t)(v >> p) & 1u; }
+
+__global__ void __launch_bounds__(kPdThreads)
+k_pd_class(uint32_t* __restrict__ lat, int L, int stride, int nw, int k, uint32_t t, uint32_t k0, uint32_t k1,
+           const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta) {
+    __shared__ uint32_t sT[kPdTableSize];
+    __shared__ int s_part[kPdThreads / 64];
+    for (int q = threadIdx.x; q < kPdTableSize; q += blockDim.x) sT[q] = T[q];
+    __syncthreads();
+    const int p = k >> 2, qc = k & 3;
+    const int rows = L >> 1;  // rows of parity p
+    const int64_t task = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int my_delta = 0;
+    if (task < (int64_t)rows * nw) {
+        const int ri = (int)(task / nw), w = (int)(task - (int64_t)ri * nw);
+        const int i = p + 2 * ri;
+        const int h = (i >> 1) & 1;
+        const int cls = (qc + 2 * h) & 3;  // column residue of the class in this row
+        const int c0 = 32 * w;
+        // five 64-bit windows, bit b = column c0 - 16 + b (periodic)
+        uint64_t win[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            int gi = i - 2 + o;
+            gi += (gi < 0) ? L : 0;
+            gi -= (gi >= L) ? L : 0;
+            const uint32_t* row = lat + (size_t)gi * stride;
+            const uint32_t lo = seg::global_window(row, L, nw, c0 - 16);
+            const uint32_t hi = seg::global_window(row, L, nw, c0 + 16);
+            win[o] = ((uint64_t)hi << 32) | lo;
+        }
+        // columns c0 .. c0 + 31 (bits at columns >= L wrap round in the
+        // windows; they are masked off, and the stored word keeps them zero)
+        const int valid = min(32, L - c0);
+        const uint32_t vmask = valid >= 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+        const uint32_t X = (uint32_t)(win[2] >> 16);
+        const uint32_t E = (uint32_t)(win[2] >> 17), Wn = (uint32_t)(win[2] >> 15);
+        const uint32_t N = (uint32_t)(win[1] >> 16), S = (uint32_t)(win[3] >> 16);
+        uint32_t act = ((X ^ E) | (X ^ Wn) | (X ^ N) | (X ^ S)) & (0x11111111u << cls) & vmask;
+        const uint32_t own = X & vmask;
+        uint32_t out = own;
+        const uint32_t row_base = (uint32_t)i * (uint32_t)L + (uint32_t)c0;
+        while (act) {
+            const int o = __ffs(act) - 1;
+            act &= act - 1u;
+            const uint4 rnd = philox4x32_10(make_uint4(row_base + (uint32_t)o, t, (uint32_t)k, 0u), k0, k1);
+            const int d = (int)(rnd.x >> 30);  // 0 E, 1 W, 2 S, 3 N
+            const int di = dir_di(d), dj = dir_dj(d);
+            const int pc = 16 + o;  // x's column in the windows
+            const int sx = (int)bit64(win[2], pc);
+            const int sy = (int)bit64(win[2 + di], pc + dj);
+            if (sx == sy) continue;
+            const int nx = (int)(bit64(win[1], pc) + bit64(win[3], pc) + bit64(win[2], pc - 1) + bit64(win[2], pc + 1));
+            const int ry = 2 + di, cy = pc + dj;
+            const int ny = (int)(bit64(win[ry - 1], cy) + bit64(win[ry + 1], cy) + bit64(win[ry], cy - 1) +
+                                 bit64(win[ry], cy + 1));
+            const int dir = sx ? 0 : 1;
+            if (rnd.y < sT[(dir * 5 + nx) * 5 + ny]) {
+                out ^= 1u << o;
+                my_delta += sy ? 1 : -1;
+            }
+        }
+        if (out != own) lat[(size_t)i * stride + w] = out;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) my_delta += __shfl_xor(my_delta, off, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = my_delta;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sum = 0;
+        for (int q = 0; q < kPdThreads / 64; ++q) sum += s_part[q];
+        if (sum) atomicAdd(slot_of(delta, (int)blockIdx.x), (unsigned long long)(long long)sum);
+    }
+}
+
+hipError_t launch_pd_class(uint32_t* lat, int L, int stride, int k, uint32_t t, uint64_t seed, const uint32_t* T,
+                           unsigned long long* delta, hipStream_t st) {
+    const int nw = (L + 31) / 32;
+    const int64_t tasks = (int64_t)(L / 2) * nw;
+    const int blocks = (int)((tasks + kPdThreads - 1) / kPdThreads);
+    hipLaunchKernelGGL(k_pd_class, dim3(blocks), dim3(kPdThreads), 0, st, lat, L, stride, nw, k, t, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), T, delta);
+    return hipGetLastError();
+}
+
+}  // namespace pgg

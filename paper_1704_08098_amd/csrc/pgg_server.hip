@@ -160,6 +160,7 @@ bool job_params_ok(const pgg_params* p, uint32_t max_L, const char** why) {
     }
     if (p->group != 0) { *why = "jobs run with the server's workgroup shape (group must be 0)"; return false; }
     if (p->schedule != PGG_SCHEDULE_COLOUR16) { *why = "jobs run the 16-colour sweep"; return false; }
+    if (p->game != PGG_GAME_PUBLIC_GOODS) { *why = "jobs run the public goods game"; return false; }
     return true;
 }
 

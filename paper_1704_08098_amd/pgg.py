@@ -25,6 +25,8 @@ KERNEL_STRIP, KERNEL_SEGMENT, KERNEL_SEGMENT_PAIR, KERNEL_RESIDENT = 5, 6, 7, 8
 SCHEDULE_COLOUR16, SCHEDULE_TILED = 0, 1
 LAYOUTS = {"int8": LAYOUT_INT8, "bits": LAYOUT_BITS}
 SCHEDULES = {"colour16": SCHEDULE_COLOUR16, "tiled": SCHEDULE_TILED}
+GAME_PUBLIC_GOODS, GAME_PAIRWISE_PD = 0, 1
+GAMES = {"pgg": GAME_PUBLIC_GOODS, "pd": GAME_PAIRWISE_PD}
 KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBAND,
            "rowband_compact": KERNEL_ROWBAND_COMPACT, "rowband_staged": KERNEL_ROWBAND_STAGED,
            "strip": KERNEL_STRIP, "segment": KERNEL_SEGMENT, "segment_pair": KERNEL_SEGMENT_PAIR,
@@ -33,6 +35,7 @@ KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBA
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
 EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table", "pgg_fermi_table",
+           "pgg_pd_table",
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_kernel_span", "pgg_set_strip_wait", "pgg_destroy",
            "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
            "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy",
@@ -46,7 +49,7 @@ class PggParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("r", ctypes.c_double), ("K", ctypes.c_double),
                 ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
                 ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("group", ctypes.c_uint32),
-                ("schedule", ctypes.c_uint32)]
+                ("schedule", ctypes.c_uint32), ("game", ctypes.c_uint32)]
 
 
 class PggServerInfo(ctypes.Structure):
@@ -85,6 +88,7 @@ def load():
         "pgg_write_lattice": (ctypes.c_int, [vp, u8p, ctypes.c_uint64]),
         "pgg_threshold_table": (ctypes.c_int, [vp, u32p]),
         "pgg_fermi_table": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, u32p]),
+        "pgg_pd_table": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, u32p]),
         "pgg_set_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "pgg_kernel_timing": (ctypes.c_int, [vp, u64p, P(ctypes.c_double), u64p]),
         "pgg_kernel_span": (ctypes.c_int, [vp, u64p, P(ctypes.c_double)]),
@@ -126,11 +130,13 @@ def _check(status):
 
 
 def make_params(L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto", tile=0, group=0,
-                schedule="colour16") -> PggParams:
+                schedule="colour16", game="pgg") -> PggParams:
+    """game "pd": the pairwise prisoner's dilemma with temptation b = r."""
     return PggParams(int(L), float(r), float(K), float(p0), int(seed) & (2**64 - 1),
                      LAYOUTS[layout] if isinstance(layout, str) else int(layout),
                      KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(tile), int(group),
-                     SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule))
+                     SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule),
+                     GAMES[game] if isinstance(game, str) else int(game))
 
 
 def pgg_device_bytes(params: PggParams) -> int:
@@ -209,6 +215,14 @@ def pgg_fermi_table(r: float, K: float) -> np.ndarray:
     return out.reshape(51, 3)
 
 
+def pgg_pd_table(b: float, K: float) -> np.ndarray:
+    """The thresholds of the pairwise prisoner's dilemma the library uses for
+    (b, K), built on the host: T[dir, n_x, n_y], shape (2, 5, 5) (host only)."""
+    out = np.zeros(50, dtype=np.uint32)
+    _check(load().pgg_pd_table(float(b), float(K), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return out.reshape(2, 5, 5)
+
+
 def pgg_set_kernel_timing(handle, enable: bool) -> None:
     _check(load().pgg_set_kernel_timing(handle, 1 if enable else 0))
 
@@ -233,8 +247,8 @@ class Sim:
     """One lattice on the GPU.  Mirrors the C calls one to one."""
 
     def __init__(self, L, r, K=0.5, p0=0.5, seed=1, layout="bits", kernel="auto",
-                 dev_buf=None, stream=None, tile=0, group=0, schedule="colour16"):
-        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile, group, schedule)
+                 dev_buf=None, stream=None, tile=0, group=0, schedule="colour16", game="pgg"):
+        self.params = make_params(L, r, K, p0, seed, layout, kernel, tile, group, schedule, game)
         self.L = int(L)
         self._buf = dev_buf  # keep a caller tensor alive as long as the handle
         self.handle = pgg_init(self.params, dev_buf, stream)
@@ -299,7 +313,8 @@ def _replica_params(replicas):
     arr = (PggParams * len(replicas))()
     for k, rp in enumerate(replicas):
         arr[k] = make_params(rp["L"], rp["r"], rp.get("K", 0.5), rp.get("p0", 0.5),
-                             rp.get("seed", 1), "bits", "auto", schedule=rp.get("schedule", "colour16"))
+                             rp.get("seed", 1), "bits", "auto", schedule=rp.get("schedule", "colour16"),
+                             game=rp.get("game", "pgg"))
     return arr
 
 

@@ -39,6 +39,7 @@ def test_params_struct_layout(pgg):
     assert pgg.PggParams.seed.offset == 32
     assert pgg.PggParams.group.offset == 52
     assert pgg.PggParams.schedule.offset == 56
+    assert pgg.PggParams.game.offset == 60
 
 
 def test_device_bytes(pgg):

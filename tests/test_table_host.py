@@ -58,3 +58,19 @@ def test_table_edge_values(pgg, oracle_lib, r, K):
 def test_table_rejects_invalid(pgg, r, K):
     with pytest.raises(pgg.PggError):
         pgg.pgg_fermi_table(r, K)
+
+
+def test_pd_table_matches_oracle(pgg, oracle_lib):
+    # the pairwise prisoner's dilemma's 50 thresholds (host-built) against
+    # oracle D's for the temptations of the tests and random (b, K)
+    rng = np.random.default_rng(130)
+    pairs = [(b, K) for b in (0.0, 1.0, 1.01, 1.05, 1.1, 1.3, 1.5, 1.7, 1.9, 2.0, 2.5) for K in (0.1, 0.5)]
+    pairs += list(zip(rng.uniform(0.0, 4.0, 2000), np.exp(rng.uniform(np.log(0.01), np.log(20.0), 2000))))
+    for b, K in pairs:
+        assert np.array_equal(pgg.pgg_pd_table(b, K), oracle_lib.pd_table(b, K)), (b, K)
+
+
+@pytest.mark.parametrize("b,K", [(float("nan"), 0.5), (-1.0, 0.5), (1.5, 0.0)])
+def test_pd_table_rejects_invalid(pgg, b, K):
+    with pytest.raises(pgg.PggError):
+        pgg.pgg_pd_table(b, K)
