@@ -195,8 +195,8 @@ typedef enum {
                                   neighbours; see pgg_pd_table).  Initial
                                   state as for the public goods game.  Needs
                                   schedule 0, kernel AUTO, tile 0, group 0;
-                                  single handles only (not ensembles or the
-                                  server)                                  */
+                                  single handles only (not ensembles, the
+                                  server or pgg_sweep_static)              */
 } pgg_game;
 
 /* Simulation parameters (Sec. III).  G = 5 and c = 1 are fixed. */
@@ -486,6 +486,43 @@ pgg_status pgg_server_stats(const pgg_server* s, pgg_server_info* st);
 
 /* Release the arena, the buffers and an owned stream.  NULL is a no-op. */
 void pgg_server_destroy(pgg_server* s);
+
+/* ------------------------------------------------------------------------
+ * A sweep that allocates nothing, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It advances a caller's bit-packed lattice exactly as
+ * pgg_init + pgg_sweep would (the same kernels, chosen as AUTO does), with
+ * every buffer the kernels need beyond the caller's lattice and counts --
+ * the Fermi thresholds, the per-sweep counters, the second lattice buffer
+ * of the out-of-place sweep -- in one fixed device array of the library
+ * (pgg_sweep_static_scratch_bytes() bytes, about 2.3 MB, held on each device
+ * the call runs on until the process ends).  It calls no hipMalloc, hipFree
+ * or allocating library routine, and does not synchronise.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the fixed device array pgg_sweep_static uses on each device. */
+size_t pgg_sweep_static_scratch_bytes(void);
+
+/* Advance the lattice in dev_lattice n_sweeps sweeps from sweep index t0.
+ *   p            host; L a multiple of 4 in [64, 4096] (larger L would need
+ *                more than the fixed array: PGG_E_INVAL), r, K and seed as
+ *                for pgg_init (p0 unused), layout BITS, kernel AUTO, tile 0,
+ *                group 0, schedule COLOUR16; anything else is PGG_E_INVAL.
+ *   dev_lattice  device, pgg_device_bytes(p) bytes, 4-byte aligned: the
+ *                lattice in the bits layout (padding bits zero), updated in
+ *                place; it holds the state after t0 sweeps on entry.
+ *   t0           sweep index of that state; t0 + n_sweeps <= 2^32.
+ *   dev_counts   device array of n_sweeps entries (8-byte aligned)
+ *                receiving N_C after each sweep, or NULL.
+ *   hip_stream   stream to order the work on (NULL: the null stream).
+ * Only enqueues work.  Every call on a device shares that device's array,
+ * which keeps the last call's contents (each call re-initialises what it
+ * reads): calls that overlap on one device -- on different streams, or from
+ * different threads -- race and give wrong results; order them on one
+ * stream.  A launch error returns PGG_E_DEVICE (there is no handle to
+ * poison). */
+pgg_status pgg_sweep_static(const pgg_params* p, void* dev_lattice, uint64_t t0, uint32_t n_sweeps,
+                            uint64_t* dev_counts, void* hip_stream);
 
 /* Thread-local, NUL-terminated description of the last error on this thread
  * ("" if none).  Valid until the next call on this thread. */

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpgg.so")
 SOURCES = ["pgg_kernels.hip", "pgg_staged.hip", "pgg_strip.hip", "pgg_ensemble.hip", "pgg_server.hip", "pgg_tiled.hip", "pgg_pd.hip",
-           "pgg_resident.hip", "pgg_api.hip"]
+           "pgg_resident.hip", "pgg_noalloc.hip", "pgg_api.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay disabled in every HIP object.

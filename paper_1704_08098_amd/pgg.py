@@ -42,7 +42,7 @@ EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop
            "pgg_ensemble_autotune", "pgg_ensemble_threshold_table",
            "pgg_server_job_bytes", "pgg_server_create", "pgg_server_submit", "pgg_server_step",
            "pgg_server_completed", "pgg_server_job_state", "pgg_server_job_result", "pgg_server_stats",
-           "pgg_server_destroy")
+           "pgg_server_destroy", "pgg_sweep_static_scratch_bytes", "pgg_sweep_static")
 
 
 class PggParams(ctypes.Structure):
@@ -115,6 +115,8 @@ def load():
         "pgg_server_job_result": (ctypes.c_int, [vp, ctypes.c_uint64, u64p, u8p]),
         "pgg_server_stats": (ctypes.c_int, [vp, P(PggServerInfo)]),
         "pgg_server_destroy": (None, [vp]),
+        "pgg_sweep_static_scratch_bytes": (ctypes.c_size_t, []),
+        "pgg_sweep_static": (ctypes.c_int, [P(PggParams), vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +238,26 @@ def pgg_kernel_timing(handle):
 
 def pgg_set_strip_wait(handle, seconds: float) -> None:
     _check(load().pgg_set_strip_wait(handle, float(seconds)))
+
+
+def pgg_sweep_static_scratch_bytes() -> int:
+    return int(load().pgg_sweep_static_scratch_bytes())
+
+
+def pgg_sweep_static(params: PggParams, dev_lattice, t0: int, n: int, dev_counts=None, stream=None) -> None:
+    """The sweep that allocates nothing: advance the bit-packed lattice in
+    the device tensor dev_lattice (pgg_device_bytes(params) bytes) n sweeps
+    from sweep index t0; dev_counts: None or a device uint64-sized tensor of
+    n entries receiving N_C after each sweep.  Only enqueues work."""
+    if dev_lattice.numel() * dev_lattice.element_size() < pgg_device_bytes(params):
+        raise ValueError("dev_lattice is smaller than pgg_device_bytes(params)")
+    cptr = None
+    if dev_counts is not None:
+        if dev_counts.numel() * dev_counts.element_size() < 8 * int(n):
+            raise ValueError("dev_counts holds fewer than n 64-bit entries")
+        cptr = dev_counts.data_ptr()
+    _check(load().pgg_sweep_static(ctypes.byref(params), dev_lattice.data_ptr(), int(t0), int(n), cptr,
+                                   _stream_handle(stream)))
 
 
 def pgg_destroy(handle) -> None:
