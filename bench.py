@@ -188,17 +188,18 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     pgg_ensemble_autotune (untimed, before the timed run)."""
     reps = wl.ensemble_replicas(sweeps=sweeps)
     total = float(sum(rp["L"] ** 2 for rp in reps)) * sweeps
-    tiles, tuned, wpg = None, None, 0
+    tiles, tuned, wpg, branches = None, None, 0, 0
     if autotune:
         t0 = time.perf_counter()
-        tiles, chunk, wpg, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
+        tiles, chunk, wpg, branches, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
         tuned = {"tiles_by_L": {int(rp["L"]): int(w) for rp, w in zip(reps, tiles)}, "chunk": chunk,
-                 "waves_per_group": wpg, "probe_ms_per_sweep": ms, "tuning_s": time.perf_counter() - t0}
-    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg)
+                 "waves_per_group": wpg, "branches": branches, "probe_ms_per_sweep": ms,
+                 "tuning_s": time.perf_counter() - t0}
+    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg, branches=branches)
     ens.sweep(min(chunk, sweeps), want_counts=False)  # first replay builds the graph
     torch.cuda.synchronize()
     ens.close()
-    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg)
+    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg, branches=branches)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ens.sweep(sweeps, want_counts=False)
@@ -323,14 +324,17 @@ def paper_workload_pass(pgg, torch, warmup, steps, stream):
                     "measured on other hardware"}
 
 
-def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64, chunk=16):
+def serving_pass(pgg, n_jobs, stream, budget_mib=256, chunk=16, max_resident=64):
     """Poisson arrivals of simulation jobs through the C job server at 70 %
-    of its capacity.  The capacity is measured first: calib_jobs jobs of the
-    same distribution all submitted at once (a closed batch)."""
+    of its capacity.  The capacity is measured first: 4 x max_resident jobs
+    of the same distribution submitted at once, at most max_resident of them
+    on the device, and the rate over the steps that began with jobs still
+    queued (the server saturated, before the batch drains)."""
     from paper_1704_08098_amd import server
 
     def run(jobs):
-        engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, chunk=chunk, stream=stream)
+        engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, max_resident=max_resident, chunk=chunk,
+                                  stream=stream)
         try:
             rep = server.serve(engine, jobs)
         finally:
@@ -338,18 +342,22 @@ def serving_pass(pgg, n_jobs, stream, budget_mib=256, calib_jobs=64, chunk=16):
         rep.pop("engine", None)
         return rep
 
+    calib_jobs = 4 * max_resident
     calib = wl.serving_trace(calib_jobs, 1.0, master_seed=11)
     for j in calib:
         j["arrival"] = 0.0
     cal = run(calib)
-    capacity = cal["site_updates_per_s"]
+    capacity = cal["site_updates_per_s_saturated"]
     probe = wl.serving_trace(n_jobs, 1.0)
     mean_work = sum(float(j["L"]) ** 2 * j["sweeps"] for j in probe) / n_jobs
     rate = 0.7 * capacity / mean_work
     rep = run(wl.serving_trace(n_jobs, rate))
     rep.update({"arrival_rate_per_s": rate, "offered_load": 0.7, "capacity_site_updates_per_s": capacity,
-                "capacity_basis": "%d jobs of the same distribution submitted at once (closed batch)" % calib_jobs,
-                "hbm_budget_MiB": budget_mib, "chunk": chunk,
+                "capacity_basis": "%d jobs of the same distribution submitted at once, at most %d resident: the "
+                                  "rate over the %.2f s of steps that began with jobs still queued (the whole "
+                                  "batch, drain included: %.3g)" % (calib_jobs, max_resident, cal["saturated_s"],
+                                                                    cal["site_updates_per_s"]),
+                "hbm_budget_MiB": budget_mib, "chunk": chunk, "max_resident": max_resident,
                 "trace": "Poisson arrivals; L log-uniform in [64, 2048] (multiples of 4), r ~ U[3.5, 5.6], "
                          "MCS ~ U{1000..10000}, p0 ~ U[0.1, 0.9], seed 7"})
     return rep
@@ -470,6 +478,7 @@ def main():
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
     ap.add_argument("--serve-chunk", type=int, default=16, help="sweeps per server step")
+    ap.add_argument("--serve-resident", type=int, default=64, help="most jobs on the device at once")
     ap.add_argument("--no-paper-workload", dest="paper_workload", action="store_false",
                     help="skip the paper's own workload (double tiling, L = 4096, r = 3.98)")
     ap.add_argument("--no-decay-batch", dest="decay_batch", action="store_false",
@@ -596,7 +605,7 @@ def main():
     serving = None
     if args.serve_jobs > 0:
         log("serving pass: capacity batch, then %d jobs" % args.serve_jobs)
-        serving = serving_pass(pgg, args.serve_jobs, stream, chunk=args.serve_chunk)
+        serving = serving_pass(pgg, args.serve_jobs, stream, chunk=args.serve_chunk, max_resident=args.serve_resident)
 
     scan = None
     if args.scan_sweeps > 0:

@@ -366,12 +366,19 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
  *              workgroup serves one replica and shares one copy of its
  *              threshold table; each replica's waves are padded to whole
  *              workgroups.
+ *   branches   concurrent replica groups, 0..16 (0 or 1: one): the replicas
+ *              are cut into this many contiguous ranges of about equal work
+ *              (sum of L^2), each range's chunk is its own chain of launches,
+ *              and the chains run side by side as parallel branches of the
+ *              chunk's graph.  Results never depend on it.  The tiled
+ *              schedule takes 0 or 1.
  *   hip_stream stream to order the work on; NULL: the ensemble creates and
  *              owns a stream of default priority (graphs cannot capture the
  *              null stream).
  * Synchronises the stream once. */
 pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles,
-                               uint32_t chunk, uint32_t waves_per_group, void* hip_stream, pgg_ensemble** out);
+                               uint32_t chunk, uint32_t waves_per_group, uint32_t branches, void* hip_stream,
+                               pgg_ensemble** out);
 
 /* Advance every replica n_sweeps sweeps.  counts: NULL, or host array of
  * n_reps rows of n_sweeps entries receiving N_C after each sweep (row k is
@@ -396,8 +403,8 @@ pgg_status pgg_ensemble_threshold_table(pgg_ensemble* e, uint32_t rep, uint32_t*
 void pgg_ensemble_destroy(pgg_ensemble* e);
 
 /* Autotune the batched launch for a set of replicas: the segment width of
- * each distinct L, the waves per workgroup and the chunk length of a graph
- * replay.  Results never depend on them; only the speed does.
+ * each distinct L, the waves per workgroup, the concurrent replica groups
+ * and the chunk length of a graph replay.  Results never depend on them; only the speed does.
  *   reps, n_reps  as for pgg_ensemble_create, schedule COLOUR16 (the tiled
  *                 schedule has nothing to tune: PGG_E_INVAL).
  *   probe_sweeps  sweeps timed per trial, 1..4096 (after 2 untimed ones).
@@ -406,19 +413,41 @@ void pgg_ensemble_destroy(pgg_ensemble* e);
  *                 (equal for equal L).
  *   chunk_out     the chosen chunk length.
  *   wpg_out       the chosen waves per workgroup.
+ *   branches_out  the chosen number of concurrent replica groups.
  *   ms_out        NULL, or the best time per sweep of the whole ensemble.
  * Trials run on trial ensembles created from reps (fresh initial states
  * each): first the width of each distinct L in turn over the doublings
  * 64, 128, ... below L - 32, L - 32 rounded down to a multiple of 32, and
  * whole rows (L, when L is a multiple of 32),
  * the other sizes held at their best so far, then the waves per workgroup
- * over 2, 4, 8, then the chunk over 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
+ * over 2, 4, 8, then the concurrent groups over 1, 2, 4, then the chunk
+ * over 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
  * trial's final cooperator counts must equal the first trial's, else
  * PGG_E_DEVICE with a message (a tuning-dependent result would be a bug).
  * Needs the device memory of one trial ensemble at chunk 128. */
 pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps,
                                  void* hip_stream, uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out,
-                                 double* ms_out);
+                                 uint32_t* branches_out, double* ms_out);
+
+/* Tuning of a batched run (pgg_ensemble_run): the arguments of
+ * pgg_ensemble_create that only change the speed.  tiles: NULL (automatic)
+ * or host array of n_reps segment widths. */
+typedef struct {
+    const uint32_t* tiles;
+    uint32_t chunk;           /* 1..1024                         */
+    uint32_t waves_per_group; /* 0, 2, 4 or 8                    */
+    uint32_t branches;        /* 0..16                           */
+} pgg_ensemble_tune;
+
+/* One batched run from the initial states: create the ensemble of reps,
+ * advance every replica n_sweeps sweeps, release it.  counts: NULL, or host
+ * array of n_reps rows of n_sweeps entries (N_C after each sweep, row k =
+ * replica k).  tune: NULL to autotune first (pgg_ensemble_autotune with 8
+ * probe sweeps; the tiled schedule takes the defaults), else the settings
+ * to use.  Each replica's counts are those of pgg_init + pgg_sweep with its
+ * parameters.  Synchronises. */
+pgg_status pgg_ensemble_run(const pgg_params* reps, uint32_t n_reps, uint32_t n_sweeps, uint64_t* counts,
+                            const pgg_ensemble_tune* tune, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Job server: continuous batching of simulation jobs on one GPU.  Jobs are
@@ -427,8 +456,10 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
  * (pgg_server_job_bytes) fits the HBM budget, then any later job that still
  * fits (backfill), drawing their initial states on the device; (2) advances
  * every resident job by min(chunk, remaining) sweeps in the same launches,
- * each at its own sweep index; (3) copies the chunk's counts out and retires
- * finished jobs (final lattice copied out, device space freed).  Lattices
+ * each at its own sweep index, replayed from a hipGraph captured once per
+ * bucket of resident-replica slots and waves (idle replicas pad the table);
+ * (3) copies the chunk's counts out and retires finished jobs (final
+ * lattices copied out with one synchronisation, device space freed).  Lattices
  * stay resident for a job's whole life.  A job's counts and final lattice
  * are exactly those of pgg_init + pgg_sweep with the same parameters.
  * Not thread-safe; one server per thread.
@@ -462,7 +493,9 @@ pgg_status pgg_server_create(size_t hbm_budget, uint32_t max_L, uint32_t max_res
                              void* hip_stream, pgg_server** out);
 
 /* Queue a job: p (host, copied; 64 <= L <= max_L, layout BITS, kernel AUTO
- * or SEGMENT, schedule COLOUR16) and n_sweeps >= 1.  A job whose footprint exceeds the whole
+ * or SEGMENT, schedule COLOUR16, game 0; tile 0 or a segment width whose
+ * LDS fits the server's launches, which reserve the widest automatic layout
+ * up to max_L) and n_sweeps >= 1.  A job whose footprint exceeds the whole
  * budget is PGG_E_INVAL.  job_id (host) receives its id.  Host only. */
 pgg_status pgg_server_submit(pgg_server* s, const pgg_params* p, uint32_t n_sweeps, uint64_t* job_id);
 

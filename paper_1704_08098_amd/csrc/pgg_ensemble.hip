@@ -292,8 +292,11 @@ int auto_segw(int L) {
     if (L % 32 == 0 && L <= 1024) return L;  // whole rows
     // About 1376 columns: at the drawn fraction of a lattice near r_c (about
     // 15 % of the sites) a class then lists about 50 sites, most of one
-    // 64-lane pass; the row is split into equal segments of that order.
-    const int nseg = (L + 1375) / 1376;
+    // 64-lane pass; the row is split into equal segments of that order.  A
+    // segment is at most L - 32 columns, so a row always takes two or more:
+    // split it evenly (one segment of L - 32 columns and one of the rest
+    // would leave the second wave almost empty).
+    const int nseg = std::max(2, (L + 1375) / 1376);
     int w = (L / nseg + 31) & ~31;
     const int cap = (L - 32) & ~31;
     if (w > cap) w = cap;
@@ -414,6 +417,16 @@ struct pgg_ensemble {
     // blocking stream is invalidated by another thread's null-stream work)
     // and launched on `stream`.
     hipStream_t capture_stream = nullptr;
+    // Concurrent replica groups: the replicas are cut into `branches`
+    // contiguous ranges of about equal work (sum of L^2); each range's chunk
+    // is its own chain of launches, and the chains run side by side as
+    // parallel branches of the chunk's graph (so one range's launch tails
+    // overlap the other ranges' launches).  Group g: replicas first[g] ..
+    // first[g] + count[g] - 1, waves[g] waves per launch.
+    int branches = 1;
+    std::vector<int> grp_first, grp_count, grp_waves;
+    std::vector<hipStream_t> branch_streams;
+    std::vector<hipEvent_t> branch_events;  // fork event, then one join event per branch
     int device = 0;
     int n = 0;
     int chunk = 32;          // sweeps per graph replay
@@ -460,6 +473,8 @@ void ens_release(pgg_ensemble* e) {
     if (e->d_counts) (void)hipFree(e->d_counts);
     if (e->d_nc) (void)hipFree(e->d_nc);
     if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
+    for (hipStream_t bs : e->branch_streams) (void)hipStreamDestroy(bs);
+    for (hipEvent_t ev : e->branch_events) (void)hipEventDestroy(ev);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -467,8 +482,22 @@ void ens_release(pgg_ensemble* e) {
 hipError_t enqueue_chunk(pgg_ensemble* e, int len, hipStream_t st) {
     if (e->tiled)
         return pgg::launch_ens_tiled_chunk(e->d_reps, e->n, e->total_waves, len, e->chunk, e->d_counts, st);
-    return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts, st,
-                                 e->wpg);
+    if (e->branches == 1)
+        return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts, st,
+                                     e->wpg);
+    // fork: every branch waits for the work before it on st, runs its range's
+    // chunk, and st waits for every branch (a graph with parallel branches)
+    hipError_t err = hipEventRecord(e->branch_events[0], st);
+    for (int g = 0; err == hipSuccess && g < e->branches; ++g) {
+        hipStream_t bs = e->branch_streams[g];
+        err = hipStreamWaitEvent(bs, e->branch_events[0], 0);
+        if (err == hipSuccess)
+            err = pgg::launch_ens_chunk(e->d_reps + e->grp_first[g], e->grp_count[g], e->grp_waves[g], e->lds, len,
+                                        e->chunk, true, e->d_counts + (size_t)e->grp_first[g] * e->chunk, bs, e->wpg);
+        if (err == hipSuccess) err = hipEventRecord(e->branch_events[1 + g], bs);
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, e->branch_events[1 + g], 0);
+    }
+    return err;
 }
 
 hipError_t graph_for(pgg_ensemble* e, int len, hipGraphExec_t* out) {
@@ -526,13 +555,15 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
 extern "C" {
 
 pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk,
-                               uint32_t waves_per_group, void* hip_stream, pgg_ensemble** out) {
+                               uint32_t waves_per_group, uint32_t branches, void* hip_stream, pgg_ensemble** out) {
     if (!out) { eerr("out is NULL"); return PGG_E_INVAL; }
     *out = nullptr;
     const pgg_status vs = validate_reps(reps, n_reps, tiles, chunk);
     if (vs != PGG_OK) return vs;
     const int wpg = waves_per_group ? (int)waves_per_group : pgg::kWavesPerGroup;
     if (!pgg::ens_wpg_valid(wpg)) { eerr("waves_per_group must be 0, 2, 4 or 8"); return PGG_E_INVAL; }
+    if (branches > 16) { eerr("branches must lie in [0, 16]"); return PGG_E_INVAL; }
+    if (branches > 1 && reps[0].schedule == PGG_SCHEDULE_TILED) { eerr("the tiled schedule runs one branch"); return PGG_E_INVAL; }
     pgg_ensemble* e = new (std::nothrow) pgg_ensemble();
     if (!e) { eerr("host allocation failed"); return PGG_E_NOMEM; }
     e->stream = (hipStream_t)hip_stream;
@@ -569,6 +600,54 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     }
     e->total_waves = waves;
     e->lds = e->tiled ? 0 : pgg::ens_lds_bytes(max_words, wpg);
+    // contiguous replica ranges of about equal work; wave_base restarts in each
+    e->branches = std::max(1, std::min<int>(branches ? (int)branches : 1, (int)n_reps));
+    {
+        double total_work = 0.0;
+        for (uint32_t k = 0; k < n_reps; ++k) total_work += (double)reps[k].L * (double)reps[k].L;
+        double acc = 0.0;
+        int g = 0, base = 0;
+        e->grp_first.assign(1, 0);
+        for (uint32_t k = 0; k < n_reps; ++k) {
+            pgg::EnsRep& rp = e->host_reps[k];
+            // start the next range once this one holds its share of the work
+            // (every range keeps at least one replica)
+            if (g + 1 < e->branches && k > (uint32_t)e->grp_first[g] &&
+                acc >= total_work * (double)(g + 1) / (double)e->branches) {
+                e->grp_waves.push_back(base);
+                e->grp_count.push_back((int)k - e->grp_first[g]);
+                e->grp_first.push_back((int)k);
+                ++g;
+                base = 0;
+            }
+            rp.wave_base = base;
+            if (!e->tiled) base += pgg::ens_waves(rp, wpg);
+            acc += (double)reps[k].L * (double)reps[k].L;
+        }
+        e->grp_waves.push_back(base);
+        e->grp_count.push_back((int)n_reps - e->grp_first[g]);
+        e->branches = g + 1;
+        if (e->tiled) {  // the tiled schedule keeps its one range and its own wave bases
+            e->grp_first.assign(1, 0);
+            e->grp_count.assign(1, (int)n_reps);
+            e->grp_waves.assign(1, waves);
+            int wb = 0;
+            for (uint32_t k = 0; k < n_reps; ++k) {
+                e->host_reps[k].wave_base = wb;
+                wb += pgg::tiled_blocks(e->host_reps[k].L);
+            }
+        }
+    }
+    for (int g = 0; e->branches > 1 && g < e->branches; ++g) {
+        hipStream_t bs = nullptr;
+        if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) { eerr("stream creation failed"); ens_release(e); return PGG_E_DEVICE; }
+        e->branch_streams.push_back(bs);
+    }
+    for (int g = 0; e->branches > 1 && g <= e->branches; ++g) {
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { eerr("event creation failed"); ens_release(e); return PGG_E_DEVICE; }
+        e->branch_events.push_back(ev);
+    }
     if (e->lds > pgg::kMaxDynamicLds) {
         eerr("the widest replica layout (%d LDS words per wave) does not fit %d waves per workgroup", max_words, wpg);
         ens_release(e);
@@ -690,8 +769,9 @@ pgg_status pgg_ensemble_threshold_table(pgg_ensemble* e, uint32_t rep, uint32_t*
 void pgg_ensemble_destroy(pgg_ensemble* e) { ens_release(e); }
 
 pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps, void* hip_stream,
-                                 uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out, double* ms_out) {
-    if (!reps || !tiles_out || !chunk_out || !wpg_out) { eerr("NULL argument"); return PGG_E_INVAL; }
+                                 uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out, uint32_t* branches_out,
+                                 double* ms_out) {
+    if (!reps || !tiles_out || !chunk_out || !wpg_out || !branches_out) { eerr("NULL argument"); return PGG_E_INVAL; }
     if (probe_sweeps == 0 || probe_sweeps > 4096) { eerr("probe_sweeps must lie in [1, 4096]"); return PGG_E_INVAL; }
     const pgg_status vs = validate_reps(reps, n_reps, nullptr, 1);
     if (vs != PGG_OK) return vs;
@@ -701,7 +781,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         if (std::find(sizes.begin(), sizes.end(), reps[k].L) == sizes.end()) sizes.push_back(reps[k].L);
     std::map<uint32_t, uint32_t> width;  // current choice per L (0 = automatic)
     for (uint32_t L : sizes) width[L] = 0;
-    uint32_t chunk = 32, wpg = (uint32_t)pgg::kWavesPerGroup;
+    uint32_t chunk = 32, wpg = (uint32_t)pgg::kWavesPerGroup, branches = 1;
     std::vector<uint64_t> fingerprint, nc(n_reps);
     std::vector<uint32_t> tiles(n_reps);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -714,7 +794,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     auto trial = [&](double* ms) -> pgg_status {
         for (uint32_t k = 0; k < n_reps; ++k) tiles[k] = width[reps[k].L];
         pgg_ensemble* e = nullptr;
-        pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.data(), chunk, wpg, hip_stream, &e);
+        pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.data(), chunk, wpg, branches, hip_stream, &e);
         if (st != PGG_OK) return st;
         st = pgg_ensemble_sweep(e, 2, nullptr);
         double best = 1e300;
@@ -773,6 +853,16 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_wpg = g; }
     }
     wpg = best_wpg;
+    const uint32_t branch_counts[] = {1, 2, 4};
+    uint32_t best_branches = branches;
+    for (uint32_t bcount : branch_counts) {
+        if (st != PGG_OK || bcount == best_branches || bcount > n_reps) continue;
+        branches = bcount;
+        double ms = 0.0;
+        st = trial(&ms);
+        if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_branches = bcount; }
+    }
+    branches = best_branches;
     const uint32_t chunks[] = {8, 16, 32, 64, 128};
     uint32_t best_chunk = chunk;
     for (uint32_t c : chunks) {
@@ -797,8 +887,39 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     }
     *chunk_out = best_chunk;
     *wpg_out = best_wpg;
+    *branches_out = best_branches;
     if (ms_out) *ms_out = best_ms;
     return PGG_OK;
+}
+
+pgg_status pgg_ensemble_run(const pgg_params* reps, uint32_t n_reps, uint32_t n_sweeps, uint64_t* counts,
+                            const pgg_ensemble_tune* tune, void* hip_stream) {
+    const pgg_status vs = validate_reps(reps, n_reps, tune ? tune->tiles : nullptr, tune ? tune->chunk : 1);
+    if (vs != PGG_OK) return vs;
+    std::vector<uint32_t> tiles;
+    uint32_t chunk = 32, wpg = 0, branches = 0;
+    if (tune) {
+        chunk = tune->chunk;
+        wpg = tune->waves_per_group;
+        branches = tune->branches;
+        if (tune->tiles) tiles.assign(tune->tiles, tune->tiles + n_reps);
+    } else if (reps[0].schedule != PGG_SCHEDULE_TILED) {
+        tiles.resize(n_reps);
+        const pgg_status st = pgg_ensemble_autotune(reps, n_reps, 8, hip_stream, tiles.data(), &chunk, &wpg,
+                                                    &branches, nullptr);
+        if (st != PGG_OK) return st;
+    }
+    pgg_ensemble* e = nullptr;
+    pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.empty() ? nullptr : tiles.data(), chunk, wpg, branches,
+                                        hip_stream, &e);
+    if (st != PGG_OK) return st;
+    st = pgg_ensemble_sweep(e, n_sweeps, counts);
+    if (st == PGG_OK) {
+        const hipError_t err = hipStreamSynchronize(e->stream);
+        if (err != hipSuccess) st = efail(e, err, "ensemble run");
+    }
+    pgg_ensemble_destroy(e);
+    return st;
 }
 
 }  // extern "C"

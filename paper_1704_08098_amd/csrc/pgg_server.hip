@@ -101,6 +101,18 @@ struct pgg_server {
     unsigned long long* d_counts = nullptr;  // max_resident x chunk
     uint8_t* d_stage = nullptr;              // max_L^2 bytes for lattice read-out
     pgg::EnsRep* h_reps = nullptr;           // pinned staging of the replica table
+    // A step's launches (a chunk of every resident job) are replayed from a
+    // hipGraph captured once per (replica slots, waves) bucket: the replica
+    // table is padded with idle replicas (n_active 0) up to the bucket's
+    // slot count and the waves up to the bucket's wave count, so the same
+    // graph serves every step with that bucket whatever jobs are resident.
+    hipStream_t capture_stream = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+    uint32_t slots = 0;                      // d_reps / h_reps entries (max_resident rounded up)
+    size_t lds = 0;                          // LDS of any job's waves (the largest over the sizes accepted)
+    char* d_idle = nullptr;                  // buffers the idle replicas point at
+    pgg::EnsRep idle{};
     std::vector<unsigned long long> h_counts;
     std::deque<uint64_t> queue;
     std::vector<uint64_t> resident;
@@ -189,6 +201,43 @@ hipError_t admit(pgg_server* s, uint64_t id, Job& j) {
     return e;
 }
 
+// Buckets: replica slots rounded up to a power of two (at least 8), waves up
+// to a multiple of an eighth of their power of two (at least 64), so that the
+// padding costs at most about an eighth of a launch in idle workgroups.
+int slot_bucket(int n) {
+    int b = 8;
+    while (b < n) b <<= 1;
+    return b;
+}
+int wave_bucket(int w) {
+    int p = 64;
+    while (p < w) p <<= 1;
+    const int step = std::max(64, p / 8);
+    return (w + step - 1) / step * step;
+}
+
+// The graph of one step for a bucket (captured on first use).
+hipError_t step_graph(pgg_server* s, int slots, int waves, hipGraphExec_t* out) {
+    const auto key = std::make_pair(slots, waves);
+    auto it = s->graphs.find(key);
+    if (it != s->graphs.end()) { *out = it->second; return hipSuccess; }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t enq = pgg::launch_ens_chunk(s->d_reps, slots, waves, s->lds, (int)s->chunk, (int)s->chunk, false,
+                                                 s->d_counts, s->capture_stream);
+    e = hipStreamEndCapture(s->capture_stream, &g);
+    if (enq != hipSuccess) { if (g) (void)hipGraphDestroy(g); return enq; }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return e; }
+    s->graph_defs.push_back(g);
+    s->graphs[key] = ex;
+    *out = ex;
+    return hipSuccess;
+}
+
 void server_release(pgg_server* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
@@ -197,6 +246,10 @@ void server_release(pgg_server* s) {
     if (s->d_counts) (void)hipFree(s->d_counts);
     if (s->d_stage) (void)hipFree(s->d_stage);
     if (s->h_reps) (void)hipHostFree(s->h_reps);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : s->graph_defs) (void)hipGraphDestroy(g);
+    if (s->d_idle) (void)hipFree(s->d_idle);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -228,18 +281,49 @@ pgg_status pgg_server_create(size_t hbm_budget, uint32_t max_L, uint32_t max_res
         e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
         s->own_stream = (e == hipSuccess);
     }
+    s->slots = (uint32_t)slot_bucket((int)max_resident);
+    // the widest wave layout over every side a job may have
+    {
+        int words = 0;
+        for (uint32_t L = 64; L <= max_L; L += 4) {
+            pgg::EnsRep rp;
+            std::memset(&rp, 0, sizeof(rp));
+            pgg::ens_geometry(rp, (int)L, 0);
+            words = std::max(words, pgg::ens_wave_words(rp));
+        }
+        s->lds = pgg::ens_lds_bytes(words);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_arena, s->budget);
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d_reps, (size_t)max_resident * sizeof(pgg::EnsRep));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d_counts, (size_t)max_resident * chunk * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_reps, (size_t)s->slots * sizeof(pgg::EnsRep));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_counts, (size_t)s->slots * chunk * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_stage, (size_t)max_L * max_L);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_reps, (size_t)max_resident * sizeof(pgg::EnsRep), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_reps, (size_t)s->slots * sizeof(pgg::EnsRep), 0);
+    // idle replicas: an L = 64 geometry, no active sweeps, and small buffers
+    // for the table, counters and N_C that the bookkeeping kernels touch
+    const size_t idle_tab = align_up(160 * sizeof(uint32_t));
+    const size_t idle_del = align_up((size_t)chunk * pgg::kSweepWords * sizeof(unsigned long long));
+    const size_t idle_lat = align_up(job_lattice_words(64) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_idle, idle_tab + idle_del + 2 * idle_lat + kAlign);
+    if (e == hipSuccess) {
+        std::memset(&s->idle, 0, sizeof(s->idle));
+        pgg::ens_geometry(s->idle, 64, 0);
+        s->idle.T = (const uint32_t*)s->d_idle;
+        s->idle.delta = (unsigned long long*)(s->d_idle + idle_tab);
+        s->idle.lat = (uint32_t*)(s->d_idle + idle_tab + idle_del);
+        s->idle.lat2 = (uint32_t*)(s->d_idle + idle_tab + idle_del + idle_lat);
+        s->idle.nc = (unsigned long long*)(s->d_idle + idle_tab + idle_del + 2 * idle_lat);
+        s->idle.n_active = 0;
+        e = hipMemsetAsync(s->d_idle, 0, idle_tab + idle_del + 2 * idle_lat + kAlign, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
     if (e != hipSuccess) {
         serr("server allocation failed: %s", hipGetErrorString(e));
         const bool oom = e == hipErrorOutOfMemory;
         server_release(s);
         return oom ? PGG_E_NOMEM : PGG_E_DEVICE;
     }
-    s->h_counts.resize((size_t)max_resident * chunk);
+    s->h_counts.resize((size_t)s->slots * chunk);
     *out = s;
     return PGG_OK;
 }
@@ -251,6 +335,16 @@ pgg_status pgg_server_submit(pgg_server* s, const pgg_params* p, uint32_t n_swee
     if (!job_params_ok(p, s->max_L, &why)) { serr("invalid job: %s", why); return PGG_E_INVAL; }
     if (n_sweeps == 0) { serr("a job needs at least one sweep"); return PGG_E_INVAL; }
     if (job_footprint(p->L, s->chunk) > s->budget) { serr("the job's footprint exceeds the whole budget"); return PGG_E_INVAL; }
+    {
+        // a step's launches reserve the LDS of the widest automatic layout
+        pgg::EnsRep rp;
+        std::memset(&rp, 0, sizeof(rp));
+        pgg::ens_geometry(rp, (int)p->L, (int)p->tile);
+        if (pgg::ens_lds_bytes(pgg::ens_wave_words(rp)) > s->lds) {
+            serr("the job's tile needs more LDS per workgroup than the server's launches reserve (use tile 0)");
+            return PGG_E_INVAL;
+        }
+    }
     const uint64_t id = s->next_id++;
     Job& j = s->jobs[id];
     j.p = *p;
@@ -284,8 +378,11 @@ pgg_status pgg_server_step(pgg_server* s, uint32_t* n_resident) {
     if (n_resident) *n_resident = (uint32_t)n;
     if (n == 0) return PGG_OK;
 
-    // (2) one chunk for every resident job, each at its own sweep index.
-    int waves = 0, max_words = 0, len_max = 0;
+    // (2) one chunk for every resident job, each at its own sweep index: the
+    // replica table (padded with idle replicas to the bucket's slots) goes up,
+    // and the bucket's graph runs chunk sweeps -- a job with fewer sweeps
+    // left runs only its own n_active of them.
+    int waves = 0;
     for (int k = 0; k < n; ++k) {
         Job& j = s->jobs[s->resident[k]];
         pgg::EnsRep rp = j.rep;
@@ -293,21 +390,27 @@ pgg_status pgg_server_step(pgg_server* s, uint32_t* n_resident) {
         rp.n_active = (int)std::min<uint32_t>(s->chunk, j.n_sweeps - j.done);
         rp.wave_base = waves;
         waves += pgg::ens_waves(rp);
-        max_words = std::max(max_words, pgg::ens_wave_words(rp));
-        len_max = std::max(len_max, (int)std::min<uint32_t>(s->chunk, j.n_sweeps - j.done));
         s->h_reps[k] = rp;
     }
-    SRV_HIP(s, hipMemcpyAsync(s->d_reps, s->h_reps, (size_t)n * sizeof(pgg::EnsRep), hipMemcpyHostToDevice, s->stream));
-    // Launches cover len_max sweeps; a job with fewer remaining sweeps runs
-    // only its own n_active of them.
-    SRV_HIP(s, pgg::launch_ens_chunk(s->d_reps, n, waves, pgg::ens_lds_bytes(max_words), len_max, (int)s->chunk,
-                                     false, s->d_counts, s->stream));
+    const int slots = std::min<int>(slot_bucket(n), (int)s->slots);
+    const int wave_pad = wave_bucket(waves);
+    for (int k = n; k < slots; ++k) {
+        s->h_reps[k] = s->idle;
+        s->h_reps[k].wave_base = wave_pad;  // owns no wave of the launch
+    }
+    hipGraphExec_t g = nullptr;
+    SRV_HIP(s, step_graph(s, slots, wave_pad, &g));
+    SRV_HIP(s, hipMemcpyAsync(s->d_reps, s->h_reps, (size_t)slots * sizeof(pgg::EnsRep), hipMemcpyHostToDevice,
+                              s->stream));
+    SRV_HIP(s, hipGraphLaunch(g, s->stream));
     SRV_HIP(s, hipMemcpyAsync(s->h_counts.data(), s->d_counts, (size_t)n * s->chunk * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s->stream));
     SRV_HIP(s, hipStreamSynchronize(s->stream));
 
-    // (3) collect counts, retire finished jobs.
-    std::vector<uint64_t> still;
+    // (3) collect counts, retire finished jobs: every finished lattice is
+    // unpacked and copied out in stream order (the staging buffer is reused
+    // in turn), with one synchronisation for all of them.
+    std::vector<uint64_t> still, retired;
     still.reserve(n);
     for (int k = 0; k < n; ++k) {
         const uint64_t id = s->resident[k];
@@ -321,7 +424,11 @@ pgg_status pgg_server_step(pgg_server* s, uint32_t* n_resident) {
         j.lattice.resize(cells);
         SRV_HIP(s, pgg::launch_unpack(j.rep.lat, s->d_stage, j.rep.L, j.rep.stride, s->stream));
         SRV_HIP(s, hipMemcpyAsync(j.lattice.data(), s->d_stage, cells, hipMemcpyDeviceToHost, s->stream));
-        SRV_HIP(s, hipStreamSynchronize(s->stream));
+        retired.push_back(id);
+    }
+    if (!retired.empty()) SRV_HIP(s, hipStreamSynchronize(s->stream));
+    for (uint64_t id : retired) {
+        Job& j = s->jobs[id];
         j.state = kDone;
         s->arena.release(j.off, j.bytes);
         s->completed.push_back(id);

@@ -39,7 +39,7 @@ EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_kernel_span", "pgg_set_strip_wait", "pgg_destroy",
            "pgg_last_error", "pgg_ensemble_create", "pgg_ensemble_sweep", "pgg_ensemble_coop_counts",
            "pgg_ensemble_sweep_index", "pgg_ensemble_read_lattice", "pgg_ensemble_destroy",
-           "pgg_ensemble_autotune", "pgg_ensemble_threshold_table",
+           "pgg_ensemble_autotune", "pgg_ensemble_threshold_table", "pgg_ensemble_run",
            "pgg_server_job_bytes", "pgg_server_create", "pgg_server_submit", "pgg_server_step",
            "pgg_server_completed", "pgg_server_job_state", "pgg_server_job_result", "pgg_server_stats",
            "pgg_server_destroy", "pgg_sweep_static_scratch_bytes", "pgg_sweep_static")
@@ -50,6 +50,11 @@ class PggParams(ctypes.Structure):
                 ("p0", ctypes.c_double), ("seed", ctypes.c_uint64), ("layout", ctypes.c_uint32),
                 ("kernel", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("group", ctypes.c_uint32),
                 ("schedule", ctypes.c_uint32), ("game", ctypes.c_uint32)]
+
+
+class PggEnsembleTune(ctypes.Structure):
+    _fields_ = [("tiles", ctypes.POINTER(ctypes.c_uint32)), ("chunk", ctypes.c_uint32),
+                ("waves_per_group", ctypes.c_uint32), ("branches", ctypes.c_uint32)]
 
 
 class PggServerInfo(ctypes.Structure):
@@ -96,15 +101,17 @@ def load():
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
         "pgg_ensemble_create": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, u32p, ctypes.c_uint32,
-                                               ctypes.c_uint32, vp, P(vp)]),
+                                               ctypes.c_uint32, ctypes.c_uint32, vp, P(vp)]),
         "pgg_ensemble_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, u64p]),
         "pgg_ensemble_coop_counts": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_read_lattice": (ctypes.c_int, [vp, ctypes.c_uint32, u8p]),
         "pgg_ensemble_destroy": (None, [vp]),
         "pgg_ensemble_threshold_table": (ctypes.c_int, [vp, ctypes.c_uint32, u32p]),
+        "pgg_ensemble_run": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, u64p,
+                                            P(PggEnsembleTune), vp]),
         "pgg_ensemble_autotune": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, vp, u32p, u32p,
-                                                 u32p, P(ctypes.c_double)]),
+                                                 u32p, u32p, P(ctypes.c_double)]),
         "pgg_server_job_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
         "pgg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                              vp, P(vp)]),
@@ -341,17 +348,40 @@ def _replica_params(replicas):
 
 
 def ensemble_autotune(replicas, probe_sweeps=8, stream=None):
-    """pgg_ensemble_autotune: (tiles per replica, chunk, waves per group, ms per sweep)."""
+    """pgg_ensemble_autotune: (tiles per replica, chunk, waves per group,
+    concurrent replica groups, ms per sweep)."""
     n = len(replicas)
     arr = _replica_params(replicas)
     tiles = np.zeros(n, dtype=np.uint32)
     chunk = ctypes.c_uint32()
     wpg = ctypes.c_uint32()
+    branches = ctypes.c_uint32()
     ms = ctypes.c_double()
     _check(load().pgg_ensemble_autotune(arr, n, int(probe_sweeps), _stream_handle(stream),
                                         tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
-                                        ctypes.byref(chunk), ctypes.byref(wpg), ctypes.byref(ms)))
-    return tiles, int(chunk.value), int(wpg.value), float(ms.value)
+                                        ctypes.byref(chunk), ctypes.byref(wpg), ctypes.byref(branches),
+                                        ctypes.byref(ms)))
+    return tiles, int(chunk.value), int(wpg.value), int(branches.value), float(ms.value)
+
+
+def ensemble_run(replicas, n_sweeps, tune=None, stream=None):
+    """pgg_ensemble_run: counts (n_reps, n_sweeps) of one batched run from the
+    initial states.  tune: None (autotune) or a dict with chunk,
+    waves_per_group, branches and optionally tiles."""
+    n = len(replicas)
+    arr = _replica_params(replicas)
+    out = np.zeros((n, max(int(n_sweeps), 1)), dtype=np.uint64)
+    t = None
+    if tune is not None:
+        tl = None
+        if tune.get("tiles") is not None:
+            tl = np.ascontiguousarray(np.asarray(tune["tiles"], dtype=np.uint32))
+        t = PggEnsembleTune(tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None else None,
+                            int(tune.get("chunk", 32)), int(tune.get("waves_per_group", 0)),
+                            int(tune.get("branches", 0)))
+    _check(load().pgg_ensemble_run(arr, n, int(n_sweeps), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   ctypes.byref(t) if t is not None else None, _stream_handle(stream)))
+    return out[:, :n_sweeps]
 
 
 class Ensemble:
@@ -360,9 +390,10 @@ class Ensemble:
     replicas: sequence of dicts with L, r and optionally K, p0, seed.
     tiles: optional per-replica segment widths (0 = automatic).
     waves_per_group: segment waves per workgroup, 2, 4 or 8 (0 = 4).
+    branches: concurrent replica groups (parallel graph branches), 0..16.
     """
 
-    def __init__(self, replicas, tiles=None, chunk=32, stream=None, waves_per_group=0):
+    def __init__(self, replicas, tiles=None, chunk=32, stream=None, waves_per_group=0, branches=0):
         lib = load()
         n = len(replicas)
         arr = _replica_params(replicas)
@@ -376,8 +407,8 @@ class Ensemble:
         h = ctypes.c_void_p()
         _check(lib.pgg_ensemble_create(arr, n,
                                        tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None
-                                       else None, int(chunk), int(waves_per_group), _stream_handle(stream),
-                                       ctypes.byref(h)))
+                                       else None, int(chunk), int(waves_per_group), int(branches),
+                                       _stream_handle(stream), ctypes.byref(h)))
         self.handle = h
 
     def sweep(self, n_sweeps, want_counts=True):

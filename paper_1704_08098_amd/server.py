@@ -4,7 +4,9 @@ Jobs arrive over time (e.g. a Poisson trace from workloads.serving_trace);
 the loop submits every job whose arrival time has passed, steps the engine
 (admission by HBM footprint, one chunk of sweeps for all resident jobs,
 retirement), and stamps each job's completion.  Latency = completion -
-arrival on the wall clock; throughput = site updates completed / makespan.
+arrival on the wall clock; throughput = site updates completed / makespan,
+and, over the steps that began with jobs still queued (the engine saturated),
+the site updates those steps did / their duration.
 The engine is any object with submit/step/completed/result/stats (the C
 engine `pgg.ServerEngine`, or a stand-in for host-only tests).
 """
@@ -39,6 +41,9 @@ def serve(engine, jobs, clock=time.perf_counter, sleep=time.sleep, keep_results=
     results = {}
     steps = 0
     resident_hist = []
+    # saturation: the steps that began with jobs still waiting in the queue
+    # (the engine had more work than it admitted), and the site updates they did
+    sat_time, sat_updates = 0.0, 0
     t0 = clock()
     while len(finished_at) < len(jobs):
         now = clock() - t0
@@ -53,7 +58,12 @@ def serve(engine, jobs, clock=time.perf_counter, sleep=time.sleep, keep_results=
             # nothing in flight: wait for the next arrival
             sleep(max(0.0, jobs[order[nxt]]["arrival"] - (clock() - t0)))
             continue
+        st0 = engine.stats()
+        step_t0 = clock()
         n_res = engine.step()
+        if st0["queued"] > 0:
+            sat_time += clock() - step_t0
+            sat_updates += engine.stats()["site_updates"] - st0["site_updates"]
         steps += 1
         resident_hist.append(n_res)
         done_t = clock() - t0
@@ -72,6 +82,8 @@ def serve(engine, jobs, clock=time.perf_counter, sleep=time.sleep, keep_results=
         "latency_mean_s": float(np.mean(lat_s)), "site_updates": updates,
         "site_updates_per_s": updates / makespan if makespan > 0 else float("nan"),
         "mean_resident": float(np.mean(resident_hist)) if resident_hist else 0.0,
+        "saturated_s": sat_time,
+        "site_updates_per_s_saturated": sat_updates / sat_time if sat_time > 0 else None,
         "max_resident": int(max(resident_hist)) if resident_hist else 0,
         "engine": engine.stats(),
     }

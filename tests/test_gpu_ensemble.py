@@ -120,7 +120,7 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
     reps = [dict(L=128, r=3.8, seed=11), dict(L=256, r=3.7, seed=12), dict(L=128, r=3.9, seed=13),
             dict(L=256, r=3.65, seed=14), dict(L=96, r=4.0, seed=15)]
     say("autotune over", [rp["L"] for rp in reps])
-    tiles, chunk, wpg, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
+    tiles, chunk, wpg, branches, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
     assert chunk in (8, 16, 32, 64, 128) and wpg in (2, 4, 8) and ms > 0.0
     by_L = {}
     for rp, w in zip(reps, tiles):
@@ -129,7 +129,8 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
         by_L.setdefault(rp["L"], set()).add(int(w))
     assert all(len(ws) == 1 for ws in by_L.values())
     n = 21
-    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk, waves_per_group=wpg) as a, pgg.Ensemble(reps) as b:
+    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk, waves_per_group=wpg, branches=branches) as a, \
+            pgg.Ensemble(reps) as b:
         ca, cb = a.sweep(n), b.sweep(n)
         assert np.array_equal(ca, cb)
         ref, _, counts = oracle_lib.run(256, 3.7, 0.5, 0.5, 12, n)
@@ -286,3 +287,49 @@ def _oracle_tiled_run(args):
     L, r, seed, n = args
     lat, _, counts = oracle.run_tiled(L, r, 0.5, 0.5, seed, n)
     return lat, counts
+
+
+@pytest.mark.parametrize("branches", [2, 3, 4, 16])
+def test_concurrent_replica_groups_do_not_change_results(pgg, oracle_lib, branches):
+    """Replicas cut into contiguous groups of about equal work that run as
+    parallel branches of the chunk's graph: every replica's counts after
+    every sweep and its lattice equal the one-branch ensemble's, and two of
+    them equal the oracle (chunks of 8 with a short tail, uneven sizes so the
+    groups hold different numbers of replicas)."""
+    reps = [dict(L=L, r=r, seed=200 + k) for k, (L, r) in
+            enumerate([(64, 3.8), (96, 3.9), (128, 3.75), (256, 3.85), (132, 4.1), (512, 3.8), (64, 4.4),
+                       (200, 3.95)])]
+    n = 21
+    say("ensemble with", branches, "branches over", [rp["L"] for rp in reps])
+    with pgg.Ensemble(reps, chunk=8, branches=branches) as a, pgg.Ensemble(reps, chunk=8) as b:
+        ca, cb = a.sweep(n), b.sweep(n)
+        assert np.array_equal(ca, cb)
+        for k in range(len(reps)):
+            assert np.array_equal(a.read_lattice(k), b.read_lattice(k)), k
+        assert np.array_equal(a.coop_counts(), b.coop_counts())
+    for k in (0, 5):
+        rp = reps[k]
+        ref, _, counts = oracle_lib.run(rp["L"], rp["r"], 0.5, 0.5, rp["seed"], n)
+        assert np.array_equal(ca[k], counts), k
+
+
+def test_branches_refused_where_they_do_not_apply(pgg):
+    with pytest.raises(pgg.PggError):
+        pgg.Ensemble([dict(L=128, r=3.8, seed=1)], branches=17)
+    with pytest.raises(pgg.PggError):
+        pgg.Ensemble([dict(L=128, r=3.8, seed=1, schedule="tiled"), dict(L=64, r=3.8, seed=2, schedule="tiled")],
+                     branches=2)
+
+
+def test_one_shot_run_equals_the_handle_calls(pgg, oracle_lib):
+    """pgg_ensemble_run (autotuned, and with given settings) returns the same
+    counts as create / sweep on the same replicas, and the oracle's."""
+    reps = [dict(L=L, r=r, seed=300 + k) for k, (L, r) in enumerate([(64, 3.8), (128, 3.9), (100, 4.0), (256, 3.75)])]
+    n = 17
+    say("one-shot ensemble run over", [rp["L"] for rp in reps])
+    with pgg.Ensemble(reps, chunk=8) as ens:
+        ref = ens.sweep(n)
+    assert np.array_equal(pgg.ensemble_run(reps, n), ref)
+    assert np.array_equal(pgg.ensemble_run(reps, n, tune=dict(chunk=4, waves_per_group=2, branches=2)), ref)
+    _, _, counts = oracle_lib.run(100, 4.0, 0.5, 0.5, 302, n)
+    assert np.array_equal(ref[2], counts)

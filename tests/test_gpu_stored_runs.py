@@ -1,0 +1,112 @@
+"""GPU: the batched ensemble and the job server at their full workloads
+against stored oracle results (tests/golden/make_trajectories.py, which
+calls only the oracle).
+
+* The 256-replica ensemble (64 each of L = 128, 256, 512, 1024; r ~ U[3.6,
+  3.9]; 5000 sweeps) run as the benchmark runs it -- autotuned, one batched
+  ensemble -- with 32 sampled replicas (8 of each size) checked against
+  their stored oracle runs: N_C after 1000, 2500 and 5000 sweeps, the
+  digest of N_C after every one of the 5000 sweeps and of the final lattice.
+* The serving trace's first 100 jobs (L log-uniform in [64, 2048], r ~
+  U[3.5, 5.6], 10^3..10^4 sweeps, p0 ~ U[0.1, 0.9]) run through the job
+  server as one mixed stream, with every fifth job (20 of them, L up to
+  1496, up to 9888 sweeps) checked against its stored oracle run alone:
+  the digest of its counts after every sweep, its final count and the
+  digest of its final lattice.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+from paper_1704_08098_amd import server, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pgg(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.set_device(0)
+    from paper_1704_08098_amd import pgg as mod
+    mod.load()
+    return mod
+
+
+def _rows(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip("%s not generated yet (tests/golden/make_trajectories.py)" % name)
+    head, rows = {}, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if len(parts) == 2:
+                head[parts[0]] = int(parts[1])
+            else:
+                rows.append(parts)
+    return head, rows
+
+
+def _digest_counts(c):
+    return hashlib.sha256(np.ascontiguousarray(c, dtype="<u8").tobytes()).hexdigest()
+
+
+def _digest_lattice(s):
+    return hashlib.sha256(np.ascontiguousarray(s, dtype=np.uint8).tobytes()).hexdigest()
+
+
+def test_batched_ensemble_against_stored_oracle_runs(pgg):
+    head, rows = _rows("ensemble256_5000.txt")
+    n = head["sweeps"]
+    reps = wl.ensemble_replicas(sweeps=n)
+    say("autotuning the 256-replica ensemble")
+    tiles, chunk, wpg, branches, _ = pgg.ensemble_autotune(reps, probe_sweeps=8)
+    say("ensemble: 256 replicas, %d sweeps, chunk %d, waves per group %d, branches %d" % (n, chunk, wpg, branches))
+    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk, waves_per_group=wpg, branches=branches) as ens:
+        counts = np.concatenate([ens.sweep(1000), ens.sweep(1500), ens.sweep(2500)], axis=1)
+        assert counts.shape == (len(reps), n)
+        for parts in rows:
+            k, L, r, seed = int(parts[0]), int(parts[1]), float(parts[2]), int(parts[3])
+            assert (L, r, seed) == (reps[k]["L"], reps[k]["r"], reps[k]["seed"])
+            c1000, c2500, c5000 = (int(v) for v in parts[5:8])
+            assert (int(counts[k, 999]), int(counts[k, 2499]), int(counts[k, 4999])) == (c1000, c2500, c5000), k
+            assert _digest_counts(counts[k]) == parts[8], "replica %d: counts differ" % k
+            assert _digest_lattice(ens.read_lattice(k)) == parts[9], "replica %d: lattice differs" % k
+    say("ensemble: %d sampled replicas equal the oracle" % len(rows))
+
+
+def test_served_jobs_against_stored_oracle_runs(pgg):
+    head, rows = _rows("serving_jobs.txt")
+    n_jobs = head["trace_jobs"]
+    # a mixed stream: the trace's arrivals compressed so that many jobs are
+    # resident at once (a tight HBM budget makes admission and backfill bind)
+    jobs = wl.serving_trace(n_jobs, 400.0)
+    chunk = 16
+    say("server: %d jobs, budget 64 MiB, chunk %d" % (n_jobs, chunk))
+    with pgg.ServerEngine(64 << 20, max_L=2048, chunk=chunk) as eng:
+        rep = server.serve(eng, jobs, keep_results=True)
+        st = eng.stats()
+    assert st["completed"] == n_jobs and st["peak_bytes"] <= st["budget"]
+    assert rep["max_resident"] >= 8
+    for parts in rows:
+        q, L, r, p0, seed, sweeps = int(parts[0]), int(parts[1]), float(parts[2]), float(parts[3]), int(parts[4]), \
+            int(parts[5])
+        j = jobs[q]
+        assert (L, r, p0, seed, sweeps) == (j["L"], j["r"], j["p0"], j["seed"], j["sweeps"])
+        counts, lat = rep["results"][q]
+        assert len(counts) == sweeps and int(counts[-1]) == int(parts[7]), q
+        assert _digest_counts(counts) == parts[8], "job %d: counts differ" % q
+        assert _digest_lattice(lat) == parts[9], "job %d: lattice differs" % q
+    say("server: %d sampled jobs equal the oracle (max resident %d)" % (len(rows), rep["max_resident"]))

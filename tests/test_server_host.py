@@ -17,6 +17,7 @@ class OracleEngine:
         self.budget, self.chunk, self.job_bytes = budget, chunk, job_bytes
         self.queue, self.resident, self.done_ids = [], [], []
         self.jobs, self.next_id, self.in_use, self.peak = {}, 1, 0, 0
+        self.updates = 0
 
     def submit(self, L, r, n_sweeps, K=0.5, p0=0.5, seed=1):
         jid = self.next_id
@@ -41,6 +42,7 @@ class OracleEngine:
             j["lat"], c = oracle.sweep(j["lat"], j["r"], j["K"], j["seed"], j["done"], m)
             j["counts"].extend(int(v) for v in c)
             j["done"] += m
+            self.updates += m * j["L"] * j["L"]
             if j["done"] == j["n"]:
                 self.resident.remove(jid)
                 self.in_use -= self.job_bytes(j["L"])
@@ -56,7 +58,8 @@ class OracleEngine:
         return np.array(j["counts"], dtype=np.uint64), (j["lat"] if want_lattice else None)
 
     def stats(self):
-        return {"peak_bytes": self.peak, "budget": self.budget}
+        return {"peak_bytes": self.peak, "budget": self.budget, "queued": len(self.queue),
+                "site_updates": self.updates}
 
 
 def _trace(n, rate, seed):
@@ -86,6 +89,11 @@ def test_budget_binds_admission():
     rep = server.serve(eng, jobs)
     assert rep["max_resident"] <= 2
     assert rep["steps"] >= 1
+    # jobs waited in the queue, so the engine ran saturated for a while; the
+    # saturated rate counts only the updates of those steps
+    assert rep["saturated_s"] > 0
+    assert 0 < rep["site_updates_per_s_saturated"]
+    assert eng.updates == sum(j["L"] ** 2 * j["sweeps"] for j in jobs)
 
 
 def test_percentile_nearest_rank():
