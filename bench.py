@@ -324,7 +324,25 @@ def paper_workload_pass(pgg, torch, warmup, steps, stream):
                     "measured on other hardware"}
 
 
-def serving_pass(pgg, n_jobs, stream, budget_mib=256, chunk=16, max_resident=64):
+def pairwise_pass(pgg, torch, warmup, steps, stream, L=4096, b=1.05, K=0.1):
+    """The pairwise prisoner's dilemma (the game Sec. VI names next; temptation
+    b, noise K) on one L x L lattice: its 8-colour sweep, timed like the
+    single-lattice pass."""
+    sim = pgg.Sim(L, b, K, 0.5, 1, "bits", stream=stream, game="pd")
+    sim.sweep(warmup, want_counts=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(steps, want_counts=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rho = sim.density()
+    sim.close()
+    return {"game": "pairwise prisoner's dilemma (R = 1, T = b, S = P = 0)", "L": L, "b": b, "K": K,
+            "sweeps_timed": "%d..%d" % (warmup, warmup + steps - 1), "value": float(L) * L * steps / dt,
+            "unit": "site updates/s", "ms_per_step": 1e3 * dt / steps, "density_at_end": rho}
+
+
+def serving_pass(pgg, n_jobs, stream, budget_mib=256, chunk=16, max_resident=256):
     """Poisson arrivals of simulation jobs through the C job server at 70 %
     of its capacity.  The capacity is measured first: 4 x max_resident jobs
     of the same distribution submitted at once, at most max_resident of them
@@ -478,9 +496,11 @@ def main():
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
     ap.add_argument("--serve-chunk", type=int, default=16, help="sweeps per server step")
-    ap.add_argument("--serve-resident", type=int, default=64, help="most jobs on the device at once")
+    ap.add_argument("--serve-resident", type=int, default=256, help="most jobs on the device at once")
     ap.add_argument("--no-paper-workload", dest="paper_workload", action="store_false",
                     help="skip the paper's own workload (double tiling, L = 4096, r = 3.98)")
+    ap.add_argument("--no-pairwise", dest="pairwise", action="store_false",
+                    help="skip the pairwise prisoner's dilemma pass (L = 4096, b = 1.05, K = 0.1)")
     ap.add_argument("--no-decay-batch", dest="decay_batch", action="store_false",
                     help="skip the nine L = 4096 decay lattices run as one ensemble")
     ap.add_argument("--scan-sweeps", type=int, default=10_000,
@@ -588,6 +608,11 @@ def main():
         log("paper workload: double tiling, L=4096, r=3.98")
         paper_workload = paper_workload_pass(pgg, torch, args.warmup, args.steps, stream)
 
+    pairwise = None
+    if args.pairwise:
+        log("pairwise prisoner's dilemma: L=4096")
+        pairwise = pairwise_pass(pgg, torch, args.warmup, args.steps, stream)
+
     decay_batch = None
     if args.decay_batch:
         log("decay batch: 9 lattices of L=%d as one ensemble" % wl.DECAY["L"])
@@ -631,7 +656,7 @@ def main():
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
                    "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
         "roofline": roofline, "windows": windows, "dense": dense, "late": late, "batched": batched, "serving": serving,
-        "scan": scan, "decay_batch": decay_batch, "paper_workload": paper_workload,
+        "scan": scan, "decay_batch": decay_batch, "paper_workload": paper_workload, "pairwise": pairwise,
         "cpu_baseline": cpu,
         "final_density": nc_end / float(L * L),
     }

@@ -240,12 +240,14 @@ k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restric
 }
 
 // After a chunk whose replica ran an odd number of sweeps, its state is in
-// lat2: copy it back (one block per replica).
+// lat2: copy it back (blockIdx.x = replica, kCopyBlocks blocks per replica
+// share its words).
+constexpr int kCopyBlocks = 64;
 __global__ void k_ens_copyback(const EnsRep* __restrict__ reps) {
     const EnsRep& rp = reps[blockIdx.x];
     if (rp.tiled || (rp.n_active & 1) == 0) return;  // the tiled schedule updates in place
     const int n = rp.L * rp.stride;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) rp.lat[k] = rp.lat2[k];
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < n; k += gridDim.y * blockDim.x) rp.lat[k] = rp.lat2[k];
 }
 
 // Zero the per-sweep counters of every replica (one block per replica).
@@ -365,7 +367,7 @@ hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* 
     hipError_t err;
     hipLaunchKernelGGL(k_ens_scan, dim3(n), dim3(256), 0, st, d_reps, chunk, counts);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_ens_copyback, dim3(n), dim3(256), 0, st, d_reps);
+    hipLaunchKernelGGL(k_ens_copyback, dim3(n, kCopyBlocks), dim3(256), 0, st, d_reps);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_ens_advance, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n);
     return hipGetLastError();
