@@ -55,7 +55,7 @@ GPU_CLOCK_HZ = 2.4e9
 TRAFFIC_PROFILES = {"segment": os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt"),
                     "segment_pair": os.path.join(ROOT, "profiles", "k_ens_pair_L4096_traffic.txt")}
 KERNEL_SOURCES = ("paper_1704_08098_amd/csrc/pgg_segment.hpp", "paper_1704_08098_amd/csrc/pgg_fullrow.hpp",
-                  "paper_1704_08098_amd/csrc/pgg_ensemble.hip", "paper_1704_08098_amd/csrc/pgg_device.hpp")
+                  "paper_1704_08098_amd/csrc/pgg_ens_kernels.hip", "paper_1704_08098_amd/csrc/pgg_device.hpp")
 
 
 def kernel_source_hash():
@@ -188,18 +188,19 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     pgg_ensemble_autotune (untimed, before the timed run)."""
     reps = wl.ensemble_replicas(sweeps=sweeps)
     total = float(sum(rp["L"] ** 2 for rp in reps)) * sweeps
-    tiles, tuned, wpg, branches = None, None, 0, 0
+    tune, tuned = dict(chunk=chunk), None
     if autotune:
         t0 = time.perf_counter()
-        tiles, chunk, wpg, branches, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
-        tuned = {"tiles_by_L": {int(rp["L"]): int(w) for rp, w in zip(reps, tiles)}, "chunk": chunk,
-                 "waves_per_group": wpg, "branches": branches, "probe_ms_per_sweep": ms,
+        tune, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
+        tuned = {"tiles_by_L": {int(rp["L"]): int(w) for rp, w in zip(reps, tune["tiles"])},
+                 **{k: tune[k] for k in pgg.TUNE_KEYS}, "probe_ms_per_sweep": ms,
                  "tuning_s": time.perf_counter() - t0}
-    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg, branches=branches)
+        chunk = tune["chunk"]
+    ens = pgg.Ensemble(reps, stream=stream, **tune)
     ens.sweep(min(chunk, sweeps), want_counts=False)  # first replay builds the graph
     torch.cuda.synchronize()
     ens.close()
-    ens = pgg.Ensemble(reps, tiles=tiles, chunk=chunk, stream=stream, waves_per_group=wpg, branches=branches)
+    ens = pgg.Ensemble(reps, stream=stream, **tune)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ens.sweep(sweeps, want_counts=False)

@@ -350,16 +350,9 @@ void pgg_destroy(pgg_sim* s);
  * ------------------------------------------------------------------------ */
 typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
 
-/* Create n_reps replicas and draw their initial states (t = 0).
- *   reps       host array of n_reps parameter sets: 64 <= L <= 32768, L % 4
- *              == 0, layout BITS, kernel AUTO or SEGMENT, group 0, and one
- *              schedule for all of them; copied.  With PGG_SCHEDULE_TILED
- *              (L % 8 == 0) every launch covers one domain type of one step
- *              of every replica, in place, and tiles and waves_per_group do
- *              not apply (tiles NULL or all 0).
- *   tiles      host array of n_reps work splits as pgg_params.tile of
- *              the segment kernel (0 = automatic), or NULL for all
- *              automatic.
+/* Tuning of a batched launch: what only changes the speed, never a result.
+ *   tiles      NULL (automatic) or host array of n_reps work splits as
+ *              pgg_params.tile of the segment kernel.
  *   chunk      sweeps per graph replay, 1..1024 (device counters hold
  *              chunk x n_reps x 4 KiB).
  *   waves_per_group  segment waves per workgroup: 2, 4 or 8 (0 = 4).  A
@@ -367,18 +360,41 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
  *              threshold table; each replica's waves are padded to whole
  *              workgroups.
  *   branches   concurrent replica groups, 0..16 (0 or 1: one): the replicas
- *              are cut into this many contiguous ranges of about equal work
- *              (sum of L^2), each range's chunk is its own chain of launches,
- *              and the chains run side by side as parallel branches of the
- *              chunk's graph.  Results never depend on it.  The tiled
- *              schedule takes 0 or 1.
+ *              swept by segments are cut into this many contiguous ranges
+ *              of about equal work (sum of L^2), each range's chunk is its
+ *              own chain of launches, and the chains run side by side as
+ *              parallel branches of the chunk's graph.  The tiled schedule
+ *              takes 0 or 1.
+ *   resident_max_L  0, or a side in [64, 256]: replicas with L a multiple of
+ *              32 up to this side are swept by the resident kernel instead
+ *              -- one workgroup per replica holds its lattice in LDS and
+ *              runs the whole chunk in one launch -- as one more parallel
+ *              branch beside the segment launches (16-colour schedule).
+ *   resident_waves  waves per resident workgroup: 4, 8 or 16 (0 = 8). */
+typedef struct {
+    const uint32_t* tiles;
+    uint32_t chunk;
+    uint32_t waves_per_group;
+    uint32_t branches;
+    uint32_t resident_max_L;
+    uint32_t resident_waves;
+} pgg_ensemble_tune;
+
+/* Create n_reps replicas and draw their initial states (t = 0).
+ *   reps       host array of n_reps parameter sets: 64 <= L <= 32768, L % 4
+ *              == 0, layout BITS, kernel AUTO or SEGMENT, group 0, game 0,
+ *              and one schedule for all of them; copied.  With
+ *              PGG_SCHEDULE_TILED (L % 8 == 0) every launch covers one
+ *              domain type of one step of every replica, in place, and only
+ *              tune->chunk applies (tiles NULL or all 0).
+ *   tune       host, NULL for the defaults (chunk 32, everything else
+ *              automatic), else the tuning above; copied.
  *   hip_stream stream to order the work on; NULL: the ensemble creates and
  *              owns a stream of default priority (graphs cannot capture the
  *              null stream).
  * Synchronises the stream once. */
-pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles,
-                               uint32_t chunk, uint32_t waves_per_group, uint32_t branches, void* hip_stream,
-                               pgg_ensemble** out);
+pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const pgg_ensemble_tune* tune,
+                               void* hip_stream, pgg_ensemble** out);
 
 /* Advance every replica n_sweeps sweeps.  counts: NULL, or host array of
  * n_reps rows of n_sweeps entries receiving N_C after each sweep (row k is
@@ -403,41 +419,36 @@ pgg_status pgg_ensemble_threshold_table(pgg_ensemble* e, uint32_t rep, uint32_t*
 void pgg_ensemble_destroy(pgg_ensemble* e);
 
 /* Autotune the batched launch for a set of replicas: the segment width of
- * each distinct L, the waves per workgroup, the concurrent replica groups
- * and the chunk length of a graph replay.  Results never depend on them; only the speed does.
+ * each distinct L, the waves per workgroup, the concurrent replica groups,
+ * the resident sweep of small replicas and the chunk length of a graph
+ * replay.  Results never depend on them; only the speed does.
  *   reps, n_reps  as for pgg_ensemble_create, schedule COLOUR16 (the tiled
  *                 schedule has nothing to tune: PGG_E_INVAL).
- *   probe_sweeps  sweeps timed per trial, 1..4096 (after 2 untimed ones).
+ *   probe_sweeps  sweeps per timed run, 1..4096; at least 64 and twice the
+ *                 trial's chunk are run.
  *   hip_stream    as for pgg_ensemble_create.
  *   tiles_out     host array of n_reps: the chosen width of each replica
  *                 (equal for equal L).
- *   chunk_out     the chosen chunk length.
- *   wpg_out       the chosen waves per workgroup.
- *   branches_out  the chosen number of concurrent replica groups.
+ *   tune_out      host: the chosen tuning (its tiles point at tiles_out).
  *   ms_out        NULL, or the best time per sweep of the whole ensemble.
  * Trials run on trial ensembles created from reps (fresh initial states
- * each): first the width of each distinct L in turn over the doublings
+ * each): first the width of each distinct L in turn (the six with the
+ * most work, sum of L^2, in that order; others automatic) over the doublings
  * 64, 128, ... below L - 32, L - 32 rounded down to a multiple of 32, and
- * whole rows (L, when L is a multiple of 32),
- * the other sizes held at their best so far, then the waves per workgroup
- * over 2, 4, 8, then the concurrent groups over 1, 2, 4, then the chunk
- * over 8, 16, 32, 64, 128; each trial keeps its best of two timed runs.  Every
- * trial's final cooperator counts must equal the first trial's, else
+ * whole rows (L, when L is a multiple of 32), the other sizes held at their
+ * best so far, then the waves per workgroup over 2, 4, 8, then the
+ * concurrent groups over 1, 2, 4 together with resident sweeps off, up to
+ * L = 128 or up to 256 (when some replica fits), then their 4, 8 or 16
+ * waves, then the chunk over 8, 16, 32, 64, 128; each trial runs once
+ * untimed and keeps its best of three timed runs.  Every trial's final
+ * cooperator counts must equal those of the first trial of the same length, else
  * PGG_E_DEVICE with a message (a tuning-dependent result would be a bug).
  * Needs the device memory of one trial ensemble at chunk 128. */
 pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps,
-                                 void* hip_stream, uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out,
-                                 uint32_t* branches_out, double* ms_out);
+                                 void* hip_stream, uint32_t* tiles_out, pgg_ensemble_tune* tune_out,
+                                 double* ms_out);
 
-/* Tuning of a batched run (pgg_ensemble_run): the arguments of
- * pgg_ensemble_create that only change the speed.  tiles: NULL (automatic)
- * or host array of n_reps segment widths. */
-typedef struct {
-    const uint32_t* tiles;
-    uint32_t chunk;           /* 1..1024                         */
-    uint32_t waves_per_group; /* 0, 2, 4 or 8                    */
-    uint32_t branches;        /* 0..16                           */
-} pgg_ensemble_tune;
+
 
 /* One batched run from the initial states: create the ensemble of reps,
  * advance every replica n_sweeps sweeps, release it.  counts: NULL, or host

@@ -7,7 +7,8 @@
 // counters, 4 launches per sweep, the per-replica count scan and the advance
 // of every replica's sweep index -- is captured once in a hipGraph and
 // replayed; the sweep index lives in device memory so the same graph serves
-// every chunk.  Results are those of the replicas run one by one.
+// every chunk.  Results are those of the replicas run one by one.  This file
+// is the host engine; the kernels and their launchers are pgg_ens_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,391 +22,6 @@
 
 #include "pgg.h"
 #include "pgg_internal.hpp"
-#include "pgg_fullrow.hpp"
-#include "pgg_segment.hpp"
-
-namespace pgg {
-
-// Replica whose wave range holds wave w: the last replica with wave_base <= w.
-__device__ __forceinline__ int replica_of_wave(const EnsRep* __restrict__ reps, int n, int w) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (reps[mid].wave_base <= w) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <int WPG>
-__global__ void __launch_bounds__(64 * WPG)
-k_ens_segment(const EnsRep* __restrict__ reps, int n_reps, int a, int q, unsigned long long* __restrict__ span) {
-    extern __shared__ uint32_t smem[];
-    __shared__ int s_part[2 * WPG];
-    const unsigned long long t_begin = span ? wall_clock64() : 0ull;
-    const int lane = threadIdx.x & 63;
-    // Everything below that depends only on the wave (its replica, row and
-    // segment) is wave-uniform: readfirstlane keeps it in scalar registers.
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // neighbouring rows (which share window rows) run on the same XCD's L2
-    const int first_wave = xcd_major((int)blockIdx.x, (int)gridDim.x) * WPG;
-    const int rep_id = __builtin_amdgcn_readfirstlane(replica_of_wave(reps, n_reps, first_wave));
-    const EnsRep rp = reps[rep_id];
-    uint32_t* sT = smem;
-    uint32_t* win = smem + kSegTableWords + wid * rep_wave_words(rp);
-    const int lw = first_wave + wid - rp.wave_base;  // wave index inside the replica
-    // sweep q of the chunk reads the state after sweep q - 1: lat for even q,
-    // lat2 for odd q, and writes the other buffer.
-    const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
-    uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
-    const uint32_t t = rp.t0 + (uint32_t)q;
-    int my_delta = 0, my_drawn = 0;
-    seg_load_table(sT, rp.T);
-    if (rp.rpw > 0) {
-        // whole rows: wave lw owns rows a + 4 (lw R + r), r < nrows
-        const int R = rp.rpw, rows = rp.L >> 2;
-        const bool active = q < rp.n_active && lw * R < rows;
-        const int i0 = a + 4 * lw * R;
-        const int nrows = min(R, rows - lw * R);
-        if (active) fullrow_fill(cur, next, rp.L, rp.stride, a, i0, R, win);
-        __syncthreads();
-        if (active) fullrow_run(next, rp.L, rp.stride, a, i0, R, nrows, t, rp.k0, rp.k1, sT, win, my_delta, my_drawn);
-    } else {
-        const bool active = q < rp.n_active && lw < (rp.L >> 2) * rp.nseg;
-        const SegPos g = seg_pos(rp.L, a, rp.segw, active ? lw / rp.nseg : 0, active ? lw % rp.nseg : 0);
-        if (active) segment_fill(cur, next, rp.L, rp.stride, rp.nw, a, rp.segw, g, win);
-        __syncthreads();
-        if (active)
-            segment_run(next, rp.L, rp.stride, a, rp.segw, g, t, rp.k0, rp.k1, sT, win, rp.drawn != nullptr, my_delta,
-                        my_drawn);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        my_delta += __shfl_xor(my_delta, off, 64);
-        my_drawn += __shfl_xor(my_drawn, off, 64);
-    }
-    if (lane == 0) {
-        s_part[wid] = my_delta;
-        s_part[WPG + wid] = my_drawn;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int dsum = 0, nsum = 0;
-        for (int k = 0; k < WPG; ++k) {
-            dsum += s_part[k];
-            nsum += s_part[WPG + k];
-        }
-        if (dsum)
-            atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
-                      (unsigned long long)(long long)dsum);
-        if (rp.drawn && nsum) atomicAdd(slot_of(rp.drawn, (int)blockIdx.x), (unsigned long long)nsum);
-        if (span) {  // diagnostics: earliest start and latest end over kSpanSlots spread pairs
-            unsigned long long* sp = span + 2 * (blockIdx.x & (kSpanSlots - 1));
-            atomicMin(sp, t_begin);
-            atomicMax(sp + 1, wall_clock64());
-        }
-    }
-}
-
-// Two row residues per launch (residues a and a + 1, a = 0 or 2) for one
-// lattice (reps[0], segments of rp.segw columns, L a multiple of 32).  A
-// workgroup stages rows R0 - 6 .. R1 + 5 of its band [R0, R1) (kPairBand rows)
-// and its segment's columns s - 64 .. e + 63 once.  Residue a then runs on its
-// rows in [R0 - 1, R1 + 3) -- those a row of residue a + 1 in the band reads
-// (rows i - 1 and i + 3) -- each class with 12 more margin columns, so that
-// every row and column the second residue reads is exact; after a workgroup
-// barrier residue a + 1 runs on the band's rows.
-// Only band rows and owned columns are written back and counted.  Rows of
-// residue below a come from next (this sweep), the others from cur.
-template <int B>
-__global__ void __launch_bounds__(64 * (B / 4 + 1))
-k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __restrict__ span) {
-    constexpr int NW = B / 4 + 1;
-    extern __shared__ uint32_t smem[];
-    __shared__ int s_part[2 * NW];
-    const unsigned long long t_begin = span ? wall_clock64() : 0ull;
-    const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const EnsRep rp = reps[0];
-    const int L = rp.L, segw = rp.segw, nseg = rp.nseg, stride = rp.stride, nw = rp.nw;
-    const int WB = seg_window_words(segw), cap = seg_list_cap(segw);
-    const int blk = xcd_major((int)blockIdx.x, (int)gridDim.x);  // neighbouring bands share an XCD
-    const int band = blk / nseg, sg = blk - band * nseg;
-    const int R0 = band * B, R1 = min(R0 + B, L);
-    const int s = sg * segw, e = min(L, s + segw), c0 = s - 64;
-    uint32_t* sT = smem;
-    uint32_t* wwin = smem + kSegTableWords;  // (B + 12) rows x WB
-    uint32_t* lists = wwin + (B + 12) * WB;  // NW x cap
-    const bool on = q < rp.n_active;
-    const uint32_t* cur = (q & 1) ? rp.lat2 : rp.lat;
-    uint32_t* next = (q & 1) ? rp.lat : rp.lat2;
-    const uint32_t t = rp.t0 + (uint32_t)q;
-    seg_load_table(sT, rp.T);
-    if (on) {
-        const int w0 = c0 >> 5;  // segments start on word boundaries (L % 32 == 0)
-        for (int k = threadIdx.x; k < (B + 12) * WB; k += blockDim.x) {
-            const int o = k / WB, w = k - o * WB;
-            int gi = R0 - 6 + o;  // in [-6, L + B + 6)
-            gi += (gi < 0) ? L : 0;
-            gi -= (gi >= L) ? L : 0;
-            int widx = w0 + w;  // in [-2, nw + 2)
-            widx += (widx < 0) ? nw : 0;
-            widx -= (widx >= nw) ? nw : 0;
-            const uint32_t* src = ((gi & 3) < a) ? next : cur;
-            wwin[k] = src[(size_t)gi * stride + widx];
-        }
-    }
-    __syncthreads();
-    int my_delta = 0, my_drawn = 0;
-    // residue a: rows in [R0 - 1, R1 + 3) (R0 is a multiple of 4)
-    {
-        const int i = R0 - 1 + ((a + 1) & 3) + 4 * wid;
-        if (on && i < R1 + 3) {
-            const int gi = i < 0 ? i + L : (i >= L ? i - L : i);
-            const SegPos g = {gi, s, e, c0};
-            segment_run_row(next, L, stride, a, segw, g, t, rp.k0, rp.k1, sT, wwin + (i - (R0 - 6)) * WB,
-                            lists + wid * cap, 12, i >= R0 && i < R1, rp.drawn != nullptr, my_delta, my_drawn);
-        }
-    }
-    __syncthreads();
-    // residue a + 1: band rows (R0 is a multiple of 4)
-    {
-        const int i = R0 + a + 1 + 4 * wid;
-        if (on && i < R1) {
-            const SegPos g = {i, s, e, c0};
-            segment_run_row(next, L, stride, a + 1, segw, g, t, rp.k0, rp.k1, sT, wwin + (i - (R0 - 6)) * WB,
-                            lists + wid * cap, 0, true, rp.drawn != nullptr, my_delta, my_drawn);
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        my_delta += __shfl_xor(my_delta, off, 64);
-        my_drawn += __shfl_xor(my_drawn, off, 64);
-    }
-    if (lane == 0) {
-        s_part[wid] = my_delta;
-        s_part[NW + wid] = my_drawn;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int dsum = 0, nsum = 0;
-        for (int k = 0; k < NW; ++k) {
-            dsum += s_part[k];
-            nsum += s_part[NW + k];
-        }
-        if (dsum)
-            atomicAdd(slot_of(rp.delta + (size_t)q * kSweepWords, (int)blockIdx.x),
-                      (unsigned long long)(long long)dsum);
-        if (rp.drawn && nsum) atomicAdd(slot_of(rp.drawn, (int)blockIdx.x), (unsigned long long)nsum);
-        if (span) {
-            unsigned long long* sp = span + 2 * (blockIdx.x & (kSpanSlots - 1));
-            atomicMin(sp, t_begin);
-            atomicMax(sp + 1, wall_clock64());
-        }
-    }
-}
-
-// Per replica: counts[rep][q] = nc[rep] + prefix over q of the sweep deltas
-// (q < n_active), then nc[rep] advances.  One block per replica.
-__global__ void __launch_bounds__(256)
-k_ens_scan(const EnsRep* __restrict__ reps, int K, unsigned long long* __restrict__ counts) {
-    __shared__ unsigned long long part[256];
-    const EnsRep& rp = reps[blockIdx.x];
-    const int n = min(rp.n_active, K);
-    const int tid = threadIdx.x;
-    const int chunk = (n + 255) / 256;
-    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
-    auto sweep_delta = [&](int q) {
-        unsigned long long v = 0;
-        const unsigned long long* row = rp.delta + (size_t)q * kSweepWords;
-        for (int k = 0; k < kSlots; ++k) v += row[k * kSlotStride];
-        return v;
-    };
-    unsigned long long sum = 0;
-    for (int q = lo; q < hi; ++q) sum += sweep_delta(q);
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const unsigned long long v = tid >= off ? part[tid - off] : 0ull;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    unsigned long long run = *rp.nc + (tid ? part[tid - 1] : 0ull);
-    for (int q = lo; q < hi; ++q) {
-        run += sweep_delta(q);
-        counts[(size_t)blockIdx.x * K + q] = run;
-    }
-    __syncthreads();
-    if (tid == 255) *rp.nc += part[255];
-}
-
-// After a chunk whose replica ran an odd number of sweeps, its state is in
-// lat2: copy it back (blockIdx.x = replica, kCopyBlocks blocks per replica
-// share its words).
-constexpr int kCopyBlocks = 64;
-__global__ void k_ens_copyback(const EnsRep* __restrict__ reps) {
-    const EnsRep& rp = reps[blockIdx.x];
-    if (rp.tiled || (rp.n_active & 1) == 0) return;  // the tiled schedule updates in place
-    const int n = rp.L * rp.stride;
-    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < n; k += gridDim.y * blockDim.x) rp.lat[k] = rp.lat2[k];
-}
-
-// Zero the per-sweep counters of every replica (one block per replica).
-__global__ void k_ens_zero(const EnsRep* __restrict__ reps, int chunk) {
-    unsigned long long* d = reps[blockIdx.x].delta;
-    const int n = chunk * kSlots;  // only the slot words of each sweep's row are used
-    for (int k = threadIdx.x; k < n; k += blockDim.x) d[(size_t)(k / kSlots) * kSweepWords + (k % kSlots) * kSlotStride] = 0ull;
-}
-
-// Sweep bookkeeping of every replica: n_active for the next chunk, or the
-// advance of t0 after it.
-__global__ void k_ens_set_active(EnsRep* __restrict__ reps, int n_reps, int n) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_reps) reps[k].n_active = n;
-}
-
-__global__ void k_ens_advance(EnsRep* __restrict__ reps, int n_reps) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_reps) reps[k].t0 += (uint32_t)reps[k].n_active;
-}
-
-__global__ void k_ens_set_t0(EnsRep* __restrict__ reps, int n_reps, uint32_t t0) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_reps) reps[k].t0 = t0;
-}
-
-__global__ void k_span_reset(unsigned long long* span, int n_words) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_words) span[k] = (k & 1) ? 0ull : ~0ull;
-}
-
-hipError_t launch_span_reset(unsigned long long* span, int n_launches, hipStream_t st) {
-    const int n = kSpanWords * n_launches;
-    hipLaunchKernelGGL(k_span_reset, dim3((n + 255) / 256), dim3(256), 0, st, span, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st) {
-    hipLaunchKernelGGL(k_ens_set_t0, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n, t0);
-    return hipGetLastError();
-}
-
-int auto_segw(int L) {
-    if (L % 32 == 0 && L <= 1024) return L;  // whole rows
-    // About 1376 columns: at the drawn fraction of a lattice near r_c (about
-    // 15 % of the sites) a class then lists about 50 sites, most of one
-    // 64-lane pass; the row is split into equal segments of that order.  A
-    // segment is at most L - 32 columns, so a row always takes two or more:
-    // split it evenly (one segment of L - 32 columns and one of the rest
-    // would leave the second wave almost empty).
-    const int nseg = std::max(2, (L + 1375) / 1376);
-    int w = (L / nseg + 31) & ~31;
-    const int cap = (L - 32) & ~31;
-    if (w > cap) w = cap;
-    if (w < 32) w = 32;
-    return w;
-}
-
-bool segw_valid(int L, int segw) {
-    if (segw == L) return L % 32 == 0;
-    return segw > 0 && segw % 32 == 0 && segw + 32 <= L;
-}
-
-void ens_geometry(EnsRep& rp, int L, int segw) {
-    if (segw == 0) segw = auto_segw(L);
-    rp.L = L;
-    rp.stride = 2 * ((L + 63) / 64);
-    rp.nw = (L + 31) / 32;
-    rp.segw = segw;
-    if (segw == L) {
-        rp.nseg = 1;
-        const int R = L >= 1024 ? 1 : 1024 / L;
-        rp.rpw = R < L / 4 ? R : L / 4;
-    } else {
-        rp.nseg = (L + segw - 1) / segw;
-        rp.rpw = 0;
-    }
-}
-
-int ens_waves(const EnsRep& rp, int wpg) {
-    const int rows = rp.L / 4;
-    const int wv = rp.rpw > 0 ? (rows + rp.rpw - 1) / rp.rpw : rows * rp.nseg;
-    return (wv + wpg - 1) / wpg * wpg;
-}
-
-int ens_wave_words(const EnsRep& rp) { return rep_wave_words(rp); }
-
-size_t ens_lds_bytes(int max_wave_words, int wpg) {
-    return (kSegTableWords + (size_t)wpg * max_wave_words) * sizeof(uint32_t);
-}
-
-bool ens_wpg_valid(int wpg) { return wpg == 2 || wpg == 4 || wpg == 8; }
-
-hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_active, hipStream_t st) {
-    if (set_active) {
-        hipLaunchKernelGGL(k_ens_set_active, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n, len);
-        const hipError_t err = hipGetLastError();
-        if (err != hipSuccess) return err;
-    }
-    hipLaunchKernelGGL(k_ens_zero, dim3(n), dim3(256), 0, st, d_reps, chunk);
-    return hipGetLastError();
-}
-
-hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
-                              hipStream_t st, int wpg, unsigned long long* span) {
-    const dim3 grid(total_waves / wpg), block(64 * wpg);
-    switch (wpg) {
-        case 2: hipLaunchKernelGGL(k_ens_segment<2>, grid, block, lds, st, d_reps, n, a, q, span); break;
-        case 4: hipLaunchKernelGGL(k_ens_segment<4>, grid, block, lds, st, d_reps, n, a, q, span); break;
-        case 8: hipLaunchKernelGGL(k_ens_segment<8>, grid, block, lds, st, d_reps, n, a, q, span); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_ens_end(EnsRep* d_reps, int n, int chunk, unsigned long long* counts, hipStream_t st) {
-    hipError_t err;
-    hipLaunchKernelGGL(k_ens_scan, dim3(n), dim3(256), 0, st, d_reps, chunk, counts);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_ens_copyback, dim3(n, kCopyBlocks), dim3(256), 0, st, d_reps);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_ens_advance, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_ens_chunk(EnsRep* d_reps, int n, int total_waves, size_t lds, int len, int chunk,
-                            bool set_active, unsigned long long* counts, hipStream_t st, int wpg,
-                            unsigned long long* span) {
-    hipError_t err = launch_ens_begin(d_reps, n, len, chunk, set_active, st);
-    for (int q = 0; err == hipSuccess && q < len; ++q)
-        for (int a = 0; err == hipSuccess && a < 4; ++a)
-            err = launch_ens_residue(d_reps, n, total_waves, lds, a, q, st, wpg,
-                                     span ? span + kSpanWords * (4 * q + a) : nullptr);
-    if (err != hipSuccess) return err;
-    return launch_ens_end(d_reps, n, chunk, counts, st);
-}
-
-size_t pair_lds_bytes(int segw) {
-    return (kSegTableWords + (size_t)(kPairBand + 12) * seg_window_words(segw) +
-            (size_t)(kPairBand / 4 + 1) * seg_list_cap(segw)) * sizeof(uint32_t);
-}
-
-int pair_blocks(const EnsRep& rp) { return (rp.L + kPairBand - 1) / kPairBand * rp.nseg; }
-
-hipError_t launch_pair_chunk(EnsRep* d_rep, int blocks, size_t lds, int len, int chunk, unsigned long long* counts,
-                             hipStream_t st, unsigned long long* span) {
-    hipError_t err = launch_ens_begin(d_rep, 1, len, chunk, true, st);
-    for (int q = 0; err == hipSuccess && q < len; ++q)
-        for (int h = 0; err == hipSuccess && h < 2; ++h) {
-            hipLaunchKernelGGL(k_ens_pair<kPairBand>, dim3(blocks), dim3(64 * (kPairBand / 4 + 1)), lds, st, d_rep,
-                               2 * h, q, span ? span + kSpanWords * (2 * q + h) : nullptr);
-            err = hipGetLastError();
-        }
-    if (err != hipSuccess) return err;
-    return launch_ens_end(d_rep, 1, chunk, counts, st);
-}
-
-}  // namespace pgg
 
 // ---------------------------------------------------------------------------
 // Host engine behind the pgg_ensemble_* calls.
@@ -429,6 +45,12 @@ struct pgg_ensemble {
     std::vector<int> grp_first, grp_count, grp_waves;
     std::vector<hipStream_t> branch_streams;
     std::vector<hipEvent_t> branch_events;  // fork event, then one join event per branch
+    // Replicas swept by the resident kernel (a whole chunk per launch, one
+    // workgroup of res_waves waves per replica, the lattice in LDS): their
+    // indices, on the device, and the largest side among them.  They run as
+    // one more parallel branch beside the segment launches.
+    int n_res = 0, res_L_max = 0, res_waves = 8;
+    int* d_res_idx = nullptr;
     int device = 0;
     int n = 0;
     int chunk = 32;          // sweeps per graph replay
@@ -469,6 +91,7 @@ void ens_release(pgg_ensemble* e) {
     for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipGraph_t g : e->graph_defs) (void)hipGraphDestroy(g);
     if (e->d_reps) (void)hipFree(e->d_reps);
+    if (e->d_res_idx) (void)hipFree(e->d_res_idx);
     if (e->d_lattices) (void)hipFree(e->d_lattices);
     if (e->d_tables) (void)hipFree(e->d_tables);
     if (e->d_delta) (void)hipFree(e->d_delta);
@@ -484,21 +107,37 @@ void ens_release(pgg_ensemble* e) {
 hipError_t enqueue_chunk(pgg_ensemble* e, int len, hipStream_t st) {
     if (e->tiled)
         return pgg::launch_ens_tiled_chunk(e->d_reps, e->n, e->total_waves, len, e->chunk, e->d_counts, st);
-    if (e->branches == 1)
+    if (e->branches == 1 && e->n_res == 0)
         return pgg::launch_ens_chunk(e->d_reps, e->n, e->total_waves, e->lds, len, e->chunk, true, e->d_counts, st,
                                      e->wpg);
-    // fork: every branch waits for the work before it on st, runs its range's
-    // chunk, and st waits for every branch (a graph with parallel branches)
-    hipError_t err = hipEventRecord(e->branch_events[0], st);
+    // the chunk's bookkeeping for every replica, then a fork: every segment
+    // group runs its residue launches on a stream of its own, the resident
+    // replicas theirs on another, and st waits for them all (a graph with
+    // parallel branches) before the counts are scanned
+    hipError_t err = pgg::launch_ens_begin(e->d_reps, e->n, len, e->chunk, true, st);
+    if (err == hipSuccess) err = hipEventRecord(e->branch_events[0], st);
+    int b = 0;
     for (int g = 0; err == hipSuccess && g < e->branches; ++g) {
-        hipStream_t bs = e->branch_streams[g];
+        if (e->grp_waves[g] == 0) continue;  // a range of resident replicas only
+        hipStream_t bs = e->branch_streams[b];
+        err = hipStreamWaitEvent(bs, e->branch_events[0], 0);
+        for (int q = 0; err == hipSuccess && q < len; ++q)
+            for (int a = 0; err == hipSuccess && a < 4; ++a)
+                err = pgg::launch_ens_residue(e->d_reps + e->grp_first[g], e->grp_count[g], e->grp_waves[g], e->lds,
+                                              a, q, bs, e->wpg);
+        if (err == hipSuccess) err = hipEventRecord(e->branch_events[1 + b], bs);
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, e->branch_events[1 + b], 0);
+        ++b;
+    }
+    if (err == hipSuccess && e->n_res > 0) {
+        hipStream_t bs = e->branch_streams[b];
         err = hipStreamWaitEvent(bs, e->branch_events[0], 0);
         if (err == hipSuccess)
-            err = pgg::launch_ens_chunk(e->d_reps + e->grp_first[g], e->grp_count[g], e->grp_waves[g], e->lds, len,
-                                        e->chunk, true, e->d_counts + (size_t)e->grp_first[g] * e->chunk, bs, e->wpg);
-        if (err == hipSuccess) err = hipEventRecord(e->branch_events[1 + g], bs);
-        if (err == hipSuccess) err = hipStreamWaitEvent(st, e->branch_events[1 + g], 0);
+            err = pgg::launch_ens_resident(e->d_reps, e->d_res_idx, e->n_res, e->res_L_max, e->res_waves, bs);
+        if (err == hipSuccess) err = hipEventRecord(e->branch_events[1 + b], bs);
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, e->branch_events[1 + b], 0);
     }
+    if (err == hipSuccess) err = pgg::launch_ens_end(e->d_reps, e->n, e->chunk, e->d_counts, st);
     return err;
 }
 
@@ -556,16 +195,27 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
 
 extern "C" {
 
-pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const uint32_t* tiles, uint32_t chunk,
-                               uint32_t waves_per_group, uint32_t branches, void* hip_stream, pgg_ensemble** out) {
+pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const pgg_ensemble_tune* tune,
+                               void* hip_stream, pgg_ensemble** out) {
     if (!out) { eerr("out is NULL"); return PGG_E_INVAL; }
     *out = nullptr;
+    const uint32_t* tiles = tune ? tune->tiles : nullptr;
+    const uint32_t chunk = tune ? tune->chunk : 32;
+    const uint32_t branches = tune ? tune->branches : 0;
+    const uint32_t res_max_L = tune ? tune->resident_max_L : 0;
     const pgg_status vs = validate_reps(reps, n_reps, tiles, chunk);
     if (vs != PGG_OK) return vs;
-    const int wpg = waves_per_group ? (int)waves_per_group : pgg::kWavesPerGroup;
+    const int wpg = (tune && tune->waves_per_group) ? (int)tune->waves_per_group : pgg::kWavesPerGroup;
     if (!pgg::ens_wpg_valid(wpg)) { eerr("waves_per_group must be 0, 2, 4 or 8"); return PGG_E_INVAL; }
     if (branches > 16) { eerr("branches must lie in [0, 16]"); return PGG_E_INVAL; }
-    if (branches > 1 && reps[0].schedule == PGG_SCHEDULE_TILED) { eerr("the tiled schedule runs one branch"); return PGG_E_INVAL; }
+    const bool tiled_sched = reps[0].schedule == PGG_SCHEDULE_TILED;
+    if (branches > 1 && tiled_sched) { eerr("the tiled schedule runs one branch"); return PGG_E_INVAL; }
+    if (res_max_L != 0 && (res_max_L < 64 || res_max_L > 256 || tiled_sched)) {
+        eerr("resident_max_L must be 0, or in [64, 256] with the 16-colour schedule");
+        return PGG_E_INVAL;
+    }
+    const int res_waves = (tune && tune->resident_waves) ? (int)tune->resident_waves : 8;
+    if (!pgg::resident_waves_valid(res_waves)) { eerr("resident_waves must be 0, 4, 8 or 16"); return PGG_E_INVAL; }
     pgg_ensemble* e = new (std::nothrow) pgg_ensemble();
     if (!e) { eerr("host allocation failed"); return PGG_E_NOMEM; }
     e->stream = (hipStream_t)hip_stream;
@@ -576,11 +226,13 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     e->n = (int)n_reps;
     e->chunk = (int)chunk;
     e->wpg = wpg;
-    e->tiled = reps[0].schedule == PGG_SCHEDULE_TILED;
+    e->res_waves = res_waves;
+    e->tiled = tiled_sched;
     if (hipGetDevice(&e->device) != hipSuccess) { eerr("no HIP device"); ens_release(e); return PGG_E_DEVICE; }
 
     // Layout: lattices back to back (256-byte aligned), tables, per-replica waves.
     std::vector<size_t> lat_off(n_reps);
+    std::vector<int> res_idx;
     size_t lat_words = 0;
     int max_words = 0;
     e->host_reps.resize(n_reps);
@@ -595,18 +247,26 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
         rp.t0 = 0;
         rp.wave_base = waves;
         rp.tiled = e->tiled ? 1 : 0;
+        rp.resident = (res_max_L != 0 && p.L <= res_max_L && pgg::resident_fits((int)p.L)) ? 1 : 0;
+        if (rp.resident) {
+            res_idx.push_back((int)k);
+            e->res_L_max = std::max(e->res_L_max, (int)p.L);
+        }
         waves += e->tiled ? pgg::tiled_blocks(rp.L) : pgg::ens_waves(rp, wpg);
         lat_off[k] = lat_words;
         lat_words += (e->tiled ? 1 : 2) * (((size_t)rp.L * rp.stride + 63) & ~(size_t)63);  // lat (and lat2)
-        if (!e->tiled) max_words = std::max(max_words, pgg::ens_wave_words(rp));
+        if (!e->tiled && !rp.resident) max_words = std::max(max_words, pgg::ens_wave_words(rp));
     }
+    e->n_res = (int)res_idx.size();
     e->total_waves = waves;
-    e->lds = e->tiled ? 0 : pgg::ens_lds_bytes(max_words, wpg);
-    // contiguous replica ranges of about equal work; wave_base restarts in each
+    e->lds = (e->tiled || max_words == 0) ? 0 : pgg::ens_lds_bytes(max_words, wpg);
+    // contiguous replica ranges of about equal segment work (sum of L^2 over
+    // the replicas that are not resident); wave_base restarts in each
     e->branches = std::max(1, std::min<int>(branches ? (int)branches : 1, (int)n_reps));
     {
         double total_work = 0.0;
-        for (uint32_t k = 0; k < n_reps; ++k) total_work += (double)reps[k].L * (double)reps[k].L;
+        for (uint32_t k = 0; k < n_reps; ++k)
+            if (!e->host_reps[k].resident) total_work += (double)reps[k].L * (double)reps[k].L;
         double acc = 0.0;
         int g = 0, base = 0;
         e->grp_first.assign(1, 0);
@@ -614,7 +274,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
             pgg::EnsRep& rp = e->host_reps[k];
             // start the next range once this one holds its share of the work
             // (every range keeps at least one replica)
-            if (g + 1 < e->branches && k > (uint32_t)e->grp_first[g] &&
+            if (g + 1 < e->branches && k > (uint32_t)e->grp_first[g] && !rp.resident &&
                 acc >= total_work * (double)(g + 1) / (double)e->branches) {
                 e->grp_waves.push_back(base);
                 e->grp_count.push_back((int)k - e->grp_first[g]);
@@ -624,7 +284,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
             }
             rp.wave_base = base;
             if (!e->tiled) base += pgg::ens_waves(rp, wpg);
-            acc += (double)reps[k].L * (double)reps[k].L;
+            if (!rp.resident) acc += (double)reps[k].L * (double)reps[k].L;
         }
         e->grp_waves.push_back(base);
         e->grp_count.push_back((int)n_reps - e->grp_first[g]);
@@ -640,15 +300,26 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
             }
         }
     }
-    for (int g = 0; e->branches > 1 && g < e->branches; ++g) {
+    // one stream per segment range with waves, one for the resident replicas,
+    // and a fork event plus one join event per stream (none when nothing forks)
+    int n_streams = 0;
+    for (int g = 0; g < e->branches; ++g) n_streams += e->grp_waves[g] > 0 ? 1 : 0;
+    n_streams += e->n_res > 0 ? 1 : 0;
+    const bool forks = !e->tiled && (e->branches > 1 || e->n_res > 0);
+    for (int g = 0; forks && g < n_streams; ++g) {
         hipStream_t bs = nullptr;
         if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) { eerr("stream creation failed"); ens_release(e); return PGG_E_DEVICE; }
         e->branch_streams.push_back(bs);
     }
-    for (int g = 0; e->branches > 1 && g <= e->branches; ++g) {
+    for (int g = 0; forks && g <= n_streams; ++g) {
         hipEvent_t ev = nullptr;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { eerr("event creation failed"); ens_release(e); return PGG_E_DEVICE; }
         e->branch_events.push_back(ev);
+    }
+    if (e->n_res > 0 && pgg::resident_lds_bytes(e->res_L_max, e->res_waves) > pgg::kMaxDynamicLds) {
+        eerr("resident replicas of side %d do not fit the LDS with %d waves", e->res_L_max, e->res_waves);
+        ens_release(e);
+        return PGG_E_INVAL;
     }
     if (e->lds > pgg::kMaxDynamicLds) {
         eerr("the widest replica layout (%d LDS words per wave) does not fit %d waves per workgroup", max_words, wpg);
@@ -670,6 +341,7 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
     if (st == PGG_OK) st = alloc((void**)&e->d_counts, (size_t)n_reps * chunk * sizeof(unsigned long long));
     if (st == PGG_OK) st = alloc((void**)&e->d_nc, (size_t)n_reps * sizeof(unsigned long long));
     if (st == PGG_OK) st = alloc((void**)&e->d_reps, (size_t)n_reps * sizeof(pgg::EnsRep));
+    if (st == PGG_OK && e->n_res > 0) st = alloc((void**)&e->d_res_idx, (size_t)e->n_res * sizeof(int));
     if (st != PGG_OK) { ens_release(e); return st; }
     for (uint32_t k = 0; k < n_reps; ++k) {
         pgg::EnsRep& rp = e->host_reps[k];
@@ -686,6 +358,9 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const ui
                                     hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess)
         err = hipMemcpyAsync(e->d_tables, tables.data(), tables.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                             e->stream);
+    if (err == hipSuccess && e->n_res > 0)
+        err = hipMemcpyAsync(e->d_res_idx, res_idx.data(), res_idx.size() * sizeof(int), hipMemcpyHostToDevice,
                              e->stream);
     if (err == hipSuccess) err = pgg::launch_fill_u64(e->d_nc, n_reps, 0ull, e->stream);
     for (uint32_t k = 0; k < n_reps && err == hipSuccess; ++k) {
@@ -771,9 +446,8 @@ pgg_status pgg_ensemble_threshold_table(pgg_ensemble* e, uint32_t rep, uint32_t*
 void pgg_ensemble_destroy(pgg_ensemble* e) { ens_release(e); }
 
 pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32_t probe_sweeps, void* hip_stream,
-                                 uint32_t* tiles_out, uint32_t* chunk_out, uint32_t* wpg_out, uint32_t* branches_out,
-                                 double* ms_out) {
-    if (!reps || !tiles_out || !chunk_out || !wpg_out || !branches_out) { eerr("NULL argument"); return PGG_E_INVAL; }
+                                 uint32_t* tiles_out, pgg_ensemble_tune* tune_out, double* ms_out) {
+    if (!reps || !tiles_out || !tune_out) { eerr("NULL argument"); return PGG_E_INVAL; }
     if (probe_sweeps == 0 || probe_sweeps > 4096) { eerr("probe_sweeps must lie in [1, 4096]"); return PGG_E_INVAL; }
     const pgg_status vs = validate_reps(reps, n_reps, nullptr, 1);
     if (vs != PGG_OK) return vs;
@@ -783,8 +457,8 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         if (std::find(sizes.begin(), sizes.end(), reps[k].L) == sizes.end()) sizes.push_back(reps[k].L);
     std::map<uint32_t, uint32_t> width;  // current choice per L (0 = automatic)
     for (uint32_t L : sizes) width[L] = 0;
-    uint32_t chunk = 32, wpg = (uint32_t)pgg::kWavesPerGroup, branches = 1;
-    std::vector<uint64_t> fingerprint, nc(n_reps);
+    uint32_t chunk = 32, wpg = (uint32_t)pgg::kWavesPerGroup, branches = 1, res_max_L = 0, res_waves = 8;
+    std::vector<uint64_t> nc(n_reps);
     std::vector<uint32_t> tiles(n_reps);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
@@ -792,27 +466,35 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         eerr("event creation failed");
         return PGG_E_DEVICE;
     }
-    // One trial: a fresh ensemble with the current choices; best of two timed runs.
+    // One trial: a fresh ensemble with the current choices, one untimed run
+    // (graph capture, clocks) and the best of three timed runs of n_probe
+    // sweeps each -- at least 64 and two replays of the chunk, so that the
+    // graph replays, not their capture, are timed.  Trials of equal n_probe
+    // must end with equal cooperator counts.
+    std::map<uint32_t, std::vector<uint64_t>> fingerprints;  // by n_probe
     auto trial = [&](double* ms) -> pgg_status {
+        const uint32_t n_probe = std::max(std::max(probe_sweeps, 64u), 2 * chunk);
         for (uint32_t k = 0; k < n_reps; ++k) tiles[k] = width[reps[k].L];
         pgg_ensemble* e = nullptr;
-        pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.data(), chunk, wpg, branches, hip_stream, &e);
+        const pgg_ensemble_tune tn = {tiles.data(), chunk, wpg, branches, res_max_L, res_waves};
+        pgg_status st = pgg_ensemble_create(reps, n_reps, &tn, hip_stream, &e);
         if (st != PGG_OK) return st;
-        st = pgg_ensemble_sweep(e, 2, nullptr);
+        st = pgg_ensemble_sweep(e, n_probe, nullptr);
         double best = 1e300;
-        for (int rep = 0; rep < 2 && st == PGG_OK; ++rep) {
+        for (int rep = 0; rep < 3 && st == PGG_OK; ++rep) {
             hipError_t err = hipEventRecord(ev0, e->stream);
-            if (err == hipSuccess) st = pgg_ensemble_sweep(e, probe_sweeps, nullptr);
+            if (err == hipSuccess) st = pgg_ensemble_sweep(e, n_probe, nullptr);
             if (err == hipSuccess && st == PGG_OK) err = hipEventRecord(ev1, e->stream);
             if (err == hipSuccess && st == PGG_OK) err = hipEventSynchronize(ev1);
             float f = 0.f;
             if (err == hipSuccess && st == PGG_OK) err = hipEventElapsedTime(&f, ev0, ev1);
             if (err != hipSuccess) { eerr("autotune timing: %s", hipGetErrorString(err)); st = PGG_E_DEVICE; }
-            best = std::min(best, (double)f / probe_sweeps);
+            best = std::min(best, (double)f / n_probe);
         }
         if (st == PGG_OK) st = pgg_ensemble_coop_counts(e, nc.data());
         pgg_ensemble_destroy(e);
         if (st != PGG_OK) return st;
+        std::vector<uint64_t>& fingerprint = fingerprints[n_probe];
         if (fingerprint.empty()) {
             fingerprint = nc;
         } else if (fingerprint != nc) {
@@ -823,8 +505,15 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         return PGG_OK;
     };
     double best_ms = 0.0;
-    pgg_status st = trial(&best_ms);
-    for (size_t q = 0; q < sizes.size() && st == PGG_OK; ++q) {
+    pgg_status st = trial(&best_ms);  // warms the device; timed again below
+    if (st == PGG_OK) st = trial(&best_ms);
+    // widths: the distinct sides with the most work (sum of L^2) first, at
+    // most kTunedSides of them; the others keep the automatic width
+    std::map<uint32_t, double> work;
+    for (uint32_t k = 0; k < n_reps; ++k) work[reps[k].L] += (double)reps[k].L * (double)reps[k].L;
+    std::stable_sort(sizes.begin(), sizes.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
+    constexpr size_t kTunedSides = 6;
+    for (size_t q = 0; q < std::min(sizes.size(), kTunedSides) && st == PGG_OK; ++q) {
         const uint32_t L = sizes[q];
         const uint32_t cap = (L - 32) & ~31u;
         std::vector<uint32_t> cand;
@@ -855,16 +544,37 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_wpg = g; }
     }
     wpg = best_wpg;
+    // concurrent groups and resident sweeps of the replicas that fit one
+    // workgroup's LDS (a chunk per launch, beside the segment launches) are
+    // tried together: the resident branch changes which group split is best
+    bool any_res = false;
+    for (uint32_t k = 0; k < n_reps; ++k) any_res = any_res || pgg::resident_fits((int)reps[k].L);
     const uint32_t branch_counts[] = {1, 2, 4};
-    uint32_t best_branches = branches;
+    const uint32_t res_sides[] = {0, 128, 256};
+    uint32_t best_branches = branches, best_res = res_max_L;
     for (uint32_t bcount : branch_counts) {
-        if (st != PGG_OK || bcount == best_branches || bcount > n_reps) continue;
-        branches = bcount;
-        double ms = 0.0;
-        st = trial(&ms);
-        if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_branches = bcount; }
+        for (uint32_t rl : res_sides) {
+            if (st != PGG_OK || (bcount == best_branches && rl == best_res) || bcount > n_reps) continue;
+            if (rl != 0 && !any_res) continue;
+            branches = bcount;
+            res_max_L = rl;
+            double ms = 0.0;
+            st = trial(&ms);
+            if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_branches = bcount; best_res = rl; }
+        }
     }
     branches = best_branches;
+    res_max_L = best_res;
+    uint32_t best_res_waves = res_waves;
+    const uint32_t res_wave_counts[] = {4, 16};
+    for (uint32_t rw : res_wave_counts) {
+        if (st != PGG_OK || res_max_L == 0) break;
+        res_waves = rw;
+        double ms = 0.0;
+        st = trial(&ms);
+        if (st == PGG_OK && ms < best_ms) { best_ms = ms; best_res_waves = rw; }
+    }
+    res_waves = best_res_waves;
     const uint32_t chunks[] = {8, 16, 32, 64, 128};
     uint32_t best_chunk = chunk;
     for (uint32_t c : chunks) {
@@ -887,9 +597,12 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         }
         tiles_out[k] = w;
     }
-    *chunk_out = best_chunk;
-    *wpg_out = best_wpg;
-    *branches_out = best_branches;
+    tune_out->tiles = tiles_out;
+    tune_out->chunk = best_chunk;
+    tune_out->waves_per_group = best_wpg;
+    tune_out->branches = best_branches;
+    tune_out->resident_max_L = best_res;
+    tune_out->resident_waves = best_res ? best_res_waves : 0;
     if (ms_out) *ms_out = best_ms;
     return PGG_OK;
 }
@@ -899,21 +612,16 @@ pgg_status pgg_ensemble_run(const pgg_params* reps, uint32_t n_reps, uint32_t n_
     const pgg_status vs = validate_reps(reps, n_reps, tune ? tune->tiles : nullptr, tune ? tune->chunk : 1);
     if (vs != PGG_OK) return vs;
     std::vector<uint32_t> tiles;
-    uint32_t chunk = 32, wpg = 0, branches = 0;
+    pgg_ensemble_tune tuned = {nullptr, 32, 0, 0, 0, 0};
     if (tune) {
-        chunk = tune->chunk;
-        wpg = tune->waves_per_group;
-        branches = tune->branches;
-        if (tune->tiles) tiles.assign(tune->tiles, tune->tiles + n_reps);
+        tuned = *tune;
     } else if (reps[0].schedule != PGG_SCHEDULE_TILED) {
         tiles.resize(n_reps);
-        const pgg_status st = pgg_ensemble_autotune(reps, n_reps, 8, hip_stream, tiles.data(), &chunk, &wpg,
-                                                    &branches, nullptr);
+        const pgg_status st = pgg_ensemble_autotune(reps, n_reps, 8, hip_stream, tiles.data(), &tuned, nullptr);
         if (st != PGG_OK) return st;
     }
     pgg_ensemble* e = nullptr;
-    pgg_status st = pgg_ensemble_create(reps, n_reps, tiles.empty() ? nullptr : tiles.data(), chunk, wpg, branches,
-                                        hip_stream, &e);
+    pgg_status st = pgg_ensemble_create(reps, n_reps, &tuned, hip_stream, &e);
     if (st != PGG_OK) return st;
     st = pgg_ensemble_sweep(e, n_sweeps, counts);
     if (st == PGG_OK) {

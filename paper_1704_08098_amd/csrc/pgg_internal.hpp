@@ -124,7 +124,13 @@ struct EnsRep {
     int rpw;                    // full-row sweep (segw == L): rows per wave; 0 = segments
     uint32_t k0, k1, t0;
     int tiled;                  // 1: the double-tiling schedule (in place; wave_base counts workgroups)
+    int resident;               // 1: swept by the resident kernel (in place, a chunk per launch; no segment waves)
 };
+
+// Ensemble form of the resident sweep: workgroup b of n runs the current
+// chunk of replica d_idx[b] (n_active sweeps from t0, in place); L_max is
+// the largest side among them (it sizes the LDS), W waves per workgroup.
+hipError_t launch_ens_resident(const EnsRep* d_reps, const int* d_idx, int n, int L_max, int W, hipStream_t st);
 
 // Automatic work split for side L: L itself (whole rows per wave) when L is
 // a multiple of 32 and at most 1024, else a segment width (a multiple of 32,

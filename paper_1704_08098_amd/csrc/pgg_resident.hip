@@ -32,11 +32,14 @@ namespace {
 __host__ __device__ inline int resident_rows_per_wave(int L, int W) { return (L / 4 + W - 1) / W; }
 __host__ __device__ inline int resident_list_words(int L, int W) { return resident_rows_per_wave(L, W) * (L / 4) + 8; }
 
+// The resident sweep of one lattice by the calling workgroup of W waves:
+// load the lattice into LDS, run n sweeps from t0 (per-sweep count changes
+// into delta[q]), write it back.
 template <int W>
-__global__ void __launch_bounds__(64 * W)
-k_resident(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n, uint32_t k0, uint32_t k1,
-           const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta,
-           unsigned long long* __restrict__ drawn) {
+__device__ __forceinline__ void resident_run(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n,
+                                             uint32_t k0, uint32_t k1, const uint32_t* __restrict__ T,
+                                             unsigned long long* __restrict__ delta,
+                                             unsigned long long* __restrict__ drawn) {
     extern __shared__ uint32_t smem[];
     uint32_t* sT = smem;
     const int nw = L >> 5, ldw = nw + 2;
@@ -96,6 +99,25 @@ k_resident(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n, ui
     }
 }
 
+template <int W>
+__global__ void __launch_bounds__(64 * W)
+k_resident(uint32_t* __restrict__ lat, int L, int stride, uint32_t t0, int n, uint32_t k0, uint32_t k1,
+           const uint32_t* __restrict__ T, unsigned long long* __restrict__ delta,
+           unsigned long long* __restrict__ drawn) {
+    resident_run<W>(lat, L, stride, t0, n, k0, k1, T, delta, drawn);
+}
+
+// Ensemble form: workgroup b runs the current chunk (n_active sweeps from
+// t0) of replica idx[b], in place, its per-sweep count changes into the
+// replica's own counters.
+template <int W>
+__global__ void __launch_bounds__(64 * W)
+k_ens_resident(const EnsRep* __restrict__ reps, const int* __restrict__ idx) {
+    const EnsRep& rp = reps[idx[blockIdx.x]];
+    if (rp.n_active <= 0) return;
+    resident_run<W>(rp.lat, rp.L, rp.stride, rp.t0, rp.n_active, rp.k0, rp.k1, rp.T, rp.delta, rp.drawn);
+}
+
 }  // namespace
 
 bool resident_fits(int L) { return L % 32 == 0 && L >= 64 && L <= 256; }
@@ -120,6 +142,19 @@ hipError_t launch_resident(uint32_t* lat, int L, int stride, int W, uint32_t t0,
     else
         hipLaunchKernelGGL(k_resident<16>, dim3(1), dim3(1024), lds, st, lat, L, stride, t0, n, k0, k1, T, delta,
                            drawn);
+    return hipGetLastError();
+}
+
+hipError_t launch_ens_resident(const EnsRep* d_reps, const int* d_idx, int n, int L_max, int W, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!resident_waves_valid(W)) return hipErrorInvalidValue;
+    const size_t lds = resident_lds_bytes(L_max, W);
+    if (W == 4)
+        hipLaunchKernelGGL(k_ens_resident<4>, dim3(n), dim3(256), lds, st, d_reps, d_idx);
+    else if (W == 8)
+        hipLaunchKernelGGL(k_ens_resident<8>, dim3(n), dim3(512), lds, st, d_reps, d_idx);
+    else
+        hipLaunchKernelGGL(k_ens_resident<16>, dim3(n), dim3(1024), lds, st, d_reps, d_idx);
     return hipGetLastError();
 }
 

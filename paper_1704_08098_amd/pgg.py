@@ -54,7 +54,21 @@ class PggParams(ctypes.Structure):
 
 class PggEnsembleTune(ctypes.Structure):
     _fields_ = [("tiles", ctypes.POINTER(ctypes.c_uint32)), ("chunk", ctypes.c_uint32),
-                ("waves_per_group", ctypes.c_uint32), ("branches", ctypes.c_uint32)]
+                ("waves_per_group", ctypes.c_uint32), ("branches", ctypes.c_uint32),
+                ("resident_max_L", ctypes.c_uint32), ("resident_waves", ctypes.c_uint32)]
+
+
+TUNE_KEYS = ("chunk", "waves_per_group", "branches", "resident_max_L", "resident_waves")
+
+
+def _tune_struct(tiles=None, chunk=32, waves_per_group=0, branches=0, resident_max_L=0, resident_waves=0):
+    """(PggEnsembleTune, the tiles array it points at -- keep it alive)."""
+    tl = None
+    if tiles is not None:
+        tl = np.ascontiguousarray(np.asarray(tiles, dtype=np.uint32))
+    t = PggEnsembleTune(tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None else None,
+                        int(chunk), int(waves_per_group), int(branches), int(resident_max_L), int(resident_waves))
+    return t, tl
 
 
 class PggServerInfo(ctypes.Structure):
@@ -100,8 +114,7 @@ def load():
         "pgg_set_strip_wait": (ctypes.c_int, [vp, ctypes.c_double]),
         "pgg_destroy": (None, [vp]),
         "pgg_last_error": (ctypes.c_char_p, []),
-        "pgg_ensemble_create": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, u32p, ctypes.c_uint32,
-                                               ctypes.c_uint32, ctypes.c_uint32, vp, P(vp)]),
+        "pgg_ensemble_create": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, P(PggEnsembleTune), vp, P(vp)]),
         "pgg_ensemble_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, u64p]),
         "pgg_ensemble_coop_counts": (ctypes.c_int, [vp, u64p]),
         "pgg_ensemble_sweep_index": (ctypes.c_int, [vp, u64p]),
@@ -110,8 +123,8 @@ def load():
         "pgg_ensemble_threshold_table": (ctypes.c_int, [vp, ctypes.c_uint32, u32p]),
         "pgg_ensemble_run": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, u64p,
                                             P(PggEnsembleTune), vp]),
-        "pgg_ensemble_autotune": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, vp, u32p, u32p,
-                                                 u32p, u32p, P(ctypes.c_double)]),
+        "pgg_ensemble_autotune": (ctypes.c_int, [P(PggParams), ctypes.c_uint32, ctypes.c_uint32, vp, u32p,
+                                                 P(PggEnsembleTune), P(ctypes.c_double)]),
         "pgg_server_job_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
         "pgg_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                              vp, P(vp)]),
@@ -348,39 +361,37 @@ def _replica_params(replicas):
 
 
 def ensemble_autotune(replicas, probe_sweeps=8, stream=None):
-    """pgg_ensemble_autotune: (tiles per replica, chunk, waves per group,
-    concurrent replica groups, ms per sweep)."""
+    """pgg_ensemble_autotune: (tune, ms) -- tune a dict with the chosen tiles
+    (one per replica), chunk, waves_per_group, branches, resident_max_L and
+    resident_waves (the keyword arguments of Ensemble), ms the best time per
+    sweep."""
     n = len(replicas)
     arr = _replica_params(replicas)
     tiles = np.zeros(n, dtype=np.uint32)
-    chunk = ctypes.c_uint32()
-    wpg = ctypes.c_uint32()
-    branches = ctypes.c_uint32()
+    tune = PggEnsembleTune()
     ms = ctypes.c_double()
     _check(load().pgg_ensemble_autotune(arr, n, int(probe_sweeps), _stream_handle(stream),
-                                        tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
-                                        ctypes.byref(chunk), ctypes.byref(wpg), ctypes.byref(branches),
+                                        tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(tune),
                                         ctypes.byref(ms)))
-    return tiles, int(chunk.value), int(wpg.value), int(branches.value), float(ms.value)
+    out = {k: int(getattr(tune, k)) for k in TUNE_KEYS}
+    out["tiles"] = tiles
+    return out, float(ms.value)
 
 
 def ensemble_run(replicas, n_sweeps, tune=None, stream=None):
     """pgg_ensemble_run: counts (n_reps, n_sweeps) of one batched run from the
-    initial states.  tune: None (autotune) or a dict with chunk,
-    waves_per_group, branches and optionally tiles."""
+    initial states.  tune: None (autotune) or a dict with the keyword
+    arguments of Ensemble (tiles, chunk, waves_per_group, branches,
+    resident_max_L, resident_waves)."""
     n = len(replicas)
     arr = _replica_params(replicas)
     out = np.zeros((n, max(int(n_sweeps), 1)), dtype=np.uint64)
-    t = None
+    t, keep = None, None
     if tune is not None:
-        tl = None
-        if tune.get("tiles") is not None:
-            tl = np.ascontiguousarray(np.asarray(tune["tiles"], dtype=np.uint32))
-        t = PggEnsembleTune(tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None else None,
-                            int(tune.get("chunk", 32)), int(tune.get("waves_per_group", 0)),
-                            int(tune.get("branches", 0)))
+        t, keep = _tune_struct(**{k: v for k, v in tune.items() if k in TUNE_KEYS + ("tiles",)})
     _check(load().pgg_ensemble_run(arr, n, int(n_sweeps), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                    ctypes.byref(t) if t is not None else None, _stream_handle(stream)))
+    del keep
     return out[:, :n_sweeps]
 
 
@@ -391,24 +402,22 @@ class Ensemble:
     tiles: optional per-replica segment widths (0 = automatic).
     waves_per_group: segment waves per workgroup, 2, 4 or 8 (0 = 4).
     branches: concurrent replica groups (parallel graph branches), 0..16.
+    resident_max_L: 0, or the largest side swept by the resident kernel.
+    resident_waves: waves per resident workgroup, 4, 8 or 16 (0 = 8).
     """
 
-    def __init__(self, replicas, tiles=None, chunk=32, stream=None, waves_per_group=0, branches=0):
+    def __init__(self, replicas, tiles=None, chunk=32, stream=None, waves_per_group=0, branches=0,
+                 resident_max_L=0, resident_waves=0):
         lib = load()
         n = len(replicas)
         arr = _replica_params(replicas)
         self.L = [int(rp["L"]) for rp in replicas]
         self.n = n
-        tl = None
-        if tiles is not None:
-            tl = np.ascontiguousarray(np.asarray(tiles, dtype=np.uint32))
-            assert tl.shape == (n,)
-        self._tiles = tl
+        tune, self._tiles = _tune_struct(tiles, chunk, waves_per_group, branches, resident_max_L, resident_waves)
+        if self._tiles is not None:
+            assert self._tiles.shape == (n,)
         h = ctypes.c_void_p()
-        _check(lib.pgg_ensemble_create(arr, n,
-                                       tl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if tl is not None
-                                       else None, int(chunk), int(waves_per_group), int(branches),
-                                       _stream_handle(stream), ctypes.byref(h)))
+        _check(lib.pgg_ensemble_create(arr, n, ctypes.byref(tune), _stream_handle(stream), ctypes.byref(h)))
         self.handle = h
 
     def sweep(self, n_sweeps, want_counts=True):

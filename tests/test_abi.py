@@ -155,4 +155,4 @@ def test_ensemble_autotune_rejects_bad_arguments(pgg):
             pgg.ensemble_autotune(reps, probe_sweeps=probe)
         assert e.value.status == pgg.PGG_E_INVAL
     lib = pgg.load()
-    assert lib.pgg_ensemble_autotune(None, 1, 4, None, None, None, None, None, None) == pgg.PGG_E_INVAL
+    assert lib.pgg_ensemble_autotune(None, 1, 4, None, None, None, None) == pgg.PGG_E_INVAL

@@ -120,8 +120,10 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
     reps = [dict(L=128, r=3.8, seed=11), dict(L=256, r=3.7, seed=12), dict(L=128, r=3.9, seed=13),
             dict(L=256, r=3.65, seed=14), dict(L=96, r=4.0, seed=15)]
     say("autotune over", [rp["L"] for rp in reps])
-    tiles, chunk, wpg, branches, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
-    assert chunk in (8, 16, 32, 64, 128) and wpg in (2, 4, 8) and ms > 0.0
+    tune, ms = pgg.ensemble_autotune(reps, probe_sweeps=4)
+    tiles = tune["tiles"]
+    assert tune["chunk"] in (8, 16, 32, 64, 128) and tune["waves_per_group"] in (2, 4, 8) and ms > 0.0
+    assert tune["branches"] in (1, 2, 4) and tune["resident_max_L"] in (0, 128, 256)
     by_L = {}
     for rp, w in zip(reps, tiles):
         # segments of a multiple of 32 columns up to L - 32, or whole rows (L)
@@ -129,8 +131,7 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
         by_L.setdefault(rp["L"], set()).add(int(w))
     assert all(len(ws) == 1 for ws in by_L.values())
     n = 21
-    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk, waves_per_group=wpg, branches=branches) as a, \
-            pgg.Ensemble(reps) as b:
+    with pgg.Ensemble(reps, **tune) as a, pgg.Ensemble(reps) as b:
         ca, cb = a.sweep(n), b.sweep(n)
         assert np.array_equal(ca, cb)
         ref, _, counts = oracle_lib.run(256, 3.7, 0.5, 0.5, 12, n)
@@ -333,3 +334,41 @@ def test_one_shot_run_equals_the_handle_calls(pgg, oracle_lib):
     assert np.array_equal(pgg.ensemble_run(reps, n, tune=dict(chunk=4, waves_per_group=2, branches=2)), ref)
     _, _, counts = oracle_lib.run(100, 4.0, 0.5, 0.5, 302, n)
     assert np.array_equal(ref[2], counts)
+
+
+@pytest.mark.parametrize("res_L,res_waves,branches", [(128, 4, 0), (256, 8, 0), (256, 16, 2), (256, 0, 4),
+                                                      (64, 4, 2)])
+def test_resident_replicas_do_not_change_results(pgg, oracle_lib, res_L, res_waves, branches):
+    """Replicas of side a multiple of 32 up to resident_max_L swept whole in
+    LDS (a chunk of sweeps per launch) beside the segment launches of the
+    others: counts after every sweep, coop counts and lattices equal the
+    plain ensemble's, and a resident and a segment replica equal the oracle
+    (chunks of 8 with a short tail; sides that do not fit -- not a multiple
+    of 32, or too large -- stay on the segment path)."""
+    reps = [dict(L=L, r=r, seed=400 + k) for k, (L, r) in
+            enumerate([(64, 3.8), (96, 3.9), (100, 4.0), (128, 3.75), (160, 4.2), (196, 3.85), (224, 3.7),
+                       (256, 3.95), (512, 3.8), (68, 4.4)])]
+    n = 19
+    tune = dict(chunk=8, branches=branches, resident_max_L=res_L, resident_waves=res_waves)
+    say("ensemble with resident sides up to", res_L, "waves", res_waves, "branches", branches)
+    with pgg.Ensemble(reps, **tune) as a, pgg.Ensemble(reps, chunk=8) as b:
+        ca = np.concatenate([a.sweep(11), a.sweep(8)], axis=1)
+        cb = b.sweep(n)
+        assert np.array_equal(ca, cb)
+        for k in range(len(reps)):
+            assert np.array_equal(a.read_lattice(k), b.read_lattice(k)), k
+        assert np.array_equal(a.coop_counts(), b.coop_counts())
+    for k in (0, 2):  # L = 64 is resident for every setting here, L = 100 never
+        rp = reps[k]
+        ref, _, counts = oracle_lib.run(rp["L"], rp["r"], 0.5, 0.5, rp["seed"], n)
+        assert np.array_equal(ca[k], counts), k
+
+
+def test_resident_settings_refused_where_they_do_not_apply(pgg):
+    one = [dict(L=128, r=3.8, seed=1)]
+    for bad in (dict(resident_max_L=32), dict(resident_max_L=300), dict(resident_max_L=128, resident_waves=3),
+                dict(resident_max_L=128, resident_waves=32)):
+        with pytest.raises(pgg.PggError):
+            pgg.Ensemble(one, **bad)
+    with pytest.raises(pgg.PggError):
+        pgg.Ensemble([dict(L=128, r=3.8, seed=1, schedule="tiled")], resident_max_L=128)

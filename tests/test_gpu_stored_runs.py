@@ -72,9 +72,9 @@ def test_batched_ensemble_against_stored_oracle_runs(pgg):
     n = head["sweeps"]
     reps = wl.ensemble_replicas(sweeps=n)
     say("autotuning the 256-replica ensemble")
-    tiles, chunk, wpg, branches, _ = pgg.ensemble_autotune(reps, probe_sweeps=8)
-    say("ensemble: 256 replicas, %d sweeps, chunk %d, waves per group %d, branches %d" % (n, chunk, wpg, branches))
-    with pgg.Ensemble(reps, tiles=tiles, chunk=chunk, waves_per_group=wpg, branches=branches) as ens:
+    tune, _ = pgg.ensemble_autotune(reps, probe_sweeps=8)
+    say("ensemble: 256 replicas, %d sweeps, tuning %s" % (n, {k: tune[k] for k in pgg.TUNE_KEYS}))
+    with pgg.Ensemble(reps, **tune) as ens:
         counts = np.concatenate([ens.sweep(1000), ens.sweep(1500), ens.sweep(2500)], axis=1)
         assert counts.shape == (len(reps), n)
         for parts in rows:
