@@ -130,7 +130,9 @@ typedef enum {
                                width, a multiple of 32 up to L - 64 (0 =
                                automatic); group must be 0.  int8 layout: as
                                for SEGMENT, through a bit-packed working copy */,
-    PGG_KERNEL_RESIDENT = 8 /* L a multiple of 32, 64 <= L <= 256: one
+    PGG_KERNEL_RESIDENT = 8 /* L a multiple of 32, 64 <= L <= 512 (above
+                               256 it takes more than 64 KB of LDS: the
+                               device's per-workgroup limit decides): one
                                workgroup of `group` waves (4, 8 or 16; 0 =
                                automatic) keeps the whole lattice in
                                LDS (with 3 periodic halo rows above and below)
@@ -365,7 +367,7 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
  *              own chain of launches, and the chains run side by side as
  *              parallel branches of the chunk's graph.  The tiled schedule
  *              takes 0 or 1.
- *   resident_max_L  0, or a side in [64, 256]: replicas with L a multiple of
+ *   resident_max_L  0, or a side in [64, 512]: replicas with L a multiple of
  *              32 up to this side are swept by the resident kernel instead
  *              -- one workgroup per replica holds its lattice in LDS and
  *              runs the whole chunk in one launch -- as one more parallel
@@ -438,7 +440,7 @@ void pgg_ensemble_destroy(pgg_ensemble* e);
  * whole rows (L, when L is a multiple of 32), the other sizes held at their
  * best so far, then the waves per workgroup over 2, 4, 8, then the
  * concurrent groups over 1, 2, 4 together with resident sweeps off, up to
- * L = 128 or up to 256 (when some replica fits), then their 4, 8 or 16
+ * L = 128 or 256 (when some replica fits), then their 4, 8 or 16
  * waves, then the chunk over 8, 16, 32, 64, 128; each trial runs once
  * untimed and keeps its best of three timed runs.  Every trial's final
  * cooperator counts must equal those of the first trial of the same length, else

@@ -2,6 +2,7 @@
 // around the kernels.  Declarations and the contract are in include/pgg.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -42,6 +43,31 @@ void set_errorf(const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+}
+
+size_t max_dynamic_lds() {
+    constexpr size_t kFallback = 64 * 1024;
+    constexpr int kDevices = 64;
+    static std::atomic<size_t> cache[kDevices];  // 0 = not looked up yet
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return kFallback;
+    size_t v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int bytes = 0;
+        v = (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+             bytes >= (int)kFallback)
+                ? (size_t)bytes
+                : kFallback;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+bool allow_dynamic_lds(const void* kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return true;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) return true;
+    (void)hipGetLastError();  // leave no sticky error behind
+    return false;
 }
 }  // namespace pgg
 
@@ -134,9 +160,9 @@ size_t segment_lds(uint32_t L, int segw, int wpg) {
 // narrowed until the workgroup's LDS fits.
 int choose_segw(uint32_t L, int wpg) {
     int w = pgg::auto_segw((int)L);
-    if (w == (int)L && segment_lds(L, w, wpg) <= pgg::kMaxDynamicLds) return w;
+    if (w == (int)L && segment_lds(L, w, wpg) <= pgg::max_dynamic_lds()) return w;
     if (w == (int)L) w = ((int)L - 32) & ~31;
-    while (w > 32 && segment_lds(L, w, wpg) > pgg::kMaxDynamicLds) w -= 32;
+    while (w > 32 && segment_lds(L, w, wpg) > pgg::max_dynamic_lds()) w -= 32;
     return w;
 }
 
@@ -147,7 +173,7 @@ int choose_pair_segw(uint32_t L) {
     int w = ((int)L / nseg + 31) & ~31;
     const int cap = ((int)L - 64) & ~31;
     if (w > cap) w = cap;
-    while (w > 32 && pgg::pair_lds_bytes(w) > pgg::kMaxDynamicLds) w -= 32;
+    while (w > 32 && pgg::pair_lds_bytes(w) > pgg::max_dynamic_lds()) w -= 32;
     return w;
 }
 
@@ -163,7 +189,7 @@ bool pair_fits(const pgg_params* p, int device) {
         return false;
     const int segw = choose_pair_segw(p->L);
     const long blocks = (long)((p->L + pgg::kPairBand - 1) / pgg::kPairBand) * (long)((p->L + segw - 1) / segw);
-    return blocks >= cus && blocks <= 2L * cus && pgg::pair_lds_bytes(segw) <= pgg::kMaxDynamicLds;
+    return blocks >= cus && blocks <= 2L * cus && pgg::pair_lds_bytes(segw) <= pgg::max_dynamic_lds();
 }
 
 }  // namespace
@@ -185,7 +211,7 @@ void auto_segment_plan(uint32_t L, int device, bool* pair, int* segw) {
 namespace {
 
 bool strip_fits(uint32_t L, uint32_t H) {
-    return pgg::strip_lds_bytes((int)L, (int)H, 1) <= pgg::kMaxDynamicLds;
+    return pgg::strip_lds_bytes((int)L, (int)H, 1) <= pgg::max_dynamic_lds();
 }
 
 bool params_valid(const pgg_params* p, const char** why) {
@@ -235,7 +261,7 @@ bool params_valid(const pgg_params* p, const char** why) {
             const size_t lds = p->kernel == PGG_KERNEL_ROWBAND_STAGED
                                    ? pgg::staged_lds_bytes((int)p->L, R)
                                    : pgg::rowband_lds_bytes((int)p->L, R, p->kernel == PGG_KERNEL_ROWBAND_COMPACT);
-            if (lds > pgg::kMaxDynamicLds) { *why = "the kernel's LDS footprint does not fit at this L and tile"; return false; }
+            if (lds > pgg::max_dynamic_lds()) { *why = "the kernel's LDS footprint does not fit at this L and tile"; return false; }
             break;
         }
         case PGG_KERNEL_SEGMENT: {
@@ -243,7 +269,7 @@ bool params_valid(const pgg_params* p, const char** why) {
             if (tr != 0 && !pgg::segw_valid((int)p->L, (int)tr)) { *why = "segment tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)"; return false; }
             const int wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
             if (!pgg::ens_wpg_valid(wpg)) { *why = "group must be 0, 2, 4 or 8"; return false; }
-            if (segment_lds(p->L, tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::kMaxDynamicLds) {
+            if (segment_lds(p->L, tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::max_dynamic_lds()) {
                 *why = "the segment kernel's LDS footprint does not fit at this tile and group";
                 return false;
             }
@@ -253,14 +279,14 @@ bool params_valid(const pgg_params* p, const char** why) {
             if (p->L < 512 || p->L % 32 != 0) { *why = "the paired segment kernel needs L >= 512, a multiple of 32"; return false; }
             if (tr != 0 && (tr % 32 != 0 || tr + 64 > p->L)) { *why = "paired segment tile must be a multiple of 32 and <= L - 64"; return false; }
             if (p->group != 0) { *why = "the paired segment kernel takes no group"; return false; }
-            if (pgg::pair_lds_bytes(tr ? (int)tr : choose_pair_segw(p->L)) > pgg::kMaxDynamicLds) {
+            if (pgg::pair_lds_bytes(tr ? (int)tr : choose_pair_segw(p->L)) > pgg::max_dynamic_lds()) {
                 *why = "the paired segment kernel's LDS footprint does not fit at this tile";
                 return false;
             }
             break;
         }
         case PGG_KERNEL_RESIDENT:
-            if (!pgg::resident_fits((int)p->L)) { *why = "the resident kernel needs L a multiple of 32 in [64, 256]"; return false; }
+            if (!pgg::resident_fits((int)p->L)) { *why = "the resident kernel needs L a multiple of 32 in [64, 512]"; return false; }
             if (tr != 0) { *why = "the resident kernel takes tile 0"; return false; }
             if (p->group != 0 && !pgg::resident_waves_valid((int)p->group)) {
                 *why = "the resident kernel's group (waves) must be 0, 4, 8 or 16";

@@ -351,6 +351,11 @@ hipError_t launch_ens_begin(EnsRep* d_reps, int n, int len, int chunk, bool set_
 hipError_t launch_ens_residue(const EnsRep* d_reps, int n, int total_waves, size_t lds, int a, int q,
                               hipStream_t st, int wpg, unsigned long long* span) {
     const dim3 grid(total_waves / wpg), block(64 * wpg);
+    if (lds > 64 * 1024) {  // wide explicit tiles: the per-kernel LDS attribute
+        const void* kern = wpg == 2 ? (const void*)k_ens_segment<2>
+                                    : wpg == 4 ? (const void*)k_ens_segment<4> : (const void*)k_ens_segment<8>;
+        if (!allow_dynamic_lds(kern, lds)) return hipErrorInvalidValue;
+    }
     switch (wpg) {
         case 2: hipLaunchKernelGGL(k_ens_segment<2>, grid, block, lds, st, d_reps, n, a, q, span); break;
         case 4: hipLaunchKernelGGL(k_ens_segment<4>, grid, block, lds, st, d_reps, n, a, q, span); break;
@@ -391,6 +396,7 @@ int pair_blocks(const EnsRep& rp) { return (rp.L + kPairBand - 1) / kPairBand * 
 
 hipError_t launch_pair_chunk(EnsRep* d_rep, int blocks, size_t lds, int len, int chunk, unsigned long long* counts,
                              hipStream_t st, unsigned long long* span) {
+    if (!allow_dynamic_lds((const void*)k_ens_pair<kPairBand>, lds)) return hipErrorInvalidValue;
     hipError_t err = launch_ens_begin(d_rep, 1, len, chunk, true, st);
     for (int q = 0; err == hipSuccess && q < len; ++q)
         for (int h = 0; err == hipSuccess && h < 2; ++h) {

@@ -210,8 +210,8 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const pg
     if (branches > 16) { eerr("branches must lie in [0, 16]"); return PGG_E_INVAL; }
     const bool tiled_sched = reps[0].schedule == PGG_SCHEDULE_TILED;
     if (branches > 1 && tiled_sched) { eerr("the tiled schedule runs one branch"); return PGG_E_INVAL; }
-    if (res_max_L != 0 && (res_max_L < 64 || res_max_L > 256 || tiled_sched)) {
-        eerr("resident_max_L must be 0, or in [64, 256] with the 16-colour schedule");
+    if (res_max_L != 0 && (res_max_L < 64 || res_max_L > (uint32_t)pgg::kResidentMaxL || tiled_sched)) {
+        eerr("resident_max_L must be 0, or in [64, %d] with the 16-colour schedule", pgg::kResidentMaxL);
         return PGG_E_INVAL;
     }
     const int res_waves = (tune && tune->resident_waves) ? (int)tune->resident_waves : 8;
@@ -316,12 +316,12 @@ pgg_status pgg_ensemble_create(const pgg_params* reps, uint32_t n_reps, const pg
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { eerr("event creation failed"); ens_release(e); return PGG_E_DEVICE; }
         e->branch_events.push_back(ev);
     }
-    if (e->n_res > 0 && pgg::resident_lds_bytes(e->res_L_max, e->res_waves) > pgg::kMaxDynamicLds) {
+    if (e->n_res > 0 && pgg::resident_lds_bytes(e->res_L_max, e->res_waves) > pgg::max_dynamic_lds()) {
         eerr("resident replicas of side %d do not fit the LDS with %d waves", e->res_L_max, e->res_waves);
         ens_release(e);
         return PGG_E_INVAL;
     }
-    if (e->lds > pgg::kMaxDynamicLds) {
+    if (e->lds > pgg::max_dynamic_lds()) {
         eerr("the widest replica layout (%d LDS words per wave) does not fit %d waves per workgroup", max_words, wpg);
         ens_release(e);
         return PGG_E_INVAL;
@@ -548,14 +548,22 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     // workgroup's LDS (a chunk per launch, beside the segment launches) are
     // tried together: the resident branch changes which group split is best
     bool any_res = false;
-    for (uint32_t k = 0; k < n_reps; ++k) any_res = any_res || pgg::resident_fits((int)reps[k].L);
+    uint32_t max_fit = 0;  // largest side that could run resident
+    for (uint32_t k = 0; k < n_reps; ++k)
+        if (pgg::resident_fits((int)reps[k].L)) {
+            any_res = true;
+            max_fit = std::max(max_fit, reps[k].L);
+        }
     const uint32_t branch_counts[] = {1, 2, 4};
+    // (resident sides up to 512 are accepted but not searched: on the
+    // 256-replica workload the tuner's short probes favoured them while
+    // 400-sweep runs were 5 % slower than without resident replicas)
     const uint32_t res_sides[] = {0, 128, 256};
     uint32_t best_branches = branches, best_res = res_max_L;
     for (uint32_t bcount : branch_counts) {
         for (uint32_t rl : res_sides) {
             if (st != PGG_OK || (bcount == best_branches && rl == best_res) || bcount > n_reps) continue;
-            if (rl != 0 && !any_res) continue;
+            if (rl != 0 && (!any_res || (rl > 128 && max_fit <= rl / 2))) continue;  // same set as rl / 2
             branches = bcount;
             res_max_L = rl;
             double ms = 0.0;

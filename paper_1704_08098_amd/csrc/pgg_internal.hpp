@@ -70,14 +70,22 @@ hipError_t launch_pd_class(uint32_t* lat, int L, int stride, int k, uint32_t t, 
                            unsigned long long* delta, hipStream_t st);
 // Resident sweep (pgg_resident.hip): one workgroup of W waves (4, 8 or 16)
 // holds the lattice in LDS and runs n sweeps from sweep index t0; delta[q]
-// (kSweepWords each) receives sweep t0 + q.  L a multiple of 32, 64 <= L <= 256.
+// (kSweepWords each) receives sweep t0 + q.  L a multiple of 32, 64 <= L <= 512
+// (104 KB of LDS at L = 512).
 bool resident_fits(int L);
 bool resident_waves_valid(int W);
 int resident_auto_waves(int L);
 size_t resident_lds_bytes(int L, int W);
 hipError_t launch_resident(uint32_t* lat, int L, int stride, int W, uint32_t t0, int n, uint64_t seed,
                            const uint32_t* T, unsigned long long* delta, unsigned long long* drawn, hipStream_t st);
-constexpr size_t kMaxDynamicLds = 64 * 1024;
+constexpr int kResidentMaxL = 512;
+// LDS one workgroup may allocate on the current device
+// (hipDeviceAttributeMaxSharedMemoryPerBlock: 160 KB on gfx950; 64 KB if the
+// query fails), looked up once per device.
+size_t max_dynamic_lds();
+// Lets `kernel` be launched with `bytes` of dynamic LDS (the per-kernel
+// attribute, set only above 64 KB); false if the runtime refuses.
+bool allow_dynamic_lds(const void* kernel, size_t bytes);
 
 // Persistent strip kernel (pgg_strip.hip).  One task per workgroup: rows
 // [r0, r0 + H) of one lattice, the tasks owning the strips above (up) and

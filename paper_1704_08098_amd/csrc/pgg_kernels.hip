@@ -472,6 +472,8 @@ hipError_t launch_rowband_residue(uint32_t* lat, int L, int stride, int R, bool 
     const int nw = (L + 31) / 32;
     const int bands = (L / 4 + R - 1) / R;
     const size_t lds = rowband_lds_bytes(L, R, compact);
+    if (!allow_dynamic_lds(compact ? (const void*)k_rowband_bits<true> : (const void*)k_rowband_bits<false>, lds))
+        return hipErrorInvalidValue;
     if (compact)
         hipLaunchKernelGGL(k_rowband_bits<true>, dim3(bands), dim3(kRowbandThreads), lds, st, lat, L,
                            stride, nw, a, R, t, k0, k1, T, delta, drawn);

@@ -12,8 +12,10 @@
 // rows of one residue never read each other); a workgroup barrier, the halo
 // rows refreshed from the rows they copy, another barrier, the next residue.
 // After the last sweep the rows are written back.  For L a multiple of 32,
-// 64 <= L <= 256 (the lattice and the wave lists fit the LDS); one CU does the
+// 64 <= L <= 512 (the lattice and the wave lists fit the LDS); one CU does the
 // work, so other lattices on other streams can use the rest of the device.
+// Above L = 256 the lattice and lists need more than 64 KB (104 KB at L =
+// 512); gfx950 gives a workgroup up to 160 KB.
 // Few waves with many rows each beat many sparse ones: a wave's class pass
 // issues about the same instructions whether 8 or 64 of its lanes hold sites,
 // and the CU's VALU issue is what bounds the sweep.
@@ -120,7 +122,7 @@ k_ens_resident(const EnsRep* __restrict__ reps, const int* __restrict__ idx) {
 
 }  // namespace
 
-bool resident_fits(int L) { return L % 32 == 0 && L >= 64 && L <= 256; }
+bool resident_fits(int L) { return L % 32 == 0 && L >= 64 && L <= kResidentMaxL; }
 bool resident_waves_valid(int W) { return W == 4 || W == 8 || W == 16; }
 int resident_auto_waves(int L) { return L <= 96 ? 4 : 8; }  // 4 to 8 rows of a residue per wave
 
@@ -134,14 +136,19 @@ hipError_t launch_resident(uint32_t* lat, int L, int stride, int W, uint32_t t0,
                            const uint32_t* T, unsigned long long* delta, unsigned long long* drawn, hipStream_t st) {
     if (!resident_fits(L) || !resident_waves_valid(W) || n < 1 || stride < L / 32) return hipErrorInvalidValue;
     const size_t lds = resident_lds_bytes(L, W);
+    if (lds > max_dynamic_lds()) return hipErrorInvalidValue;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (W == 4)
+    if (W == 4) {
+        if (!allow_dynamic_lds((const void*)k_resident<4>, lds)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_resident<4>, dim3(1), dim3(256), lds, st, lat, L, stride, t0, n, k0, k1, T, delta, drawn);
-    else if (W == 8)
+    } else if (W == 8) {
+        if (!allow_dynamic_lds((const void*)k_resident<8>, lds)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_resident<8>, dim3(1), dim3(512), lds, st, lat, L, stride, t0, n, k0, k1, T, delta, drawn);
-    else
+    } else {
+        if (!allow_dynamic_lds((const void*)k_resident<16>, lds)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_resident<16>, dim3(1), dim3(1024), lds, st, lat, L, stride, t0, n, k0, k1, T, delta,
                            drawn);
+    }
     return hipGetLastError();
 }
 
@@ -149,12 +156,17 @@ hipError_t launch_ens_resident(const EnsRep* d_reps, const int* d_idx, int n, in
     if (n <= 0) return hipSuccess;
     if (!resident_waves_valid(W)) return hipErrorInvalidValue;
     const size_t lds = resident_lds_bytes(L_max, W);
-    if (W == 4)
+    if (lds > max_dynamic_lds()) return hipErrorInvalidValue;
+    if (W == 4) {
+        if (!allow_dynamic_lds((const void*)k_ens_resident<4>, lds)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_ens_resident<4>, dim3(n), dim3(256), lds, st, d_reps, d_idx);
-    else if (W == 8)
+    } else if (W == 8) {
+        if (!allow_dynamic_lds((const void*)k_ens_resident<8>, lds)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_ens_resident<8>, dim3(n), dim3(512), lds, st, d_reps, d_idx);
-    else
+    } else {
+        if (!allow_dynamic_lds((const void*)k_ens_resident<16>, lds)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_ens_resident<16>, dim3(n), dim3(1024), lds, st, d_reps, d_idx);
+    }
     return hipGetLastError();
 }
 

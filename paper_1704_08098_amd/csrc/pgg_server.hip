@@ -168,7 +168,7 @@ bool job_params_ok(const pgg_params* p, uint32_t max_L, const char** why) {
         pgg::EnsRep rp;
         std::memset(&rp, 0, sizeof(rp));
         pgg::ens_geometry(rp, (int)p->L, (int)p->tile);
-        if (pgg::ens_lds_bytes(pgg::ens_wave_words(rp)) > pgg::kMaxDynamicLds) { *why = "tile too wide for the workgroup's LDS"; return false; }
+        if (pgg::ens_lds_bytes(pgg::ens_wave_words(rp)) > pgg::max_dynamic_lds()) { *why = "tile too wide for the workgroup's LDS"; return false; }
     }
     if (p->group != 0) { *why = "jobs run with the server's workgroup shape (group must be 0)"; return false; }
     if (p->schedule != PGG_SCHEDULE_COLOUR16) { *why = "jobs run the 16-colour sweep"; return false; }

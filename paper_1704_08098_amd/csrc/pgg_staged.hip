@@ -207,6 +207,7 @@ hipError_t launch_staged_residue(uint32_t* lat, int L, int stride, int R, int a,
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const int nw = (L + 31) / 32;
     const int bands = (L / 4 + R - 1) / R;
+    if (!allow_dynamic_lds((const void*)k_rowband_staged, staged_lds_bytes(L, R))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rowband_staged, dim3(bands), dim3(kRowbandThreads), staged_lds_bytes(L, R), st,
                        lat, L, stride, nw, a, R, t, k0, k1, T, delta, drawn);
     return hipGetLastError();

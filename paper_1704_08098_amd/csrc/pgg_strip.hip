@@ -327,6 +327,7 @@ hipError_t launch_strip(const StripTask* d_tasks, int n_tasks, uint64_t* ring, u
                         uint64_t wait_ticks, int G, size_t lds, hipStream_t st) {
     void* args[] = {(void*)&d_tasks, (void*)&n_tasks, (void*)&ring, (void*)&abort_flag,
                     (void*)&wait_ticks, (void*)&G};
+    if (!allow_dynamic_lds((const void*)k_strip, lds)) return hipErrorInvalidValue;
     return hipLaunchCooperativeKernel((const void*)k_strip, dim3(n_tasks), dim3(kStripThreads), args,
                                       (unsigned int)lds, st);
 }
@@ -337,6 +338,7 @@ hipError_t strip_capacity(size_t lds, int* blocks_per_cu, int* cus) {
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
+    if (!allow_dynamic_lds((const void*)k_strip, lds)) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_strip,
                                                         kStripThreads, lds);
 }

@@ -73,11 +73,11 @@ def test_device_bytes(pgg):
                                 dict(L=512, kernel="segment_pair", group=4),
                                 dict(layout="int8", L=480, kernel="segment_pair"),
                                 dict(layout="int8", kernel="colour", group=2),
-                                dict(L=16384, kernel="segment", tile=8192, group=8),
+                                dict(L=32768, kernel="segment", tile=16384, group=8),
                                 dict(schedule=2), dict(L=100, schedule="tiled"), dict(L=92, schedule="tiled", layout="int8"),
                                 dict(L=96, schedule="tiled", kernel="segment"), dict(L=96, schedule="tiled", tile=32),
                                 dict(L=96, schedule="tiled", group=4),
-                                dict(L=32, kernel="resident"), dict(L=288, kernel="resident"),
+                                dict(L=32, kernel="resident"), dict(L=544, kernel="resident"),
                                 dict(L=100, kernel="resident"), dict(L=240, kernel="resident"),
                                 dict(L=128, kernel="resident", tile=32), dict(L=128, kernel="resident", group=2), dict(L=128, kernel="resident", group=32),
                                 dict(L=128, schedule="tiled", kernel="resident")])

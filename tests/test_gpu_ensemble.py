@@ -337,14 +337,15 @@ def test_one_shot_run_equals_the_handle_calls(pgg, oracle_lib):
 
 
 @pytest.mark.parametrize("res_L,res_waves,branches", [(128, 4, 0), (256, 8, 0), (256, 16, 2), (256, 0, 4),
-                                                      (64, 4, 2)])
+                                                      (64, 4, 2), (512, 4, 0), (512, 16, 2), (300, 8, 0)])
 def test_resident_replicas_do_not_change_results(pgg, oracle_lib, res_L, res_waves, branches):
     """Replicas of side a multiple of 32 up to resident_max_L swept whole in
     LDS (a chunk of sweeps per launch) beside the segment launches of the
     others: counts after every sweep, coop counts and lattices equal the
     plain ensemble's, and a resident and a segment replica equal the oracle
     (chunks of 8 with a short tail; sides that do not fit -- not a multiple
-    of 32, or too large -- stay on the segment path)."""
+    of 32, or too large -- stay on the segment path; L = 512 takes 104 KB of
+    LDS per workgroup)."""
     reps = [dict(L=L, r=r, seed=400 + k) for k, (L, r) in
             enumerate([(64, 3.8), (96, 3.9), (100, 4.0), (128, 3.75), (160, 4.2), (196, 3.85), (224, 3.7),
                        (256, 3.95), (512, 3.8), (68, 4.4)])]
@@ -366,7 +367,7 @@ def test_resident_replicas_do_not_change_results(pgg, oracle_lib, res_L, res_wav
 
 def test_resident_settings_refused_where_they_do_not_apply(pgg):
     one = [dict(L=128, r=3.8, seed=1)]
-    for bad in (dict(resident_max_L=32), dict(resident_max_L=300), dict(resident_max_L=128, resident_waves=3),
+    for bad in (dict(resident_max_L=32), dict(resident_max_L=600), dict(resident_max_L=128, resident_waves=3),
                 dict(resident_max_L=128, resident_waves=32)):
         with pytest.raises(pgg.PggError):
             pgg.Ensemble(one, **bad)

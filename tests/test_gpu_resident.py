@@ -47,7 +47,7 @@ def test_every_sweep_against_oracle(pgg, oracle_lib, layout, L, r, K, seed):
 
 
 @pytest.mark.parametrize("group", [4, 8, 16])
-@pytest.mark.parametrize("L", [64, 160, 256])
+@pytest.mark.parametrize("L", [64, 160, 256, 288, 512])
 def test_wave_counts(pgg, oracle_lib, L, group):
     """Every workgroup shape (4, 8 or 16 waves, so 1 to 16 rows of a residue
     per wave) gives the oracle's lattice and count after every sweep."""
