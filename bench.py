@@ -362,10 +362,7 @@ def serving_pass(pgg, n_jobs, stream, budget_mib=256, chunk=16, max_resident=256
         return rep
 
     calib_jobs = 4 * max_resident
-    calib = wl.serving_trace(calib_jobs, 1.0, master_seed=11)
-    for j in calib:
-        j["arrival"] = 0.0
-    cal = run(calib)
+    cal = server.capacity(pgg, calib_jobs, max_resident, chunk, budget_mib, master_seed=11, stream=stream)
     capacity = cal["site_updates_per_s_saturated"]
     probe = wl.serving_trace(n_jobs, 1.0)
     mean_work = sum(float(j["L"]) ** 2 * j["sweeps"] for j in probe) / n_jobs

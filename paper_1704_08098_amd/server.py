@@ -91,3 +91,45 @@ def serve(engine, jobs, clock=time.perf_counter, sleep=time.sleep, keep_results=
         report["results"] = results
         report["latencies"] = lat_s
     return report
+
+
+def capacity(pgg, n_jobs=1024, max_resident=256, chunk=16, budget_mib=256, master_seed=11, stream=None):
+    """The C server's saturated capacity: n_jobs jobs of the serving
+    distribution (workloads.serving_trace) submitted at once, at most
+    max_resident on the device; the report of serve() on that batch."""
+    from . import workloads as wl
+    jobs = wl.serving_trace(n_jobs, 1.0, master_seed=master_seed)
+    for j in jobs:
+        j["arrival"] = 0.0
+    engine = pgg.ServerEngine(budget_mib << 20, max_L=2048, max_resident=max_resident, chunk=chunk, stream=stream)
+    try:
+        rep = serve(engine, jobs)
+    finally:
+        engine.close()
+    rep.pop("engine", None)
+    return rep
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="the job server's saturated capacity on the serving distribution")
+    ap.add_argument("--jobs", type=int, default=1024)
+    ap.add_argument("--max-resident", type=int, default=256)
+    ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--budget-mib", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=11, help="master seed of the job trace")
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    from . import pgg
+    pgg.load()
+    print("server capacity: %d jobs, at most %d resident, chunk %d" % (args.jobs, args.max_resident, args.chunk),
+          file=sys.stderr, flush=True)
+    rep = capacity(pgg, args.jobs, args.max_resident, args.chunk, args.budget_mib, args.seed)
+    print(json.dumps(rep))
+
+
+if __name__ == "__main__":
+    main()
