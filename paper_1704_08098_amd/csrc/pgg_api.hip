@@ -266,7 +266,7 @@ bool params_valid(const pgg_params* p, const char** why) {
         }
         case PGG_KERNEL_SEGMENT: {
             if (p->L < 64) { *why = "the segment kernel needs L >= 64"; return false; }
-            if (tr != 0 && !pgg::segw_valid((int)p->L, (int)tr)) { *why = "segment tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)"; return false; }
+            if (tr != 0 && !pgg::segw_valid((int)p->L, (int)tr)) { *why = "segment tile must be a multiple of 32 and <= L - 32, or L (whole rows)"; return false; }
             const int wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
             if (!pgg::ens_wpg_valid(wpg)) { *why = "group must be 0, 2, 4 or 8"; return false; }
             if (segment_lds(p->L, tr ? (int)tr : choose_segw(p->L, wpg), wpg) > pgg::max_dynamic_lds()) {

@@ -287,7 +287,10 @@ hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st)
 }
 
 int auto_segw(int L) {
-    if (L % 32 == 0 && L <= 1024) return L;  // whole rows
+    // whole rows: several per wave for L a multiple of 32, else one periodic
+    // row per wave (a row split in two would list half as many sites per
+    // class for the same per-class cost)
+    if (L <= 1024) return L;
     // About 1376 columns: at the drawn fraction of a lattice near r_c (about
     // 15 % of the sites) a class then lists about 50 sites, most of one
     // 64-lane pass; the row is split into equal segments of that order.  A
@@ -303,7 +306,7 @@ int auto_segw(int L) {
 }
 
 bool segw_valid(int L, int segw) {
-    if (segw == L) return L % 32 == 0;
+    if (segw == L) return true;  // whole rows
     return segw > 0 && segw % 32 == 0 && segw + 32 <= L;
 }
 
@@ -313,11 +316,11 @@ void ens_geometry(EnsRep& rp, int L, int segw) {
     rp.stride = 2 * ((L + 63) / 64);
     rp.nw = (L + 31) / 32;
     rp.segw = segw;
-    if (segw == L) {
+    if (segw == L && L % 32 == 0) {
         rp.nseg = 1;
         const int R = L >= 1024 ? 1 : 1024 / L;
         rp.rpw = R < L / 4 ? R : L / 4;
-    } else {
+    } else {  // segments, or one periodic row per wave (segw == L)
         rp.nseg = (L + segw - 1) / segw;
         rp.rpw = 0;
     }

@@ -186,7 +186,7 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
             return PGG_E_INVAL;
         }
         const uint32_t w = tiles ? tiles[k] : 0;
-        if (w != 0 && !pgg::segw_valid((int)p.L, (int)w)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32, or L (whole rows, L a multiple of 32)", k); return PGG_E_INVAL; }
+        if (w != 0 && !pgg::segw_valid((int)p.L, (int)w)) { eerr("replica %u: tile must be a multiple of 32 and <= L - 32, or L (whole rows)", k); return PGG_E_INVAL; }
     }
     return PGG_OK;
 }
@@ -519,7 +519,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         std::vector<uint32_t> cand;
         for (uint32_t w = 64; w < cap; w *= 2) cand.push_back(w);
         if (cap >= 32) cand.push_back(cap);
-        if (L % 32 == 0) cand.push_back(L);  // whole rows
+        cand.push_back(L);  // whole rows
         pgg::EnsRep geo;
         std::memset(&geo, 0, sizeof(geo));
         pgg::ens_geometry(geo, (int)L, 0);

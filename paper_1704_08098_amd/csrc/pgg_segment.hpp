@@ -13,8 +13,10 @@
 // [s-3, e+3) reads classes 0-1 within 3 more, and so on, so every site the
 // wave writes back -- the columns [s, e) -- is exact.  Sites in the margins
 // are recomputed (identically) by the neighbouring segment's wave and
-// discarded here.  A segment is at most L - 32 columns, so a margin site and
-// its periodic image never both lie in the columns a class updates.
+// discarded here.  A segment is at most L - 32 columns, or the whole row:
+// then the margins hold the periodic images of owned sites, and an image is
+// updated exactly as its original (same site index, so the same random
+// numbers, and the same neighbourhood), so the owned columns stay exact.
 //
 // Per class the wave computes, bit-parallel over 32-bit words, the sites
 // with a differing neighbour (the others cannot change and draw nothing),
@@ -60,6 +62,21 @@ __device__ __forceinline__ uint32_t global_window(const uint32_t* __restrict__ r
     return out;
 }
 
+// The same 32 sites for L >= 32 and -L <= c < 2L, without loops: two loads
+// and a funnel shift, and for a window that crosses column L - 1 the first
+// columns of the row shifted in after it.
+__device__ __forceinline__ uint32_t global_window_wide(const uint32_t* __restrict__ row, int L, int nw, int c) {
+    c += (c < 0) ? L : 0;
+    c -= (c >= L) ? L : 0;
+    const int wi = c >> 5, sh = c & 31;
+    const uint32_t lo = row[wi];
+    const uint32_t hi = (wi + 1 < nw) ? row[wi + 1] : 0u;
+    uint32_t v = funnel(hi, lo, sh);  // columns c, c + 1, ... of the stored words
+    const int take = L - c;           // columns before the wrap (>= 1)
+    if (take < 32) v = (v & ((1u << take) - 1u)) | (row[0] << take);
+    return v;
+}
+
 // Sigma of the site in bit 16 of the middle row, without its 5 s term: the
 // rows a2, a1, b, c1, c2 are i-2 .. i+2.  Sigma (the sum of the cooperator
 // counts of the five groups containing the site) counts the site itself 5
@@ -96,7 +113,7 @@ __device__ __forceinline__ void seg_load_table(uint32_t* __restrict__ sT, const 
 }
 
 // Window words per row and list capacity per class for a segment width.
-__host__ __device__ constexpr int seg_window_words(int segw) { return segw / 32 + 4; }
+__host__ __device__ constexpr int seg_window_words(int segw) { return (segw + 31) / 32 + 4; }
 // (class-b sites of a segment plus margins of up to 21 columns each side)
 __host__ __device__ constexpr int seg_list_cap(int segw) { return segw / 4 + 16; }
 __host__ __device__ constexpr int seg_wave_words(int segw) { return 7 * seg_window_words(segw) + seg_list_cap(segw); }
@@ -191,13 +208,24 @@ __device__ __forceinline__ void segment_fill(const uint32_t* __restrict__ cur, c
         }
         return;
     }
-    for (int q = lane; q < 7 * WB; q += 64) {
-        const int o = q / WB, w = q - (q / WB) * WB;
-        int gi = g.i - 3 + o;
-        gi += (gi < 0) ? L : 0;
-        gi -= (gi >= L) ? L : 0;
-        const uint32_t* src = ((gi & 3) < a) ? next : cur;
-        win[q] = global_window(src + (size_t)gi * stride, L, nw, g.c0 + 32 * w);
+    // L not a multiple of 32: each window word is columns c .. c + 31 of
+    // its row, modulo L (c0 >= -64 and the window ends before column 2L)
+    for (int wb = 0; wb < WB; wb += 64) {
+        const int w = wb + lane;
+        if (w < WB) {
+            const int c = g.c0 + 32 * w;
+            uint32_t v[7];
+#pragma unroll
+            for (int o = 0; o < 7; ++o) {
+                int gi = g.i - 3 + o;
+                gi += (gi < 0) ? L : 0;
+                gi -= (gi >= L) ? L : 0;
+                const uint32_t* src = ((gi & 3) < a) ? next : cur;
+                v[o] = global_window_wide(src + (size_t)gi * stride, L, nw, c);
+            }
+#pragma unroll
+            for (int o = 0; o < 7; ++o) win[o * WB + w] = v[o];
+        }
     }
 }
 

@@ -163,7 +163,7 @@ bool job_params_ok(const pgg_params* p, uint32_t max_L, const char** why) {
     if (!(p->p0 >= 0.0 && p->p0 <= 1.0)) { *why = "p0 must lie in [0, 1]"; return false; }
     if (p->layout != PGG_LAYOUT_BITS) { *why = "jobs use the bits layout"; return false; }
     if (p->kernel != PGG_KERNEL_AUTO && p->kernel != PGG_KERNEL_SEGMENT) { *why = "jobs use the segment kernel"; return false; }
-    if (p->tile != 0 && !pgg::segw_valid((int)p->L, (int)p->tile)) { *why = "tile must be a multiple of 32 and <= L - 32, or L for whole rows (L a multiple of 32)"; return false; }
+    if (p->tile != 0 && !pgg::segw_valid((int)p->L, (int)p->tile)) { *why = "tile must be a multiple of 32 and <= L - 32, or L for whole rows"; return false; }
     {
         pgg::EnsRep rp;
         std::memset(&rp, 0, sizeof(rp));

@@ -67,7 +67,7 @@ def test_device_bytes(pgg):
                                 dict(kernel="segment", group=3), dict(kernel="segment", group=16),
                                 dict(kernel="rowband", group=4), dict(layout="int8", L=60, group=4),
                                 dict(L=32768, kernel="segment", tile=32736),
-                                dict(L=100, kernel="segment", tile=100),
+                                dict(L=100, kernel="segment", tile=50),
                                 dict(L=480, kernel="segment_pair"), dict(L=516, kernel="segment_pair"),
                                 dict(L=512, kernel="segment_pair", tile=480),
                                 dict(L=512, kernel="segment_pair", group=4),

@@ -127,7 +127,7 @@ def test_autotune_choices_are_valid_and_do_not_change_results(pgg, oracle_lib):
     by_L = {}
     for rp, w in zip(reps, tiles):
         # segments of a multiple of 32 columns up to L - 32, or whole rows (L)
-        assert w % 32 == 0 and (32 <= w <= rp["L"] - 32 or w == rp["L"])
+        assert (w % 32 == 0 and 32 <= w <= rp["L"] - 32) or w == rp["L"]
         by_L.setdefault(rp["L"], set()).add(int(w))
     assert all(len(ws) == 1 for ws in by_L.values())
     n = 21

@@ -363,9 +363,13 @@ def test_strip_abort_path_reports_and_recovers(pgg, oracle_lib):
 
 
 @pytest.mark.parametrize("L,segw", [(64, 32), (100, 32), (100, 64), (132, 96), (196, 64), (260, 224),
-                                    (512, 128), (512, 480), (1024, 992)])
+                                    (512, 128), (512, 480), (1024, 992),
+                                    (68, 68), (100, 100), (196, 196), (260, 260), (500, 500), (1020, 1020),
+                                    (1500, 1500), (1500, 768), (2044, 2044)])
 def test_segment_widths(pgg, oracle_lib, L, segw):
-    """Segment widths from 32 columns to L - 32, including a short last segment."""
+    """Segment widths from 32 columns to L - 32, including a short last
+    segment, and whole periodic rows for L not a multiple of 32 (one row per
+    wave, its margins the periodic images of its own sites)."""
     r, seed, n = 3.9, 40 + L, 12
     ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
     say("segment", L, segw)
