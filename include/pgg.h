@@ -213,8 +213,9 @@ typedef struct {
     uint32_t tile;   /* work split; 0 = chosen by the library.  STRIP: rows
                         per strip (>= 4); ROWBAND*: rows per band; SEGMENT:
                         columns per segment (a multiple of 32, <= L - 32),
-                        or L itself when L is a multiple of 32: whole rows
-                        per wave (min(L/4, max(1, 1024/L)) of them).  A value
+                        or L itself: whole rows per wave (min(L/4, max(1,
+                        1024/L)) of them when L is a multiple of 32, else one
+                        periodic row).  A value
                         the kernel cannot use is PGG_E_INVAL.  Results never
                         depend on it.                                         */
     uint32_t group;  /* SEGMENT: segment waves per workgroup, 2, 4 or 8
@@ -437,7 +438,7 @@ void pgg_ensemble_destroy(pgg_ensemble* e);
  * each): first the width of each distinct L in turn (the six with the
  * most work, sum of L^2, in that order; others automatic) over the doublings
  * 64, 128, ... below L - 32, L - 32 rounded down to a multiple of 32, and
- * whole rows (L, when L is a multiple of 32), the other sizes held at their
+ * whole rows (L), the other sizes held at their
  * best so far, then the waves per workgroup over 2, 4, 8, then the
  * concurrent groups over 1, 2, 4 together with resident sweeps off, up to
  * L = 128 or 256 (when some replica fits), then their 4, 8 or 16
