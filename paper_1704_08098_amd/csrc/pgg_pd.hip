@@ -70,16 +70,29 @@ k_pd_class(uint32_t* __restrict__ lat, int L, int stride, int nw, int k, uint32_
         const int h = (i >> 1) & 1;
         const int cls = (qc + 2 * h) & 3;  // column residue of the class in this row
         const int c0 = 32 * w;
-        // five 64-bit windows, bit b = column c0 - 16 + b (periodic)
+        // five 64-bit windows, bit b = column c0 - 16 + b (periodic): for L a
+        // multiple of 32 the words w - 1, w, w + 1 of the row (modulo nw),
+        // else periodic windows built column by column
         uint64_t win[5];
+        const int wm = w == 0 ? nw - 1 : w - 1, wp = w + 1 == nw ? 0 : w + 1;
 #pragma unroll
         for (int o = 0; o < 5; ++o) {
             int gi = i - 2 + o;
             gi += (gi < 0) ? L : 0;
             gi -= (gi >= L) ? L : 0;
             const uint32_t* row = lat + (size_t)gi * stride;
-            const uint32_t lo = seg::global_window(row, L, nw, c0 - 16);
-            const uint32_t hi = seg::global_window(row, L, nw, c0 + 16);
+            uint32_t lo, hi;
+            if ((L & 31) == 0) {
+                const uint32_t a = row[wm], bw = row[w], c = row[wp];
+                lo = funnel(bw, a, 16);
+                hi = funnel(c, bw, 16);
+            } else if (L >= 32) {
+                lo = seg::global_window_wide(row, L, nw, c0 - 16);
+                hi = seg::global_window_wide(row, L, nw, c0 + 16);
+            } else {
+                lo = seg::global_window(row, L, nw, c0 - 16);
+                hi = seg::global_window(row, L, nw, c0 + 16);
+            }
             win[o] = ((uint64_t)hi << 32) | lo;
         }
         // columns c0 .. c0 + 31 (bits at columns >= L wrap round in the
