@@ -362,7 +362,8 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
  *              workgroup serves one replica and shares one copy of its
  *              threshold table; each replica's waves are padded to whole
  *              workgroups.
- *   branches   concurrent replica groups, 0..16 (0 or 1: one): the replicas
+ *   branches   concurrent replica groups, 0..16 (0: two for the 16-colour
+ *              schedule, one for the tiled one; 1: one): the replicas
  *              swept by segments are cut into this many contiguous ranges
  *              of about equal work (sum of L^2), each range's chunk is its
  *              own chain of launches, and the chains run side by side as

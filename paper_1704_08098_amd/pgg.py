@@ -401,7 +401,8 @@ class Ensemble:
     replicas: sequence of dicts with L, r and optionally K, p0, seed.
     tiles: optional per-replica segment widths (0 = automatic).
     waves_per_group: segment waves per workgroup, 2, 4 or 8 (0 = 4).
-    branches: concurrent replica groups (parallel graph branches), 0..16.
+    branches: concurrent replica groups (parallel graph branches), 0..16 (0 = two
+              for the 16-colour schedule, one for the tiled one).
     resident_max_L: 0, or the largest side swept by the resident kernel.
     resident_waves: waves per resident workgroup, 4, 8 or 16 (0 = 8).
     """
