@@ -355,7 +355,11 @@ typedef struct pgg_ensemble pgg_ensemble; /* opaque; not thread-safe */
 
 /* Tuning of a batched launch: what only changes the speed, never a result.
  *   tiles      NULL (automatic) or host array of n_reps work splits as
- *              pgg_params.tile of the segment kernel.
+ *              pgg_params.tile of the segment kernel (0 = automatic: whole
+ *              rows up to L = 8192, segments of about 1376 columns above;
+ *              a single lattice's automatic split keeps segments above
+ *              L = 1024 and for L not a multiple of 32, where it needs the
+ *              waves).
  *   chunk      sweeps per graph replay, 1..1024 (device counters hold
  *              chunk x n_reps x 4 KiB).
  *   waves_per_group  segment waves per workgroup: 2, 4 or 8 (0 = 4).  A

@@ -286,11 +286,7 @@ hipError_t launch_ens_set_t0(EnsRep* d_reps, int n, uint32_t t0, hipStream_t st)
     return hipGetLastError();
 }
 
-int auto_segw(int L) {
-    // whole rows: several per wave for L a multiple of 32, else one periodic
-    // row per wave (a row split in two would list half as many sites per
-    // class for the same per-class cost)
-    if (L <= 1024) return L;
+int split_segw(int L) {
     // About 1376 columns: at the drawn fraction of a lattice near r_c (about
     // 15 % of the sites) a class then lists about 50 sites, most of one
     // 64-lane pass; the row is split into equal segments of that order.  A
@@ -303,6 +299,19 @@ int auto_segw(int L) {
     if (w > cap) w = cap;
     if (w < 32) w = 32;
     return w;
+}
+
+int auto_segw(int L) {
+    // Whole rows: several per wave for L a multiple of 32 below 1024, else
+    // one row per wave (periodic when L is not a multiple of 32).  A launch
+    // over many lattices has waves to spare, so fewer, fuller waves win: a
+    // row split into segments lists fewer sites per class for the same
+    // per-class cost and recomputes its margins (ensembles of 64 replicas:
+    // 2.0-2.6e11 -> 3.7-3.8e11 site updates/s at L = 500 ... 1020, 3.3-3.6e11
+    // -> 4.9-5.4e11 at L = 1276 ... 1500, 1.6 x at 9 x L = 4096).  Up to L =
+    // 8192 (62 KB of LDS for 4 waves per workgroup).
+    if (L <= kEnsWholeRowMaxL) return L;
+    return split_segw(L);
 }
 
 bool segw_valid(int L, int segw) {

@@ -97,9 +97,10 @@ void ens_release(pgg_ensemble* e) {
     if (e->d_delta) (void)hipFree(e->d_delta);
     if (e->d_counts) (void)hipFree(e->d_counts);
     if (e->d_nc) (void)hipFree(e->d_nc);
+    // events before the streams they were recorded on
+    for (hipEvent_t ev : e->branch_events) (void)hipEventDestroy(ev);
     if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
     for (hipStream_t bs : e->branch_streams) (void)hipStreamDestroy(bs);
-    for (hipEvent_t ev : e->branch_events) (void)hipEventDestroy(ev);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
@@ -464,9 +465,23 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     uint32_t chunk = 32, wpg = (uint32_t)pgg::kWavesPerGroup, branches = 1, res_max_L = 0, res_waves = 8;
     std::vector<uint64_t> nc(n_reps);
     std::vector<uint32_t> tiles(n_reps);
+    // Every trial ensemble runs on one stream that outlives them all (the
+    // caller's, or one made here), so the timing events are only ever
+    // recorded on a live stream -- never re-recorded after the stream of an
+    // earlier record has been destroyed.
+    hipStream_t tune_stream = (hipStream_t)hip_stream;
+    bool own_tune_stream = false;
+    if (!tune_stream) {
+        if (hipStreamCreateWithFlags(&tune_stream, hipStreamNonBlocking) != hipSuccess) {
+            eerr("stream creation failed");
+            return PGG_E_DEVICE;
+        }
+        own_tune_stream = true;
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
         if (ev0) (void)hipEventDestroy(ev0);
+        if (own_tune_stream) (void)hipStreamDestroy(tune_stream);
         eerr("event creation failed");
         return PGG_E_DEVICE;
     }
@@ -481,7 +496,7 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
         for (uint32_t k = 0; k < n_reps; ++k) tiles[k] = width[reps[k].L];
         pgg_ensemble* e = nullptr;
         const pgg_ensemble_tune tn = {tiles.data(), chunk, wpg, branches, res_max_L, res_waves};
-        pgg_status st = pgg_ensemble_create(reps, n_reps, &tn, hip_stream, &e);
+        pgg_status st = pgg_ensemble_create(reps, n_reps, &tn, tune_stream, &e);
         if (st != PGG_OK) return st;
         st = pgg_ensemble_sweep(e, n_probe, nullptr);
         double best = 1e300;
@@ -598,6 +613,10 @@ pgg_status pgg_ensemble_autotune(const pgg_params* reps, uint32_t n_reps, uint32
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
+    if (own_tune_stream) {
+        (void)hipStreamSynchronize(tune_stream);
+        (void)hipStreamDestroy(tune_stream);
+    }
     if (st != PGG_OK) return st;
     for (uint32_t k = 0; k < n_reps; ++k) {
         uint32_t w = width[reps[k].L];

@@ -143,7 +143,12 @@ hipError_t launch_ens_resident(const EnsRep* d_reps, const int* d_idx, int n, in
 // Automatic work split for side L: L itself (whole rows per wave) when L is
 // a multiple of 32 and at most 1024, else a segment width (a multiple of 32,
 // <= L - 32).
+// Automatic segment widths: for launches over many lattices (ensembles,
+// server) whole rows up to kEnsWholeRowMaxL; split_segw: rows cut into
+// segments of about 1376 columns (a single lattice, which needs the waves).
+constexpr int kEnsWholeRowMaxL = 8192;
 int auto_segw(int L);
+int split_segw(int L);
 // Whether a width is usable at side L: a multiple of 32 up to L - 32
 // (segments), or L itself when L is a multiple of 32 (whole rows).
 bool segw_valid(int L, int segw);
