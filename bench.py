@@ -18,7 +18,7 @@ Prints one JSON line:
               numbers (no skipping of no-op updates)
   late        the same lattice later in its decay (sweeps 10^4 .. 10^4+K-1)
   batched     256 replicas of uneven L, r, seed in one graph-replayed ensemble
-              (autotuned) vs the same replicas one lattice at a time
+              (the tuner's settings) vs the same replicas one lattice at a time
   serving     a Poisson trace of simulation jobs through the job server:
               p50/p99 latency and aggregate site updates/s
   cpu_baseline  the oracle, single-threaded, on a bounded sample
@@ -181,14 +181,23 @@ def kernel_pass(pgg, torch, L, r, seed, kernel, layout, warmup, steps, stream, t
     return launches, ms, drawn, (span_us / span_n if span_n else None)
 
 
+# The batched pass's settings when it is not autotuned: what
+# pgg_ensemble_autotune chose for this workload (whole rows for every size,
+# chunk 32, 4 waves per workgroup, two concurrent groups, the L <= 256
+# replicas resident on 4 waves).
+ENSEMBLE_TUNE = dict(chunk=32, waves_per_group=4, branches=2, resident_max_L=256, resident_waves=4)
+
+
 def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     """Batched ensemble (all replicas, one graph replay per chunk) vs the same
-    replicas run one lattice at a time (a sample of each size, scaled).  With
-    autotune, the segment width per size and the chunk come from
+    replicas run one lattice at a time (a sample of each size, scaled).  The
+    settings are ENSEMBLE_TUNE, or with autotune (and chunk 0) those of
     pgg_ensemble_autotune (untimed, before the timed run)."""
     reps = wl.ensemble_replicas(sweeps=sweeps)
     total = float(sum(rp["L"] ** 2 for rp in reps)) * sweeps
-    tune, tuned = dict(chunk=chunk), None
+    tune = dict(ENSEMBLE_TUNE, chunk=chunk) if chunk else dict(ENSEMBLE_TUNE)
+    chunk = tune["chunk"]
+    tuned = None
     if autotune:
         t0 = time.perf_counter()
         tune, ms = pgg.ensemble_autotune(reps, probe_sweeps=8, stream=stream)
@@ -238,7 +247,8 @@ def ensemble_pass(pgg, torch, sweeps, chunk, plain_per_size, stream, autotune):
     return {"metric": "replica-site updates/s", "value": total / t_batched, "plain_value": total / t_plain,
             "ratio_vs_plain": t_plain / t_batched if identical else None,
             "identical_to_plain": identical, "plain_checked": checked, "plain_mismatched": mismatched, "replicas": len(reps), "sweeps": sweeps,
-            "sizes": sorted(by_size), "chunk": chunk, "autotuned": tuned, "batched_s": t_batched, "plain_s_estimated": t_plain,
+            "sizes": sorted(by_size), "chunk": chunk, "settings": {k: tune[k] for k in pgg.TUNE_KEYS},
+            "autotuned": tuned, "batched_s": t_batched, "plain_s_estimated": t_plain,
             "plain": "each replica alone (pgg_init/pgg_sweep, automatic kernel), %d per size timed, "
                      "scaled to the %d replicas of each size; each sampled replica's final count and lattice "
                      "compared with its batched run" % (plain_per_size, len(reps) // len(by_size)),
@@ -489,7 +499,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ensemble-sweeps", type=int, default=5000, help="0 skips the ensemble pass")
-    ap.add_argument("--ensemble-chunk", type=int, default=50)
+    ap.add_argument("--ensemble-chunk", type=int, default=0, help="sweeps per graph replay of the batched pass "
+                    "(0 = that of ENSEMBLE_TUNE)")
     ap.add_argument("--plain-per-size", type=int, default=4)
     ap.add_argument("--late-start", type=int, default=10_000, help="first sweep of the late window (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving pass (0 skips it)")
@@ -503,8 +514,8 @@ def main():
                     help="skip the nine L = 4096 decay lattices run as one ensemble")
     ap.add_argument("--scan-sweeps", type=int, default=10_000,
                     help="sweeps of the L = 1024 r scan run as one ensemble (0 skips it)")
-    ap.add_argument("--no-autotune", action="store_true", help="ensemble pass with automatic widths and "
-                    "--ensemble-chunk instead of pgg_ensemble_autotune")
+    ap.add_argument("--autotune", action="store_true", help="ensemble pass with the settings of "
+                    "pgg_ensemble_autotune instead of ENSEMBLE_TUNE")
     ap.add_argument("--source-hash", action="store_true", help="print the segment kernel's source hash and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
@@ -599,7 +610,7 @@ def main():
     if args.ensemble_sweeps > 0:
         log("ensemble pass: %d sweeps" % args.ensemble_sweeps)
         batched = ensemble_pass(pgg, torch, args.ensemble_sweeps, args.ensemble_chunk, args.plain_per_size, stream,
-                                not args.no_autotune)
+                                args.autotune)
 
     paper_workload = None
     if args.paper_workload:

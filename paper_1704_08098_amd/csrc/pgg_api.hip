@@ -159,9 +159,10 @@ size_t segment_lds(uint32_t L, int segw, int wpg) {
 // Work split of the segment kernel: the automatic one, with segments
 // narrowed until the workgroup's LDS fits.
 int choose_segw(uint32_t L, int wpg) {
-    // a single lattice needs its waves: whole rows (several per wave) only
-    // for L a multiple of 32 up to 1024, else segments of about 1376 columns
-    int w = (L % 32 == 0 && L <= 1024) ? (int)L : pgg::split_segw((int)L);
+    // a single lattice needs its waves: whole rows (several per wave for L a
+    // multiple of 32, one periodic row otherwise) only up to L = 1024, else
+    // segments of about 1376 columns
+    int w = L <= 1024 ? (int)L : pgg::split_segw((int)L);
     if (w == (int)L && segment_lds(L, w, wpg) <= pgg::max_dynamic_lds()) return w;
     if (w == (int)L) w = ((int)L - 32) & ~31;
     while (w > 32 && segment_lds(L, w, wpg) > pgg::max_dynamic_lds()) w -= 32;
