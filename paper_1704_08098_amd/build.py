@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpgg.so")
-SOURCES = ["pgg_kernels.hip", "pgg_staged.hip", "pgg_strip.hip", "pgg_ens_kernels.hip", "pgg_ensemble.hip", "pgg_server.hip", "pgg_tiled.hip", "pgg_pd.hip",
+SOURCES = ["pgg_kernels.hip", "pgg_staged.hip", "pgg_strip.hip", "pgg_ens_kernels.hip", "pgg_geometry.hip", "pgg_ensemble.hip", "pgg_server.hip", "pgg_tiled.hip", "pgg_pd.hip",
            "pgg_resident.hip", "pgg_noalloc.hip", "pgg_api.hip"]
 ARCH = "gfx950"
 
