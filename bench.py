@@ -584,7 +584,10 @@ def main():
                    "rowband_staged": "k_rowband_staged", "rowband_compact": "k_rowband_bits<true>",
                    "rowband": "k_rowband_bits<false>", "colour": "k_colour_int8", "tiled": "k_tiled_part",
                    "resident": "k_resident"}[args.kernel]
-    traffic = measured_traffic(args.kernel, L, args.tile, args.group)
+    # the work split the sweep actually ran (the library's choice when
+    # --tile is 0): the committed counter summaries are matched on it
+    _, split = pgg.pgg_plan(pgg.make_params(L, r, 0.5, 0.5, seed, layout, args.kernel, args.tile, args.group))
+    traffic = measured_traffic(args.kernel, L, split, args.group)
     roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -599,7 +602,7 @@ def main():
                 "kernel_span_us": span_us,
                 "drawn_fraction": drawn / updates,
                 "frac_int8_equivalent": achieved_gbs * 2.0 / hbm_bytes / HBM_PEAK_GBS,
-                "valu": measured_valu(args.kernel, L, args.tile, args.group, avg_ms * 1e3),
+                "valu": measured_valu(args.kernel, L, split, args.group, avg_ms * 1e3),
                 "note": "the state is read and written once per sweep (2 bits per site update on the bit-packed "
                         "lattice); the path is bound by integer VALU issue (one Philox4x32-10 per drawn update), "
                         "not by HBM -- 'valu' gives the counter-measured share of the VALU lanes"}
@@ -663,7 +666,8 @@ def main():
                                "(seed %d), sweeps %d..%d timed" % (L, L, r, seed, args.warmup,
                                                                  args.warmup + args.steps - 1),
                    "L": L, "r": r, "K": wl.K_PAPER, "p0": 0.5, "seed": seed, "layout": layout,
-                   "kernel": args.kernel, "tile": args.tile, "group": args.group, "parallelism": "single GPU"},
+                   "kernel": args.kernel, "tile": args.tile, "work_split": split, "group": args.group,
+                   "parallelism": "single GPU"},
         "roofline": roofline, "windows": windows, "dense": dense, "late": late, "batched": batched, "serving": serving,
         "scan": scan, "decay_batch": decay_batch, "paper_workload": paper_workload, "pairwise": pairwise,
         "cpu_baseline": cpu,

@@ -231,6 +231,16 @@ typedef struct pgg_sim pgg_sim; /* opaque handle */
  * a caller-supplied dev_buf must have).  0 if the parameters are invalid. */
 size_t pgg_device_bytes(const pgg_params* p);
 
+/* The plan pgg_init would take for p on the current device, without
+ * allocating or launching: *kernel the pgg_kernel it runs (AUTO resolved;
+ * PGG_KERNEL_AUTO for the tiled schedule and the pairwise game, which have a
+ * kernel each) and *tile its work split -- segment width for SEGMENT and
+ * SEGMENT_PAIR, rows per band for the ROWBAND kernels, waves per workgroup
+ * for RESIDENT, the requested strip height for STRIP (0: chosen at
+ * pgg_init from the device's occupancy), 0 for the others.  PGG_E_INVAL
+ * for parameters pgg_init refuses on validation. */
+pgg_status pgg_plan(const pgg_params* p, uint32_t* kernel, uint32_t* tile);
+
 /* Create a simulation and draw its initial state (Sec. III: every player C
  * with probability p0, D otherwise), t = 0.
  *   p          host; copied, the caller keeps ownership.

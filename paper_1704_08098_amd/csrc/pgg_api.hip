@@ -169,10 +169,14 @@ int choose_segw(uint32_t L, int wpg) {
     return w;
 }
 
-// Paired kernel: segments of about 1024 columns (at L = 4096: 128 bands x 4
-// segments = 512 workgroups, 2 per CU, all resident at once), at most L - 64.
+// Paired kernel: segments of about 2048 columns (at L = 4096: 128 bands x 2
+// segments = 256 workgroups, one per CU), at most L - 64.  Measured at L =
+// 4096 over sweeps 5..24: 39.4 us per sweep against 43.2 with 1024 columns
+// (512 workgroups, two per CU) and 44.0 with 1536 -- a wave's class lists
+// twice the sites for about the same per-class cost; at t = 10^4 the two
+// are within 2 %.
 int choose_pair_segw(uint32_t L) {
-    const int nseg = ((int)L + 512) / 1024 > 0 ? ((int)L + 512) / 1024 : 1;
+    const int nseg = ((int)L + 1024) / 2048 > 0 ? ((int)L + 1024) / 2048 : 1;
     int w = ((int)L / nseg + 31) & ~31;
     const int cap = ((int)L - 64) & ~31;
     if (w > cap) w = cap;
@@ -212,6 +216,17 @@ void auto_segment_plan(uint32_t L, int device, bool* pair, int* segw) {
 }  // namespace pgg
 
 namespace {
+
+// The kernel a handle runs (an internal id for the tiled schedule and the
+// pairwise game), on `device`.
+int choose_kernel(const pgg_params* p, int device) {
+    if (p->game == PGG_GAME_PAIRWISE_PD) return kKernelPd;
+    if (p->schedule == PGG_SCHEDULE_TILED) return kKernelTiled;
+    if (p->kernel != PGG_KERNEL_AUTO) return (int)p->kernel;
+    if (p->L < 64) return p->layout == PGG_LAYOUT_INT8 ? PGG_KERNEL_COLOUR : PGG_KERNEL_ROWBAND_COMPACT;
+    if (p->L <= kResidentAutoMaxL && pgg::resident_fits((int)p->L) && p->group == 0) return PGG_KERNEL_RESIDENT;
+    return pair_fits(p, device) ? PGG_KERNEL_SEGMENT_PAIR : PGG_KERNEL_SEGMENT;
+}
 
 bool strip_fits(uint32_t L, uint32_t H) {
     return pgg::strip_lds_bytes((int)L, (int)H, 1) <= pgg::max_dynamic_lds();
@@ -639,6 +654,30 @@ size_t pgg_device_bytes(const pgg_params* p) {
     return lattice_bytes(p);
 }
 
+pgg_status pgg_plan(const pgg_params* p, uint32_t* kernel, uint32_t* tile) {
+    if (!kernel || !tile) { set_err("NULL argument"); return PGG_E_INVAL; }
+    const char* why = nullptr;
+    if (!params_valid(p, &why)) { set_err("invalid parameters: %s", why); return PGG_E_INVAL; }
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) { set_err("no HIP device"); return PGG_E_DEVICE; }
+    const int k = choose_kernel(p, device);
+    const int wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
+    uint32_t w = 0;
+    switch (k) {
+        case PGG_KERNEL_SEGMENT: w = p->tile ? p->tile : (uint32_t)choose_segw(p->L, wpg); break;
+        case PGG_KERNEL_SEGMENT_PAIR: w = p->tile ? p->tile : (uint32_t)choose_pair_segw(p->L); break;
+        case PGG_KERNEL_ROWBAND:
+        case PGG_KERNEL_ROWBAND_COMPACT:
+        case PGG_KERNEL_ROWBAND_STAGED: w = p->tile ? p->tile : (uint32_t)choose_R(p->L); break;
+        case PGG_KERNEL_RESIDENT: w = p->group ? p->group : (uint32_t)pgg::resident_auto_waves((int)p->L); break;
+        case PGG_KERNEL_STRIP: w = p->tile; break;
+        default: w = 0;
+    }
+    *kernel = (k == kKernelPd || k == kKernelTiled) ? (uint32_t)PGG_KERNEL_AUTO : (uint32_t)k;
+    *tile = w;
+    return PGG_OK;
+}
+
 pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* hip_stream,
                     pgg_sim** out) {
     g_err[0] = 0;
@@ -665,18 +704,7 @@ pgg_status pgg_init(const pgg_params* p, void* dev_buf, size_t dev_bytes, void* 
     }
     s->stride = bits_stride(p->L);
     s->R = p->tile ? (int)p->tile : choose_R(p->L);
-    if (p->game == PGG_GAME_PAIRWISE_PD)
-        s->kernel = kKernelPd;
-    else if (p->schedule == PGG_SCHEDULE_TILED)
-        s->kernel = kKernelTiled;
-    else if (p->kernel != PGG_KERNEL_AUTO)
-        s->kernel = (int)p->kernel;
-    else if (p->L < 64)
-        s->kernel = p->layout == PGG_LAYOUT_INT8 ? PGG_KERNEL_COLOUR : PGG_KERNEL_ROWBAND_COMPACT;
-    else if (p->L <= kResidentAutoMaxL && pgg::resident_fits((int)p->L) && p->group == 0)
-        s->kernel = PGG_KERNEL_RESIDENT;
-    else
-        s->kernel = pair_fits(p, s->device) ? PGG_KERNEL_SEGMENT_PAIR : PGG_KERNEL_SEGMENT;
+    s->kernel = choose_kernel(p, s->device);
     s->wpg = p->group ? (int)p->group : pgg::kWavesPerGroup;
     if (s->kernel == PGG_KERNEL_SEGMENT) s->segw = p->tile ? (int)p->tile : choose_segw(p->L, s->wpg);
     if (s->kernel == PGG_KERNEL_SEGMENT_PAIR) {

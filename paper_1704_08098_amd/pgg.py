@@ -33,7 +33,7 @@ KERNELS = {"auto": KERNEL_AUTO, "colour": KERNEL_COLOUR, "rowband": KERNEL_ROWBA
            "resident": KERNEL_RESIDENT}
 
 # Every symbol include/pgg.h declares (checked by the CPU test suite).
-EXPORTS = ("pgg_device_bytes", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
+EXPORTS = ("pgg_device_bytes", "pgg_plan", "pgg_init", "pgg_sweep", "pgg_density", "pgg_coop_count",
            "pgg_sweep_index", "pgg_read_lattice", "pgg_write_lattice", "pgg_threshold_table", "pgg_fermi_table",
            "pgg_pd_table",
            "pgg_set_kernel_timing", "pgg_kernel_timing", "pgg_kernel_span", "pgg_set_strip_wait", "pgg_destroy",
@@ -98,6 +98,7 @@ def load():
     vp, u8p, u32p, u64p = ctypes.c_void_p, P(ctypes.c_uint8), P(ctypes.c_uint32), P(ctypes.c_uint64)
     sig = {
         "pgg_device_bytes": (ctypes.c_size_t, [P(PggParams)]),
+        "pgg_plan": (ctypes.c_int, [P(PggParams), P(ctypes.c_uint32), P(ctypes.c_uint32)]),
         "pgg_init": (ctypes.c_int, [P(PggParams), vp, ctypes.c_size_t, vp, P(vp)]),
         "pgg_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, u64p]),
         "pgg_density": (ctypes.c_int, [vp, P(ctypes.c_double)]),
@@ -171,6 +172,17 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return stream
     return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def pgg_plan(params: PggParams):
+    """The (kernel name, tile) pgg_init would take for these parameters on
+    the current device: AUTO resolved, and the work split it runs (segment
+    width, rows per band, waves; 0 where there is none).  The tiled schedule
+    and the pairwise game report "auto"."""
+    k, t = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().pgg_plan(ctypes.byref(params), ctypes.byref(k), ctypes.byref(t)))
+    names = {v: n for n, v in KERNELS.items()}
+    return names.get(k.value, str(k.value)), int(t.value)
 
 
 def pgg_init(params: PggParams, dev_buf=None, stream=None):

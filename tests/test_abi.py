@@ -156,3 +156,12 @@ def test_ensemble_autotune_rejects_bad_arguments(pgg):
         assert e.value.status == pgg.PGG_E_INVAL
     lib = pgg.load()
     assert lib.pgg_ensemble_autotune(None, 1, 4, None, None, None, None) == pgg.PGG_E_INVAL
+
+
+def test_plan_validates_before_touching_the_device(pgg):
+    lib = pgg.load()
+    k, t = ctypes.c_uint32(), ctypes.c_uint32()
+    p = pgg.make_params(L=102, r=3.8)  # L not a multiple of 4
+    assert lib.pgg_plan(ctypes.byref(p), ctypes.byref(k), ctypes.byref(t)) == pgg.PGG_E_INVAL
+    p = pgg.make_params(L=128, r=3.8)
+    assert lib.pgg_plan(ctypes.byref(p), None, ctypes.byref(t)) == pgg.PGG_E_INVAL

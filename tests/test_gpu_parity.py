@@ -663,3 +663,17 @@ def test_tiled_maximum_size_count_is_a_recount(pgg):
     pop = int(np.bitwise_count(buf.cpu().numpy()).sum(dtype=np.uint64))
     assert pop == int(c[-1])
     assert not torch.equal(before, buf) and int(c[-1]) != nc0
+
+
+def test_plan_reports_what_init_runs(pgg):
+    """pgg_plan resolves AUTO and the work split as pgg_init does."""
+    mk = pgg.make_params
+    assert pgg.pgg_plan(mk(4096, 3.7443, kernel="segment_pair")) == ("segment_pair", 2048)
+    assert pgg.pgg_plan(mk(4096, 3.7443)) == ("segment_pair", 2048)
+    assert pgg.pgg_plan(mk(4096, 3.7443, kernel="segment_pair", tile=1024)) == ("segment_pair", 1024)
+    assert pgg.pgg_plan(mk(128, 3.8)) == ("resident", 8)
+    assert pgg.pgg_plan(mk(96, 3.8)) == ("resident", 4)
+    assert pgg.pgg_plan(mk(100, 3.8)) == ("segment", 100)  # one periodic row per wave
+    assert pgg.pgg_plan(mk(2048, 3.8)) == ("segment", 1024)
+    assert pgg.pgg_plan(mk(256, 3.8, schedule="tiled")) == ("auto", 0)
+    assert pgg.pgg_plan(mk(256, 1.05, game="pd")) == ("auto", 0)
