@@ -60,7 +60,10 @@ __device__ __forceinline__ int tiled_domain(uint32_t* __restrict__ lat, int L, i
             int gi = 4 * I - 3 + o;  // in [-3, L + 6)
             gi += (gi < 0) ? L : 0;
             gi -= (gi >= L) ? L : 0;
-            w[o * kTiledThreads] = seg::global_window(lat + (size_t)gi * stride, L, nw, 4 * J - 3) & 0x3FFu;
+            const uint32_t* row = lat + (size_t)gi * stride;
+            const uint32_t bits = L >= 32 ? seg::global_window_wide(row, L, nw, 4 * J - 3)
+                                          : seg::global_window(row, L, nw, 4 * J - 3);
+            w[o * kTiledThreads] = bits & 0x3FFu;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) orig[q] = (w[(3 + q) * kTiledThreads] >> 3) & 0xFu;
