@@ -586,7 +586,10 @@ def main():
                    "resident": "k_resident"}[args.kernel]
     # the work split the sweep actually ran (the library's choice when
     # --tile is 0): the committed counter summaries are matched on it
-    _, split = pgg.pgg_plan(pgg.make_params(L, r, 0.5, 0.5, seed, layout, args.kernel, args.tile, args.group))
+    if args.kernel == "tiled":
+        split = 0  # the double tiling has no work split to choose
+    else:
+        _, split = pgg.pgg_plan(pgg.make_params(L, r, 0.5, 0.5, seed, layout, args.kernel, args.tile, args.group))
     traffic = measured_traffic(args.kernel, L, split, args.group)
     roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
