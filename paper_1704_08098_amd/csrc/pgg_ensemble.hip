@@ -183,7 +183,7 @@ pgg_status validate_reps(const pgg_params* reps, uint32_t n_reps, const uint32_t
         if (p.schedule != PGG_SCHEDULE_COLOUR16 && p.schedule != PGG_SCHEDULE_TILED) { eerr("replica %u: unknown schedule", k); return PGG_E_INVAL; }
         if (p.schedule != reps[0].schedule) { eerr("replica %u: every replica of an ensemble runs the same schedule", k); return PGG_E_INVAL; }
         if (p.schedule == PGG_SCHEDULE_TILED && (p.L % 8 != 0 || (tiles && tiles[k] != 0))) {
-            eerr("replica %u: the tiled schedule needs L % 8 == 0 and tile 0", k);
+            eerr("replica %u: the tiled schedule needs L %% 8 == 0 and tile 0", k);
             return PGG_E_INVAL;
         }
         const uint32_t w = tiles ? tiles[k] : 0;

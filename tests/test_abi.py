@@ -146,6 +146,7 @@ def test_tiled_ensemble_rules(pgg):
     with pytest.raises(pgg.PggError) as e:
         pgg.Ensemble([dict(L=128, r=3.8, seed=1, schedule="tiled")], tiles=[64])
     assert e.value.status == pgg.PGG_E_INVAL
+    assert "the tiled schedule needs L % 8 == 0 and tile 0" in str(e.value)
 
 
 def test_ensemble_autotune_rejects_bad_arguments(pgg):
