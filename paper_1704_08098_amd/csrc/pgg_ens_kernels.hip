@@ -136,17 +136,44 @@ k_ens_pair(const EnsRep* __restrict__ reps, int a, int q, unsigned long long* __
     const uint32_t t = rp.t0 + (uint32_t)q;
     seg_load_table(sT, rp.T);
     if (on) {
+        // Wave wid stages window rows wid, wid + NW, ..; lane l words l and
+        // l + 64 of each (128 words per pass).  Every load of a pass is
+        // issued before the first LDS store, so a wave waits for one round
+        // trip to L2 per pass, not one per word.
+        constexpr int NR = (B + 12 + NW - 1) / NW;  // window rows per wave
         const int w0 = c0 >> 5;  // segments start on word boundaries (L % 32 == 0)
-        for (int k = threadIdx.x; k < (B + 12) * WB; k += blockDim.x) {
-            const int o = k / WB, w = k - o * WB;
-            int gi = R0 - 6 + o;  // in [-6, L + B + 6)
-            gi += (gi < 0) ? L : 0;
-            gi -= (gi >= L) ? L : 0;
-            int widx = w0 + w;  // in [-2, nw + 2)
-            widx += (widx < 0) ? nw : 0;
-            widx -= (widx >= nw) ? nw : 0;
-            const uint32_t* src = ((gi & 3) < a) ? next : cur;
-            wwin[k] = src[(size_t)gi * stride + widx];
+        for (int wb = 0; wb < WB; wb += 128) {
+            int widx[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int x = w0 + wb + 64 * u + lane;  // in [-2, nw + 2) where the word is staged
+                x += (x < 0) ? nw : 0;
+                x -= (x >= nw) ? nw : 0;
+                widx[u] = x;
+            }
+            uint32_t v[2][NR];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int o = wid + NW * j;
+                int gi = R0 - 6 + o;  // in [-6, L + B + 6)
+                gi += (gi < 0) ? L : 0;
+                gi -= (gi >= L) ? L : 0;
+                const uint32_t* src = (((gi & 3) < a) ? next : cur) + (size_t)gi * stride;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int w = wb + 64 * u + lane;
+                    v[u][j] = (o < B + 12 && w < WB) ? src[widx[u]] : 0u;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int o = wid + NW * j;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int w = wb + 64 * u + lane;
+                    if (o < B + 12 && w < WB) wwin[o * WB + w] = v[u][j];
+                }
+            }
         }
     }
     __syncthreads();

@@ -262,28 +262,36 @@ __device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int
         const int wlo = lo >> 5, whi = (hi + 31) >> 5;
         // 1. candidates per word (the class-b bits), 2. compacted list: each
         // lane's offset is the exclusive prefix sum of the candidate counts
-        // (0..8) of the lanes below it, taken bit-sliced from four ballots.
+        // of the lanes below it, taken bit-sliced from ballots.
         // positions [lo, hi): only the first and the last word are partial
         const uint32_t m_first = 0xFFFFFFFFu << (lo & 31);
         const uint32_t m_last = (hi & 31) ? (1u << (hi & 31)) - 1u : 0xFFFFFFFFu;
-        int total = 0;  // wave-uniform
-        for (int wbase = wlo; wbase < whi; wbase += 64) {
-            const int w = wbase + lane;
-            uint32_t act = 0;
-            if (w < whi) {
-                const uint32_t X = r0[w];
-                const uint32_t E = funnel(r0[w + 1], X, 1);
-                const uint32_t Wn = funnel(X, r0[w - 1], 31);
-                act = ((X ^ E) | (X ^ Wn) | (X ^ r0[w - WB]) | (X ^ r0[w + WB])) & (0x11111111u << b);
-                if (w == wlo) act &= m_first;
-                if (w == whi - 1) act &= m_last;
-                // draws of owned sites (margin sites are recomputed copies)
-                if (count_drawn && owned_row) {
-                    const int own_lo = max(64 - 32 * w, 0), own_hi = min(64 + (e - s) - 32 * w, 32);
-                    if (own_hi > own_lo) my_drawn += __popc(act & bit_range(own_lo, own_hi));
-                }
+        auto word_act = [&](int w) {
+            const uint32_t X = r0[w];
+            const uint32_t E = funnel(r0[w + 1], X, 1);
+            const uint32_t Wn = funnel(X, r0[w - 1], 31);
+            uint32_t act = ((X ^ E) | (X ^ Wn) | (X ^ r0[w - WB]) | (X ^ r0[w + WB])) & (0x11111111u << b);
+            if (w == wlo) act &= m_first;
+            if (w == whi - 1) act &= m_last;
+            // draws of owned sites (margin sites are recomputed copies)
+            if (count_drawn && owned_row) {
+                const int own_lo = max(64 - 32 * w, 0), own_hi = min(64 + (e - s) - 32 * w, 32);
+                if (own_hi > own_lo) my_drawn += __popc(act & bit_range(own_lo, own_hi));
             }
-            const int cnt = __popc(act);
+            return act;
+        };
+        // Up to 128 words per pass, lane l taking words wbase + l and wbase +
+        // 64 + l: a row a little over 64 words (2048 owned columns and their
+        // margins) takes one pass, its last few words loaded and listed
+        // beside the first 64 instead of in a pass of their own.
+        int total = 0;  // wave-uniform
+        for (int wbase = wlo; wbase < whi; wbase += 128) {
+            const int w1 = wbase + lane, w2 = w1 + 64;
+            const bool two = wbase + 64 < whi;  // wave-uniform
+            uint32_t act1 = 0, act2 = 0;
+            if (w1 < whi) act1 = word_act(w1);
+            if (two && w2 < whi) act2 = word_act(w2);
+            const int cnt = __popc(act1) + __popc(act2);  // 0..16
             int pos = total;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -291,10 +299,20 @@ __device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int
                 pos += lanes_below(m) << k;
                 total += __popcll(m) << k;
             }
-            while (act) {
-                const int bit = __ffs(act) - 1;
-                act &= act - 1u;
-                list[pos++] = (uint32_t)(32 * w + bit);
+            if (two) {
+                const unsigned long long m = __ballot((cnt >> 4) & 1);
+                pos += lanes_below(m) << 4;
+                total += __popcll(m) << 4;
+            }
+            while (act1) {
+                const int bit = __ffs(act1) - 1;
+                act1 &= act1 - 1u;
+                list[pos++] = (uint32_t)(32 * w1 + bit);
+            }
+            while (act2) {
+                const int bit = __ffs(act2) - 1;
+                act2 &= act2 - 1u;
+                list[pos++] = (uint32_t)(32 * w2 + bit);
             }
         }
         __builtin_amdgcn_wave_barrier();
