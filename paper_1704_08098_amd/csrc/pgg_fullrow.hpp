@@ -44,16 +44,32 @@ __device__ __forceinline__ void fullrow_fill(const uint32_t* __restrict__ cur, c
     const int lane = threadIdx.x & 63;
     const int nw = L >> 5, ldw = nw + 2;
     const int n = (4 * R + 3) * ldw;
-    for (int q = lane; q < n; q += 64) {
-        const int o = q / ldw;
-        int w = q - o * ldw - 1;  // -1 .. nw
-        w += (w < 0) ? nw : 0;
-        w -= (w >= nw) ? nw : 0;
-        int gi = i0 - 3 + o;  // in [-3, 2L)
-        gi += (gi < 0) ? L : 0;
-        gi -= (gi >= L) ? L : 0;
-        const uint32_t* src = ((gi & 3) < a) ? next : cur;
-        win[q] = src[(size_t)gi * stride + w];
+    // four loads in flight per lane before their LDS stores: one round trip
+    // to L2 per 256 words of the window, not one per 64
+    constexpr int U = 4;
+    for (int qb = 0; qb < n; qb += 64 * U) {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = qb + 64 * u + lane;
+            v[u] = 0u;
+            if (q < n) {
+                const int o = q / ldw;
+                int w = q - o * ldw - 1;  // -1 .. nw
+                w += (w < 0) ? nw : 0;
+                w -= (w >= nw) ? nw : 0;
+                int gi = i0 - 3 + o;  // in [-3, 2L)
+                gi += (gi < 0) ? L : 0;
+                gi -= (gi >= L) ? L : 0;
+                const uint32_t* src = ((gi & 3) < a) ? next : cur;
+                v[u] = src[(size_t)gi * stride + w];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = qb + 64 * u + lane;
+            if (q < n) win[q] = v[u];
+        }
     }
 }
 
