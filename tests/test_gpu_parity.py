@@ -378,6 +378,22 @@ def test_segment_widths(pgg, oracle_lib, L, segw):
         assert np.array_equal(sim.read_lattice(), ref)
 
 
+@pytest.mark.parametrize("kernel,L,segw", [("segment", 4100, 4100), ("segment", 4096, 4064),
+                                           ("segment_pair", 4096, 4032)])
+def test_rows_wider_than_one_candidate_pass(pgg, oracle_lib, kernel, L, segw):
+    """Rows of more than 128 window words (a lane takes two words per pass,
+    so these need two passes, the second for the last word or two): a whole
+    periodic row of L = 4100, a 4064-column segment with a 32-column last one,
+    and 4032-column segments of the paired kernel; two sweeps against the
+    oracle."""
+    r, seed, n = 3.9, 50 + L + segw, 2
+    ref, nc0, counts = oracle_lib.run(L, r, 0.5, 0.5, seed, n)
+    say(kernel, L, segw)
+    with pgg.Sim(L, r, 0.5, 0.5, seed, "bits", kernel, tile=segw) as sim:
+        assert np.array_equal(sim.sweep(n), counts)
+        assert np.array_equal(sim.read_lattice(), ref)
+
+
 @pytest.mark.parametrize("group", [2, 4, 8])
 def test_segment_workgroup_shapes(pgg, oracle_lib, group):
     """2, 4 or 8 segment waves per workgroup (the last workgroup padded with
