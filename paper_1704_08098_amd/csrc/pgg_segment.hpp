@@ -285,34 +285,35 @@ __device__ __forceinline__ void segment_run_row(uint32_t* __restrict__ next, int
         // margins) takes one pass, its last few words loaded and listed
         // beside the first 64 instead of in a pass of their own.
         int total = 0;  // wave-uniform
-        for (int wbase = wlo; wbase < whi; wbase += 128) {
-            const int w1 = wbase + lane, w2 = w1 + 64;
-            const bool two = wbase + 64 < whi;  // wave-uniform
-            uint32_t act1 = 0, act2 = 0;
-            if (w1 < whi) act1 = word_act(w1);
-            if (two && w2 < whi) act2 = word_act(w2);
-            const int cnt = __popc(act1) + __popc(act2);  // 0..16
+        // this lane's offset: the counts (0..2^nbits - 1) of the lanes below
+        auto offset = [&](int cnt, int nbits) {
             int pos = total;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < nbits; ++k) {
                 const unsigned long long m = __ballot((cnt >> k) & 1);
                 pos += lanes_below(m) << k;
                 total += __popcll(m) << k;
             }
-            if (two) {
-                const unsigned long long m = __ballot((cnt >> 4) & 1);
-                pos += lanes_below(m) << 4;
-                total += __popcll(m) << 4;
+            return pos;
+        };
+        auto emit = [&](uint32_t act, int w, int& pos) {
+            while (act) {
+                const int bit = __ffs(act) - 1;
+                act &= act - 1u;
+                list[pos++] = (uint32_t)(32 * w + bit);
             }
-            while (act1) {
-                const int bit = __ffs(act1) - 1;
-                act1 &= act1 - 1u;
-                list[pos++] = (uint32_t)(32 * w1 + bit);
-            }
-            while (act2) {
-                const int bit = __ffs(act2) - 1;
-                act2 &= act2 - 1u;
-                list[pos++] = (uint32_t)(32 * w2 + bit);
+        };
+        for (int wbase = wlo; wbase < whi; wbase += 128) {
+            const int w1 = wbase + lane, w2 = w1 + 64;
+            if (wbase + 64 < whi) {  // wave-uniform: two words for some lanes
+                const uint32_t act1 = word_act(w1);  // w1 < wbase + 64 < whi
+                const uint32_t act2 = w2 < whi ? word_act(w2) : 0u;
+                int pos = offset(__popc(act1) + __popc(act2), 5);
+                emit(act1, w1, pos);
+                emit(act2, w2, pos);
+            } else {
+                const uint32_t act1 = w1 < whi ? word_act(w1) : 0u;
+                int pos = offset(__popc(act1), 4);
+                emit(act1, w1, pos);
             }
         }
         __builtin_amdgcn_wave_barrier();
