@@ -49,7 +49,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.3 T full-rate lane-ops/s
 # summaries (rocprofv3 --pmc), like the traffic: per dispatch, the VALU
 # instructions issued and the lane-cycles they kept busy; the summary records
 # the hash of the kernel's sources, and a changed kernel reads as null.
-COUNTER_PROFILES = {"segment_pair": os.path.join(ROOT, "profiles", "k_ens_pair_L4096_sq_counters.txt")}
+COUNTER_PROFILES = {"segment": os.path.join(ROOT, "profiles", "k_ens_segment_L4096_sq_counters.txt"),
+                    "segment_pair": os.path.join(ROOT, "profiles", "k_ens_pair_L4096_sq_counters.txt")}
 N_SIMDS = 256 * 4
 GPU_CLOCK_HZ = 2.4e9
 TRAFFIC_PROFILES = {"segment": os.path.join(ROOT, "profiles", "k_ens_segment_L4096_traffic.txt"),
